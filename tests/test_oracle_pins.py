@@ -1,0 +1,345 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix,
+independently of the oracle's own formulas (CPU only)."""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _small(M=4, N=16, level=1, seed=0, geo=None):
+    rng = np.random.default_rng(seed)
+    mics = synth.geometry(geo) if geo else synth.random_array(M, 0.08, rng)
+    grid = synth.icosphere(level)
+    return mics, grid, rng
+
+
+# ------------------------------------------------------------------ P4
+def _golden_gains():
+    rows = {}
+    with open(os.path.join(HERE, "golden", "table1_gains.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                g, v = line.split()
+                rows[g] = int(v)
+    return rows
+
+
+@pytest.mark.parametrize("geo", ["1d", "2d", "3d"])
+def test_p4_paper_gains(geo):
+    """Section 4: delta = 1e-5 gives Q/K = 320 / 53 / 36 with the Table 1
+    parameters and the Table 2 arrays."""
+    t1 = synth.TABLE1
+    mics = synth.geometry(geo)
+    grid = synth.icosphere(4)
+    assert grid.shape[0] == t1["Q"]
+    tau = oracle.tdoa_farfield(mics, grid, t1["fs"], t1["c"])
+    W = oracle.steering_matrix(tau, t1["N"])
+    _, s, _, Kp, K = oracle.truncated_svd(W, 1e-5)
+    assert int(t1["Q"] / Kp) == _golden_gains()[geo]
+    # P1 on the same matrix: every entry of eq. (4) has unit modulus.
+    assert abs(np.sum(s ** 2) / W.size - 1.0) < 1e-12
+
+
+# ------------------------------------------------------------------ P1, P3
+def test_p1_p3_energy_and_residual():
+    mics, grid, _ = _small(M=5, N=32, level=2)
+    tau = oracle.tdoa_farfield(mics, grid, 16000.0, 343.0)
+    W = oracle.steering_matrix(tau, 32)
+    Q, L = W.shape
+    assert np.allclose(np.abs(W), 1.0, atol=1e-15)
+    for delta in (1e-1, 1e-3, 1e-5):
+        U, s, Vh, Kp, K = oracle.truncated_svd(W, delta)
+        E = Q * L
+        assert abs(np.sum(s ** 2) - E) < 1e-9 * E
+        # explicit reconstruction residual, eq. (11)
+        WK = (U * s[:K]) @ Vh
+        res = np.sum(np.abs(W - WK) ** 2) / E
+        assert res <= delta * (1 + 1e-9)
+        assert abs(res - np.sum(s[K:] ** 2) / E) < 1e-10
+        # K_paper is the smallest rank that satisfies eq. (11)
+        if Kp > 1:
+            assert np.sum(s[:Kp - 1] ** 2) < (1 - delta) * E
+        # columns of U and V are orthonormal
+        assert np.allclose(U.conj().T @ U, np.eye(K), atol=1e-10)
+        assert np.allclose(Vh @ Vh.conj().T, np.eye(K), atol=1e-10)
+
+
+def test_rank_rule_cluster_extension():
+    s = np.array([5.0, 3.0, 2.0, 2.0, 2.0, 1.0, 0.1])
+    E = np.sum(s ** 2)
+    # cut at K=3 falls inside the cluster {2,2,2}: extended to 5
+    delta = 1 - np.sum(s[:3] ** 2) / E
+    Kp, K = oracle.choose_rank(s, delta * 1.000001)
+    assert Kp == 3 and K == 5
+    Kp, K = oracle.choose_rank(s, 0.0)
+    assert Kp == K == 7
+
+
+# ------------------------------------------------------------------ P2
+def test_p2_full_rank_equals_srp():
+    mics, grid, rng = _small(M=4, N=16, level=2, seed=3)
+    tau = oracle.tdoa_farfield(mics, grid, 16000.0, 343.0)
+    W = oracle.steering_matrix(tau, 16)
+    U, s, Vh, Kp, K = oracle.truncated_svd(W, 0.0)
+    X = rng.standard_normal((6, 4, 9)) + 1j * rng.standard_normal((6, 4, 9))
+    x = oracle.phat_vector(X)
+    y_srp = oracle.srp_phat_power(W, x)
+    y_svd = oracle.svd_phat_power(U, s, Vh, x)
+    assert np.max(np.abs(y_srp - y_svd)) <= 1e-10 * W.shape[1]
+    # stacked real form gives the same numbers
+    Ast, Ust = oracle.stacked_projection(U, s, Vh)
+    xs = np.concatenate([x.real, x.imag], axis=1)
+    assert np.allclose((xs @ Ast.T) @ Ust.T, y_svd, atol=1e-9)
+
+
+# ------------------------------------------------------------------ P10 brute force
+def test_p10_brute_force_eq5():
+    """Eq. (5) written as three explicit loops with eqs. (2)-(4), against the
+    matrix form of eq. (9) and the argmax of eq. (6)."""
+    M, N, fs, c = 3, 8, 16000.0, 343.0
+    mics, grid, rng = _small(M=M, N=N, level=1, seed=7)
+    X = rng.standard_normal((2, M, N // 2 + 1)) + 1j * rng.standard_normal((2, M, N // 2 + 1))
+    W = oracle.steering_matrix(oracle.tdoa_farfield(mics, grid, fs, c), N)
+    y = oracle.srp_phat_power(W, oracle.phat_vector(X))
+    for f in range(2):
+        ybf = []
+        for s in grid:
+            sh = s / math.sqrt(sum(v * v for v in s))
+            acc = 0j
+            for i in range(M):
+                for j in range(i + 1, M):
+                    tau = fs / c * sum((mics[j][d] - mics[i][d]) * sh[d] for d in range(3))
+                    for k in range(N // 2 + 1):
+                        Xi, Xj = X[f, i, k], X[f, j, k]
+                        xij = Xi * Xj.conjugate() / (abs(Xi) * abs(Xj))
+                        acc += complex(math.cos(2 * math.pi * k * tau / N),
+                                       math.sin(2 * math.pi * k * tau / N)) * xij
+            ybf.append(acc.real)
+        assert np.allclose(y[f], ybf, atol=1e-12)
+        best = max(range(len(ybf)), key=lambda q: (ybf[q], -q))
+        assert int(np.argmax(y[f])) == best
+
+
+# ------------------------------------------------------------------ P6, P7
+@pytest.mark.parametrize("geo", ["1d", "2d", "3d"])
+def test_p7_dirichlet_closed_form(geo):
+    """Noiseless off-grid plane wave: eq. (9) equals the Dirichlet-kernel sum."""
+    N, fs, c = 512, 16000.0, 343.0
+    mics = synth.geometry(geo)
+    grid = synth.icosphere(2)
+    rng = np.random.default_rng(11)
+    u = synth.random_direction(rng)
+    X = synth.plane_wave_fd(mics, u, 3, N, fs, c, rng)
+    x = oracle.phat_vector(X)
+    tau = oracle.tdoa_farfield(mics, grid, fs, c)
+    y = oracle.srp_phat_power(oracle.steering_matrix(tau, N), x)
+    # pair delays of the source direction, from the microphone advances
+    a = fs * (mics @ u) / c
+    tsrc = np.array([a[j] - a[i] for i, j in oracle.mic_pairs(7)])
+    yc = oracle.dirichlet_power(tau, tsrc, N)
+    L = 21 * (N // 2 + 1)
+    for f in range(3):
+        assert np.max(np.abs(y[f] - yc)) <= 1e-9 * L
+
+
+@pytest.mark.parametrize("geo", ["1d", "2d", "3d"])
+def test_p6_on_grid_plane_wave(geo):
+    """A noiseless plane wave from grid direction q0 gives Y_q0 = L, the
+    maximum, for SRP-PHAT and for the truncated SVD-PHAT at delta = 1e-5."""
+    N, fs, c = 512, 16000.0, 343.0
+    mics = synth.geometry(geo)
+    grid = synth.icosphere(3)
+    plan = oracle.make_plan(mics, grid, fs, c, N, 1e-5)
+    rng = np.random.default_rng(5)
+    L = plan.W.shape[1]
+    for q0 in rng.choice(grid.shape[0], 12, replace=False):
+        X = synth.plane_wave_fd(mics, grid[q0], 1, N, fs, c, rng)
+        x = oracle.phat_vector(X)
+        y = oracle.srp_phat_power(plan.W, x)[0]
+        assert abs(y[q0] - L) < 1e-8 * L
+        qbar, _, _ = oracle.argmax_with_margin(y, plan.rep)
+        assert qbar[0] == plan.rep[q0]
+        ysvd = oracle.svd_phat_power(plan.U, plan.s, plan.Vh, x)
+        qs, _, _ = oracle.argmax_with_margin(ysvd, plan.rep)
+        assert qs[0] == plan.rep[q0]
+
+
+def test_p6_time_domain_generator():
+    """The time-domain generator (fractional advance + sine-window STFT)
+    agrees with the sign conventions: a noiseless wave from a grid direction
+    is localised at that direction's class."""
+    N, fs, c = 512, 16000.0, 343.0
+    mics = synth.geometry("3d")
+    grid = synth.icosphere(3)
+    tau = oracle.tdoa_farfield(mics, grid, fs, c)
+    W = oracle.steering_matrix(tau, N)
+    rep = oracle.direction_classes(tau)
+    rng = np.random.default_rng(2)
+    for q0 in rng.choice(grid.shape[0], 6, replace=False):
+        X = synth.plane_wave_td(mics, [grid[q0]], 4, N, 256, fs, c, rng)
+        y = oracle.srp_phat_power(W, oracle.phat_vector(X))
+        qbar, _, _ = oracle.argmax_with_margin(y, rep)
+        assert np.all(qbar == rep[q0])
+
+
+# ------------------------------------------------------------------ P8
+def test_p8_row_bound():
+    N, fs, c = 512, 16000.0, 343.0
+    mics = synth.geometry("2d")
+    grid = synth.icosphere(2)
+    plan = oracle.make_plan(mics, grid, fs, c, N, 1e-3)
+    rng = np.random.default_rng(8)
+    X = synth.plane_wave_fd(mics, synth.random_direction(rng), 8, N, fs, c, rng, snr_db=5)
+    x = oracle.phat_vector(X)
+    ys = oracle.srp_phat_power(plan.W, x)
+    yv = oracle.svd_phat_power(plan.U, plan.s, plan.Vh, x)
+    D = plan.U * plan.s[:plan.K]
+    r2 = plan.W.shape[1] - np.sum(np.abs(D) ** 2, axis=1)          # ||r_q||^2
+    WK = D @ plan.Vh
+    assert np.allclose(r2, np.sum(np.abs(plan.W - WK) ** 2, axis=1), atol=1e-8)
+    bound = np.sqrt(np.maximum(r2, 0))[None, :] * np.linalg.norm(x, axis=1)[:, None]
+    assert np.all(np.abs(ys - yv) <= bound + 1e-9)
+
+
+# ------------------------------------------------------------------ P9
+def test_p9_metamorphic():
+    N, fs, c = 32, 16000.0, 343.0
+    mics, grid, rng = _small(M=4, N=N, level=2, seed=9)
+    B = N // 2 + 1
+    X = rng.standard_normal((3, 4, B)) + 1j * rng.standard_normal((3, 4, B))
+    x = oracle.phat_vector(X)
+    # per-mic positive gains and a common per-bin phase leave x unchanged
+    a = rng.uniform(0.1, 10, size=(1, 4, B))
+    ph = np.exp(1j * rng.uniform(0, 2 * np.pi, size=(1, 1, B)))
+    assert np.allclose(oracle.phat_vector(X * a * ph), x, atol=1e-12)
+    tau = oracle.tdoa_farfield(mics, grid, fs, c)
+    y = oracle.srp_phat_power(oracle.steering_matrix(tau, N), x)
+    # relabelling the microphones leaves every power unchanged
+    perm = [2, 0, 3, 1]
+    tau2 = oracle.tdoa_farfield(mics[perm], grid, fs, c)
+    y2 = oracle.srp_phat_power(oracle.steering_matrix(tau2, N), oracle.phat_vector(X[:, perm]))
+    assert np.allclose(y, y2, atol=1e-10)
+    # permuting the grid permutes the powers
+    gp = rng.permutation(grid.shape[0])
+    tau3 = oracle.tdoa_farfield(mics, grid[gp], fs, c)
+    y3 = oracle.srp_phat_power(oracle.steering_matrix(tau3, N), x)
+    assert np.allclose(y3, y[:, gp], atol=1e-10)
+    # a silent bin of one microphone removes that bin's pairs
+    Xz = X.copy()
+    Xz[:, 1, 3] = 0
+    xz = oracle.phat_vector(Xz).reshape(3, 6, B)
+    for p, (i, j) in enumerate(oracle.mic_pairs(4)):
+        if 1 in (i, j):
+            assert np.all(xz[:, p, 3] == 0)
+
+
+# ------------------------------------------------------------------ classes
+def test_classes_follow_array_symmetry():
+    """A linear array along z only sees s_z; a planar array in z = 0 cannot
+    tell +z from -z.  The classes must be exactly those."""
+    grid = synth.icosphere(3)
+    fs, c = 16000.0, 343.0
+    r1 = oracle.direction_classes(oracle.tdoa_farfield(synth.geometry("1d"), grid, fs, c))
+    key = np.round(grid[:, 2], 9)
+    for q in range(grid.shape[0]):
+        assert r1[q] == np.flatnonzero(key == key[q])[0]
+    r2 = oracle.direction_classes(oracle.tdoa_farfield(synth.geometry("2d"), grid, fs, c))
+    kx, ky = np.round(grid[:, 0], 9), np.round(grid[:, 1], 9)
+    for q in range(grid.shape[0]):
+        assert r2[q] == np.flatnonzero((kx == kx[q]) & (ky == ky[q]))[0]
+    r3 = oracle.direction_classes(oracle.tdoa_farfield(synth.geometry("3d"), grid, fs, c))
+    assert np.all(r3 == np.arange(grid.shape[0]))
+
+
+def test_margin_between_classes():
+    y = np.array([[1.0, 3.0, 3.0, 2.0]])
+    rep = np.array([0, 1, 1, 3])
+    q, y1, m = oracle.argmax_with_margin(y, rep)
+    assert q[0] == 1 and y1[0] == 3.0 and abs(m[0] - 1 / 3) < 1e-15
+
+
+def test_exact_power_is_row_of_srp():
+    N = 64
+    mics, grid, rng = _small(M=4, N=N, level=1, seed=4)
+    tau = oracle.tdoa_farfield(mics, grid, 16000.0, 343.0)
+    W = oracle.steering_matrix(tau, N)
+    X = rng.standard_normal((2, 4, N // 2 + 1)) + 1j * rng.standard_normal((2, 4, N // 2 + 1))
+    x = oracle.phat_vector(X)
+    y = oracle.srp_phat_power(W, x)
+    for q in (0, 5, 41):
+        assert abs(oracle.exact_power(tau[q], N, x[1]) - y[1, q]) < 1e-10
+
+
+# ------------------------------------------------------------------ grid
+def test_icosphere_counts_and_nesting():
+    for lv in range(5):
+        g = synth.icosphere(lv)
+        assert g.shape == (synth.icosphere_count(lv), 3)
+        assert np.allclose(np.linalg.norm(g, axis=1), 1.0)
+    g3, g5 = synth.icosphere(3), synth.icosphere(5)
+    assert np.array_equal(g5[:642], g3)
+    # all points distinct
+    d = g3 @ g3.T - 2 * np.eye(642)
+    assert d.max() < 1 - 1e-6
+
+
+# ------------------------------------------------------------------ MLP (proposal)
+def _mlp(rng, i=6, h=5, o=4):
+    return [rng.standard_normal((h, i)) * 0.5, rng.standard_normal(h) * 0.1,
+            rng.standard_normal((h, h)) * 0.5, rng.standard_normal(h) * 0.1,
+            rng.standard_normal((o, h)) * 0.5, rng.standard_normal(o) * 0.1]
+
+
+def test_gelu_definition():
+    from scipy.stats import norm
+    x = np.linspace(-6, 6, 101)
+    assert np.allclose(oracle.gelu(x), x * norm.cdf(x), atol=1e-14)
+    h = 1e-6
+    fd = (oracle.gelu(x + h) - oracle.gelu(x - h)) / (2 * h)
+    assert np.allclose(oracle.gelu_grad(x), fd, atol=1e-8)
+
+
+def test_mlp_gradient_finite_differences():
+    rng = np.random.default_rng(1)
+    params = _mlp(rng)
+    f = rng.standard_normal((7, 6))
+    lab = rng.integers(0, 4, 7)
+    logits, cache = oracle.mlp_forward(params, f)
+    loss, dl, _ = oracle.softmax_xent(logits, lab)
+    grads = oracle.mlp_backward(params, cache, dl)
+    h = 1e-5
+    for P, G in zip(params, grads):
+        for idx in itertools.islice(np.ndindex(P.shape), 0, None, 3):
+            old = P[idx]
+            P[idx] = old + h
+            lp, _, _ = oracle.softmax_xent(oracle.mlp_forward(params, f)[0], lab)
+            P[idx] = old - h
+            lm, _, _ = oracle.softmax_xent(oracle.mlp_forward(params, f)[0], lab)
+            P[idx] = old
+            assert abs((lp - lm) / (2 * h) - G[idx]) < 1e-7
+
+
+def test_adam_first_step():
+    """First Adam step moves each parameter by lr * g / (|g| + eps')."""
+    g = np.array([0.3, -2.0, 1e-3])
+    p, m, v = oracle.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=0.01)
+    assert np.allclose(p, -0.01 * np.sign(g), rtol=1e-4)
+
+
+def test_coarse_cells_nesting():
+    fine = synth.icosphere(4)
+    coarse = synth.icosphere(2)
+    cell = oracle.coarse_cells(fine, coarse)
+    assert np.array_equal(cell[:coarse.shape[0]], np.arange(coarse.shape[0]))
+    # brute force nearest by angle
+    for q in range(0, fine.shape[0], 97):
+        ang = np.arccos(np.clip(coarse @ fine[q], -1, 1))
+        assert ang[cell[q]] <= ang.min() + 1e-9
