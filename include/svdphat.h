@@ -1,0 +1,174 @@
+/*
+ * svdphat.h -- C ABI of the MI355X (gfx950) SVD-PHAT sound-source localiser.
+ *
+ * Method: F. Grondin and J. Glass, "SVD-PHAT: A Fast Sound Source
+ * Localization Method" (arXiv 1811.11785).  Section 2 defines SRP-PHAT
+ * (far-field delays eq. (2), PHAT cross-spectra eq. (3), steering
+ * coefficients eq. (4), powers eq. (5)/(9), argmax eq. (6)); Section 3
+ * defines SVD-PHAT (eqs. (7)-(14)) and Algorithm 1 splits it into an offline
+ * plan and an online per-frame search.
+ *
+ * Conventions shared by every call
+ *   - Every function returns an int status: SVDPHAT_OK (0) or a negative
+ *     SVDPHAT_E_* code.  No C++ exception crosses this boundary.  The
+ *     message of the last failure on the calling thread is returned by
+ *     svdphat_last_error().
+ *   - "host" pointers are read (or written) before the call returns.
+ *     "device" pointers are HIP device memory owned by the caller; the call
+ *     enqueues work on the given HIP stream (a hipStream_t passed as void*,
+ *     NULL = the null stream) and returns without waiting.  Errors raised by
+ *     that work surface at the next call or at svdphat_sync().
+ *   - Directions are returned as 0-based indices into the caller's grid.
+ *     Directions whose delay rows are identical (within 1e-9 samples in every
+ *     pair) have identical rows of W and so identical powers; they form one
+ *     class, and the index returned is always the lowest index of the class.
+ *   - Inputs: STFT frames X are complex64 (interleaved re, im) laid out
+ *     [F][M][N/2+1]: frame-major, then microphone, then bin k = 0 .. N/2
+ *     (Section 2, bins k in [0, N/2]).
+ */
+#ifndef SVDPHAT_H
+#define SVDPHAT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define SVDPHAT_OK              0
+#define SVDPHAT_E_INVAL        -1  /* invalid argument (shape, range, NULL) */
+#define SVDPHAT_E_NOMEM        -2  /* device or host allocation failed */
+#define SVDPHAT_E_DEVICE       -3  /* a HIP / rocBLAS / rocSOLVER call failed */
+#define SVDPHAT_E_NUMERIC      -4  /* eigensolver failure or non-finite factors */
+#define SVDPHAT_E_NODEV        -5  /* no usable GPU */
+#define SVDPHAT_E_UNSUPPORTED  -6  /* request not supported by this plan */
+
+/* ---- plan flags ------------------------------------------------------ */
+#define SVDPHAT_KEEP_W    0x1u  /* also store W in FP32 for svdphat_srp_locate */
+#define SVDPHAT_NO_DEDUP  0x2u  /* score every direction, not one per class */
+
+/* ---- precision of the two projections in svdphat_locate --------------- */
+#define SVDPHAT_FP32  0   /* FP32 operands, FP32 accumulation */
+#define SVDPHAT_BF16  1   /* BF16 operands on MFMA, FP32 accumulation */
+#define SVDPHAT_FP16  2   /* FP16 operands on MFMA, FP32 accumulation */
+
+/* ---- mode bits of svdphat_locate ------------------------------------- */
+#define SVDPHAT_RESCORE  0x1u /* rescore in FP32 every direction whose
+                                 low-precision power is within the rounding
+                                 bound of the maximum (else only the tiles
+                                 holding the maximum are rescored) */
+#define SVDPHAT_HILO     0x2u /* recompute Z = S V^H X with a split hi/lo
+                                 (compensated) product for frames whose
+                                 rescored top-two margin is small */
+
+typedef struct svdphat_plan svdphat_plan;
+
+typedef struct svdphat_info {
+    int32_t M;          /* microphones */
+    int32_t P;          /* pairs, M(M-1)/2 */
+    int32_t B;          /* bins, N/2 + 1 */
+    int32_t L;          /* P * B, length of X in eq. (7) */
+    int32_t Q;          /* directions */
+    int32_t n_classes;  /* rows scored by the reduced search */
+    int32_t K;          /* rank used */
+    int32_t K_paper;    /* smallest K satisfying eq. (11) */
+    int32_t N;          /* frame size */
+    int32_t has_w;      /* 1 if the plan keeps W in FP32 */
+    double residual;    /* 1 - sum_{k<=K} s_k^2 / ||W||_F^2 */
+    double sigma1;      /* largest singular value */
+    double sigmaK;      /* K-th singular value */
+    double fro2;        /* ||W||_F^2 (= Q * L exactly in exact arithmetic) */
+    double u_rownorm_max; /* max_q ||U_q||_2 over the kept rank */
+    int64_t device_bytes;
+} svdphat_info;
+
+/*
+ * svdphat_plan_create -- Algorithm 1, offline steps 1-2 (Section 3).
+ *   mic_xyz_m  host, M x 3 doubles, microphone positions in metres.
+ *   grid_xyz   host, Q x 3 doubles, candidate directions s_q (any nonzero
+ *              length; each row is normalised as in eq. (2)).
+ *   fs, c      sample rate (Hz) and speed of sound (m/s), both > 0.
+ *   N          STFT frame size, even, >= 2.
+ *   delta      tolerated relative reconstruction error of eq. (11),
+ *              0 <= delta < 1; 0 keeps every singular value above
+ *              1e-6 times the largest (the full numerical rank).
+ *   flags      SVDPHAT_KEEP_W | SVDPHAT_NO_DEDUP.
+ *   out        receives the new plan (set to NULL on failure).
+ * Builds the far-field delays (eq. (2)), W (eqs. (4), (8)) in FP64 on the
+ * GPU, its truncated SVD (eq. (10)) through the Hermitian eigen-
+ * decomposition of the smaller Gram matrix, chooses K by eq. (11) (extended
+ * over a cluster of equal singular values at the cut), and packs the device
+ * operands.  Synchronous.  The plan owns all the device memory it creates.
+ * Errors: E_INVAL (M < 2, Q < 1, N odd or < 2, delta outside [0,1), a zero
+ * grid row, non-finite input), E_NODEV, E_NOMEM, E_DEVICE, E_NUMERIC.
+ */
+int svdphat_plan_create(const double* mic_xyz_m, int32_t M,
+                        const double* grid_xyz, int32_t Q,
+                        double fs, double c, int32_t N, double delta,
+                        uint32_t flags, svdphat_plan** out);
+
+/* svdphat_plan_info -- sizes and factorisation summary of a plan (host). */
+int svdphat_plan_info(const svdphat_plan* plan, svdphat_info* out);
+
+/*
+ * svdphat_plan_export -- copies the FP64 factors to host memory (a testing
+ * aid; any pointer may be NULL to skip it).
+ *   sigma      min(Q, L) singular values, descending (eq. (10)).
+ *   U          Q x K complex (interleaved), row-major.
+ *   V          L x K complex (interleaved), row-major, rows in the order of
+ *              eq. (7) (pair-major, bin-minor).
+ *   class_rep  Q ints: lowest index of each direction's class.
+ */
+int svdphat_plan_export(const svdphat_plan* plan, double* sigma, double* U,
+                        double* V, int32_t* class_rep);
+
+/*
+ * svdphat_locate -- Algorithm 1 online steps 1-4 (Section 3) with the
+ * exhaustive search of eq. (14) for F frames.
+ *   X          device, complex64 [F][M][N/2+1] STFT frames.
+ *   F          number of frames, >= 0 (0 is a no-op).
+ *   precision  SVDPHAT_FP32 | SVDPHAT_BF16 | SVDPHAT_FP16.
+ *   mode       SVDPHAT_RESCORE | SVDPHAT_HILO.
+ *   doa        device, int32 [F]: class-lowest index of argmax_q Y_q.
+ *   power      device, f32 [F]: Y at doa from the row of W (step 4, eq. (9)).
+ *   yhat       device, f32 [F] or NULL: the reduced power Re{D_q Z} at doa.
+ *   margin     device, f32 [F] or NULL: (y1 - y2) / |y1| between the best and
+ *              the second-best class of the FP32-rescored reduced powers
+ *              (a lower bound where the runner-up was not rescored).
+ *   y_opt      device, f32 [F][Q] or NULL: reduced powers of every direction
+ *              in the requested precision (debugging; slower).
+ *   stream     hipStream_t or NULL.
+ * Errors: E_INVAL (NULL plan/X/doa/power with F > 0, bad precision), E_NOMEM
+ * (workspace), E_DEVICE.
+ */
+int svdphat_locate(svdphat_plan* plan, const void* X, int64_t F,
+                   int32_t precision, uint32_t mode, int32_t* doa,
+                   float* power, float* yhat, float* margin, float* y_opt,
+                   void* stream);
+
+/*
+ * svdphat_srp_locate -- plain SRP-PHAT, eqs. (3), (9), (6), in FP32.
+ *   X, F, stream as above; doa [F] class-lowest argmax, power [F] its Y,
+ *   y_opt [F][Q] or NULL.  Needs a plan created with SVDPHAT_KEEP_W, else
+ *   E_UNSUPPORTED.
+ */
+int svdphat_srp_locate(svdphat_plan* plan, const void* X, int64_t F,
+                       int32_t* doa, float* power, float* y_opt, void* stream);
+
+/* svdphat_plan_destroy -- frees the plan and its device memory; NULL is a no-op. */
+void svdphat_plan_destroy(svdphat_plan* plan);
+
+/* svdphat_last_error -- message of the last failure on this thread ("" if none). */
+const char* svdphat_last_error(void);
+
+/* svdphat_sync -- waits for the stream and reports any pending device error. */
+int svdphat_sync(void* stream);
+
+/* svdphat_version -- ABI version (major * 10000 + minor * 100 + patch). */
+int svdphat_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SVDPHAT_H */

@@ -1,0 +1,209 @@
+"""Python binding of libsvdphat (SVD-PHAT on MI355X / gfx950).
+
+Argument marshalling only: every step of the localisation runs in the HIP
+library.  PyTorch provides device memory and streams; tensors are passed by
+``data_ptr()`` and the current HIP stream.  The functions mirror the C ABI
+declared in ``include/svdphat.h``; :class:`Plan` wraps them.
+
+The library is built in place by ``paper_1811_11785_amd.build.build()``;
+importing this module does not build it, and every call fails loudly if the
+shared library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsvdphat.so")
+
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_NUMERIC, E_NODEV, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+KEEP_W, NO_DEDUP = 0x1, 0x2
+FP32, BF16, FP16 = 0, 1, 2
+RESCORE, HILO = 0x1, 0x2
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16}
+
+
+class SvdphatError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"svdphat error {code}: {msg}")
+        self.code = code
+
+
+class Info(C.Structure):
+    _fields_ = [("M", C.c_int32), ("P", C.c_int32), ("B", C.c_int32), ("L", C.c_int32),
+                ("Q", C.c_int32), ("n_classes", C.c_int32), ("K", C.c_int32),
+                ("K_paper", C.c_int32), ("N", C.c_int32), ("has_w", C.c_int32),
+                ("residual", C.c_double), ("sigma1", C.c_double), ("sigmaK", C.c_double),
+                ("fro2", C.c_double), ("u_rownorm_max", C.c_double),
+                ("device_bytes", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+# exported symbols and their C signatures (restype, argtypes)
+SIGNATURES = {
+    "svdphat_version": (C.c_int, []),
+    "svdphat_last_error": (C.c_char_p, []),
+    "svdphat_plan_create": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_double,
+                                      C.c_double, C.c_int32, C.c_double, C.c_uint32,
+                                      C.POINTER(C.c_void_p)]),
+    "svdphat_plan_info": (C.c_int, [C.c_void_p, C.POINTER(Info)]),
+    "svdphat_plan_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "svdphat_locate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_uint32,
+                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p]),
+    "svdphat_srp_locate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]),
+    "svdphat_plan_destroy": (None, [C.c_void_p]),
+    "svdphat_sync": (C.c_int, [C.c_void_p]),
+}
+
+
+def lib():
+    """The loaded shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run paper_1811_11785_amd.build.build() first")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != OK:
+        raise SvdphatError(code, lib().svdphat_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------ C ABI mirror
+def svdphat_version() -> int:
+    return lib().svdphat_version()
+
+
+def svdphat_plan_create(mics, grid, fs, c, N, delta, flags=0):
+    mics = np.ascontiguousarray(mics, dtype=np.float64)
+    grid = np.ascontiguousarray(grid, dtype=np.float64)
+    out = C.c_void_p()
+    _check(lib().svdphat_plan_create(mics.ctypes.data, mics.shape[0], grid.ctypes.data,
+                                     grid.shape[0], float(fs), float(c), int(N), float(delta),
+                                     int(flags), C.byref(out)))
+    return out
+
+
+def svdphat_plan_info(plan) -> dict:
+    info = Info()
+    _check(lib().svdphat_plan_info(plan, C.byref(info)))
+    return info.as_dict()
+
+
+def svdphat_plan_export(plan):
+    info = svdphat_plan_info(plan)
+    Q, L, K = info["Q"], info["L"], info["K"]
+    sig = np.zeros(min(Q, L))
+    U = np.zeros((Q, K, 2))
+    V = np.zeros((L, K, 2))
+    rep = np.zeros(Q, dtype=np.int32)
+    _check(lib().svdphat_plan_export(plan, sig.ctypes.data, U.ctypes.data, V.ctypes.data,
+                                     rep.ctypes.data))
+    return sig, U[..., 0] + 1j * U[..., 1], V[..., 0] + 1j * V[..., 1], rep
+
+
+def svdphat_locate(plan, X, precision, mode, doa, power, yhat=None, margin=None, y_opt=None,
+                   stream=None):
+    _check(lib().svdphat_locate(plan, _ptr(X), X.shape[0], precision, mode, _ptr(doa), _ptr(power),
+                                _ptr(yhat), _ptr(margin), _ptr(y_opt), _stream(stream)))
+
+
+def svdphat_srp_locate(plan, X, doa, power, y_opt=None, stream=None):
+    _check(lib().svdphat_srp_locate(plan, _ptr(X), X.shape[0], _ptr(doa), _ptr(power), _ptr(y_opt),
+                                    _stream(stream)))
+
+
+def svdphat_plan_destroy(plan):
+    lib().svdphat_plan_destroy(plan)
+
+
+def svdphat_sync(stream=None):
+    _check(lib().svdphat_sync(_stream(stream)))
+
+
+# ------------------------------------------------------------ convenience
+class Plan:
+    """Offline plan (Algorithm 1, offline) and online search on device tensors."""
+
+    def __init__(self, mics, grid, fs=16000.0, c=343.0, N=512, delta=1e-5, keep_w=False,
+                 dedup=True):
+        flags = (KEEP_W if keep_w else 0) | (0 if dedup else NO_DEDUP)
+        self._h = svdphat_plan_create(mics, grid, fs, c, N, delta, flags)
+        self.info = svdphat_plan_info(self._h)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def locate(self, X, precision="fp32", rescore=True, hilo=False, want_y=False, stream=None):
+        """X: complex64 CUDA tensor [F, M, N/2+1].  Returns a dict of device
+        tensors doa (int32), power, yhat, margin (f32) and y ([F, Q]) if asked."""
+        import torch
+        assert X.is_cuda and X.dtype == torch.complex64 and X.is_contiguous()
+        F = X.shape[0]
+        dev = X.device
+        doa = torch.empty(F, dtype=torch.int32, device=dev)
+        power = torch.empty(F, dtype=torch.float32, device=dev)
+        yhat = torch.empty(F, dtype=torch.float32, device=dev)
+        margin = torch.empty(F, dtype=torch.float32, device=dev)
+        y = torch.empty((F, self.info["Q"]), dtype=torch.float32, device=dev) if want_y else None
+        mode = (RESCORE if rescore else 0) | (HILO if hilo else 0)
+        svdphat_locate(self._h, X, PRECISIONS[precision], mode, doa, power, yhat, margin, y, stream)
+        out = dict(doa=doa, power=power, yhat=yhat, margin=margin)
+        if want_y:
+            out["y"] = y
+        return out
+
+    def srp_locate(self, X, want_y=False, stream=None):
+        import torch
+        F = X.shape[0]
+        dev = X.device
+        doa = torch.empty(F, dtype=torch.int32, device=dev)
+        power = torch.empty(F, dtype=torch.float32, device=dev)
+        y = torch.empty((F, self.info["Q"]), dtype=torch.float32, device=dev) if want_y else None
+        svdphat_srp_locate(self._h, X, doa, power, y, stream)
+        out = dict(doa=doa, power=power)
+        if want_y:
+            out["y"] = y
+        return out
+
+    def export(self):
+        return svdphat_plan_export(self._h)
+
+    def close(self):
+        if self._h is not None:
+            svdphat_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,221 @@
+// C ABI of the SVD-PHAT library: argument checking, error model, workspace
+// pool, and dispatch to the plan builder and the kernel launchers.
+#include "internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+namespace svdphat {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+// Workspace of one stream on one plan, grown on demand (hipMalloc outside any
+// kernel; calls on the same plan and stream are ordered by the stream).
+void* ws_get(svdphat_plan* p, hipStream_t s, size_t bytes) {
+    std::lock_guard<std::mutex> lk(p->ws_mu);
+    Workspace& w = p->ws[(void*)s];
+    if (w.bytes < bytes) {
+        if (w.buf) {
+            SP_HIP(hipStreamSynchronize(s));
+            (void)hipFree(w.buf);
+            w.buf = nullptr;
+            w.bytes = 0;
+        }
+        size_t n = (size_t)round_up64((int64_t)bytes, 1 << 20);
+        if (hipMalloc(&w.buf, n) != hipSuccess) {
+            w.buf = nullptr;
+            (void)hipGetLastError();
+            fail(SVDPHAT_E_NOMEM, "workspace allocation of " + std::to_string(n) + " bytes failed");
+        }
+        w.bytes = n;
+    }
+    return w.buf;
+}
+
+template <typename Fn>
+static int guarded(Fn&& fn) {
+    try {
+        fn();
+        g_last_error.clear();
+        return SVDPHAT_OK;
+    } catch (const Error& e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return SVDPHAT_E_NOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return SVDPHAT_E_DEVICE;
+    } catch (...) {
+        g_last_error = "unknown failure";
+        return SVDPHAT_E_DEVICE;
+    }
+}
+
+static void free_plan(svdphat_plan* p) {
+    if (!p) return;
+    (void)hipSetDevice(p->device);
+    for (int i = 0; i < 3; ++i) {
+        if (p->A[i]) (void)hipFree(p->A[i]);
+        if (p->Alo[i]) (void)hipFree(p->Alo[i]);
+        if (p->Ufr[i]) (void)hipFree(p->Ufr[i]);
+    }
+    void* bufs[] = {p->U32T, p->d_rows, p->d_rep, p->d_rowof, p->d_tauN, p->d_tauN_all, p->d_pi, p->d_pj, p->Wfr};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    for (auto& kv : p->ws)
+        if (kv.second.buf) (void)hipFree(kv.second.buf);
+    delete p;
+}
+
+static void require_device() {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        fail(SVDPHAT_E_NODEV, "no HIP device available");
+    }
+}
+
+void build_plan(svdphat_plan* p, const double* mics, const double* grid);
+
+}  // namespace svdphat
+
+using namespace svdphat;
+
+extern "C" {
+
+int svdphat_version(void) { return 10000; }
+
+const char* svdphat_last_error(void) { return g_last_error.c_str(); }
+
+int svdphat_plan_create(const double* mic_xyz_m, int32_t M, const double* grid_xyz, int32_t Q, double fs,
+                        double c, int32_t N, double delta, uint32_t flags, svdphat_plan** out) {
+    return guarded([&] {
+        SP_REQUIRE(out != nullptr, SVDPHAT_E_INVAL, "out is NULL");
+        *out = nullptr;
+        SP_REQUIRE(mic_xyz_m && grid_xyz, SVDPHAT_E_INVAL, "NULL geometry or grid");
+        SP_REQUIRE(M >= 2 && M <= 16, SVDPHAT_E_INVAL, "M must be in [2, 16]");
+        SP_REQUIRE(Q >= 1, SVDPHAT_E_INVAL, "Q must be >= 1");
+        SP_REQUIRE(N >= 2 && N % 2 == 0, SVDPHAT_E_INVAL, "N must be even and >= 2");
+        SP_REQUIRE(std::isfinite(fs) && fs > 0 && std::isfinite(c) && c > 0, SVDPHAT_E_INVAL,
+                   "fs and c must be finite and > 0");
+        SP_REQUIRE(std::isfinite(delta) && delta >= 0.0 && delta < 1.0, SVDPHAT_E_INVAL, "delta must be in [0, 1)");
+        SP_REQUIRE((flags & ~(uint32_t)(SVDPHAT_KEEP_W | SVDPHAT_NO_DEDUP)) == 0, SVDPHAT_E_INVAL, "unknown flags");
+        for (int i = 0; i < 3 * M; ++i)
+            SP_REQUIRE(std::isfinite(mic_xyz_m[i]), SVDPHAT_E_INVAL, "non-finite microphone position");
+        for (int q = 0; q < Q; ++q) {
+            const double* s = grid_xyz + 3 * q;
+            SP_REQUIRE(std::isfinite(s[0]) && std::isfinite(s[1]) && std::isfinite(s[2]), SVDPHAT_E_INVAL,
+                       "non-finite grid direction");
+            SP_REQUIRE(s[0] * s[0] + s[1] * s[1] + s[2] * s[2] > 0.0, SVDPHAT_E_INVAL,
+                       "zero grid direction at row " + std::to_string(q));
+        }
+        const int64_t L = (int64_t)M * (M - 1) / 2 * (N / 2 + 1);
+        SP_REQUIRE(L < (int64_t)1 << 30 && (int64_t)Q * L < ((int64_t)1 << 40), SVDPHAT_E_INVAL, "problem too large");
+        require_device();
+        svdphat_plan* p = new svdphat_plan();
+        SP_HIP(hipGetDevice(&p->device));
+        p->M = M;
+        p->Q = Q;
+        p->N = N;
+        p->fs = fs;
+        p->c = c;
+        p->delta = delta;
+        p->flags = flags;
+        try {
+            build_plan(p, mic_xyz_m, grid_xyz);
+        } catch (...) {
+            free_plan(p);
+            throw;
+        }
+        *out = p;
+    });
+}
+
+int svdphat_plan_info(const svdphat_plan* p, svdphat_info* o) {
+    return guarded([&] {
+        SP_REQUIRE(p && o, SVDPHAT_E_INVAL, "NULL argument");
+        std::memset(o, 0, sizeof(*o));
+        o->M = p->M;
+        o->P = p->P;
+        o->B = p->B;
+        o->L = p->L;
+        o->Q = p->Q;
+        o->n_classes = p->ncls;
+        o->K = p->K;
+        o->K_paper = p->K_paper;
+        o->N = p->N;
+        o->has_w = p->Wfr != nullptr;
+        o->residual = p->residual;
+        o->sigma1 = p->sigma.empty() ? 0.0 : p->sigma[0];
+        o->sigmaK = p->K > 0 ? p->sigma[p->K - 1] : 0.0;
+        o->fro2 = p->fro2;
+        o->u_rownorm_max = p->kappa;
+        o->device_bytes = p->device_bytes;
+    });
+}
+
+int svdphat_plan_export(const svdphat_plan* p, double* sigma, double* U, double* V, int32_t* class_rep) {
+    return guarded([&] {
+        SP_REQUIRE(p, SVDPHAT_E_INVAL, "NULL plan");
+        if (sigma) std::memcpy(sigma, p->sigma.data(), p->sigma.size() * sizeof(double));
+        if (U) std::memcpy(U, p->U.data(), p->U.size() * sizeof(double));
+        if (V) {
+            // internal row c = bin * P + pair -> eq. (7) row pair * B + bin
+            const int K = p->K;
+            for (int bin = 0; bin < p->B; ++bin)
+                for (int pp = 0; pp < p->P; ++pp) {
+                    const size_t src = ((size_t)bin * p->P + pp) * K * 2;
+                    const size_t dst = ((size_t)pp * p->B + bin) * K * 2;
+                    std::memcpy(V + dst, p->V.data() + src, (size_t)K * 2 * sizeof(double));
+                }
+        }
+        if (class_rep) std::memcpy(class_rep, p->rep.data(), p->rep.size() * sizeof(int32_t));
+    });
+}
+
+int svdphat_locate(svdphat_plan* p, const void* X, int64_t F, int32_t precision, uint32_t mode, int32_t* doa,
+                   float* power, float* yhat, float* margin, float* y_opt, void* stream) {
+    return guarded([&] {
+        SP_REQUIRE(p, SVDPHAT_E_INVAL, "NULL plan");
+        SP_REQUIRE(F >= 0 && F < ((int64_t)1 << 31), SVDPHAT_E_INVAL, "F out of range");
+        SP_REQUIRE(precision == SVDPHAT_FP32 || precision == SVDPHAT_BF16 || precision == SVDPHAT_FP16,
+                   SVDPHAT_E_INVAL, "unknown precision");
+        SP_REQUIRE((mode & ~(uint32_t)(SVDPHAT_RESCORE | SVDPHAT_HILO)) == 0, SVDPHAT_E_INVAL, "unknown mode bits");
+        if (F == 0) return;
+        SP_REQUIRE(X && doa && power, SVDPHAT_E_INVAL, "NULL X, doa or power");
+        SP_HIP(hipSetDevice(p->device));
+        launch_locate(p, X, F, precision, mode, doa, power, yhat, margin, y_opt, (hipStream_t)stream);
+    });
+}
+
+int svdphat_srp_locate(svdphat_plan* p, const void* X, int64_t F, int32_t* doa, float* power, float* y_opt,
+                       void* stream) {
+    return guarded([&] {
+        SP_REQUIRE(p, SVDPHAT_E_INVAL, "NULL plan");
+        SP_REQUIRE(p->Wfr != nullptr, SVDPHAT_E_UNSUPPORTED, "plan was created without SVDPHAT_KEEP_W");
+        SP_REQUIRE(F >= 0 && F < ((int64_t)1 << 31), SVDPHAT_E_INVAL, "F out of range");
+        if (F == 0) return;
+        SP_REQUIRE(X && doa && power, SVDPHAT_E_INVAL, "NULL X, doa or power");
+        SP_HIP(hipSetDevice(p->device));
+        launch_srp(p, X, F, doa, power, y_opt, (hipStream_t)stream);
+    });
+}
+
+void svdphat_plan_destroy(svdphat_plan* p) { free_plan(p); }
+
+int svdphat_sync(void* stream) {
+    return guarded([&] {
+        require_device();
+        SP_HIP(hipStreamSynchronize((hipStream_t)stream));
+        SP_HIP(hipGetLastError());
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+// Internal declarations of the SVD-PHAT gfx950 library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/svdphat.h"
+
+namespace svdphat {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    int code;
+    std::string msg;
+};
+void set_last_error(const std::string& msg);
+[[noreturn]] void fail(int code, const std::string& msg);
+#define SP_HIP(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess)                                                     \
+            ::svdphat::fail(SVDPHAT_E_DEVICE, std::string(#call) + ": " +         \
+                                                  hipGetErrorString(e_));         \
+    } while (0)
+#define SP_REQUIRE(cond, code, msg)                                               \
+    do {                                                                          \
+        if (!(cond)) ::svdphat::fail((code), (msg));                              \
+    } while (0)
+
+// ------------------------------------------------------------ MFMA types
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Element-type traits for the three MFMA operand types.  KSTEP is the
+// reduction depth of one v_mfma_f32_16x16xKSTEP instruction and EPL the
+// number of operand elements each of the 64 lanes holds.
+template <typename T> struct Mf;
+template <> struct Mf<float> {
+    static constexpr int KSTEP = 4, EPL = 1;
+};
+template <> struct Mf<_Float16> {
+    static constexpr int KSTEP = 32, EPL = 8;
+};
+template <> struct Mf<__bf16> {
+    static constexpr int KSTEP = 32, EPL = 8;
+};
+
+enum Prec { P_FP32 = 0, P_BF16 = 1, P_FP16 = 2 };
+
+inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
+inline int64_t round_up64(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Rows of the reduced search are scored in tiles of this many directions;
+// the per-tile maximum is the unit of the candidate set that is rescored.
+constexpr int QTILE = 64;
+
+// Layout of the stacked-real GEMM1 operand for one element type: the
+// reduction axis (bins x pairs x {re, im}, bin-major) is cut into chunks of
+// BB bins; chunk width CW = round_up(BB * 2P, KSTEP) stacked values.
+struct G1Layout {
+    int BB = 0;       // bins per chunk
+    int CW = 0;       // stacked values per chunk (padded)
+    int nch = 0;      // chunks
+    int ks_chunk = 0; // MFMA k-steps per chunk
+    int64_t elems = 0;  // packed elements of A (all row blocks)
+};
+
+struct Workspace {
+    int64_t cap_frames = 0;
+    void* buf = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace svdphat
+
+struct svdphat_plan {
+    int device = 0;
+    int M = 0, P = 0, B = 0, L = 0, Q = 0, N = 0, K = 0, K_paper = 0;
+    double fs = 0, c = 0, delta = 0;
+    uint32_t flags = 0;
+    double residual = 0, fro2 = 0, kappa = 0;  // kappa = max_q ||U_q||
+    std::vector<double> tau;     // [Q][P] delays in samples, eq. (2)
+    std::vector<int32_t> rep;    // [Q] class representative
+    std::vector<int32_t> rows;   // [ncls] direction index of each scored row
+    std::vector<double> sigma;   // all singular values, descending
+    std::vector<double> U, V;    // FP64 factors, complex interleaved [Q][K], [L][K] (eq. (7) order)
+    int ncls = 0;                // scored rows
+    int ncls_pad = 0;            // rows padded to a multiple of 256
+    int R = 0;                   // 2K stacked rows of Z
+    int Rp = 0;                  // R padded to 32
+    svdphat::G1Layout g1[3];     // per precision
+    int64_t device_bytes = 0;
+
+    // device operands (all owned)
+    void* A[3] = {nullptr, nullptr, nullptr};    // GEMM1 operand per precision
+    void* Alo[3] = {nullptr, nullptr, nullptr};  // low parts (16-bit only)
+    void* Ufr[3] = {nullptr, nullptr, nullptr};  // GEMM2 operand per precision
+    float uscale[3] = {1.f, 1.f, 1.f};           // exact power-of-two scale of U per precision
+    float* U32T = nullptr;                       // [ntile][Rp][QTILE] FP32 rescoring rows
+    int32_t* d_rows = nullptr;                   // [ncls] direction index of row
+    int32_t* d_rep = nullptr;                    // [Q]
+    int32_t* d_rowof = nullptr;                  // [Q] scored row holding each direction's class
+    float* d_tauN = nullptr;                     // [ncls][P] tau / N (rows of the search)
+    float* d_tauN_all = nullptr;                 // [Q][P] tau / N
+    int8_t* d_pi = nullptr;                      // [P] first mic of pair
+    int8_t* d_pj = nullptr;                      // [P] second mic of pair
+    float* Wfr = nullptr;                        // plain form operand (KEEP_W)
+    int Wrows_pad = 0, Wks = 0;                  // rows padded to 128, k-steps of 4
+
+    std::mutex ws_mu;
+    std::map<void*, svdphat::Workspace> ws;  // per stream
+};
+
+namespace svdphat {
+// launchers (kernels.hip)
+void launch_locate(svdphat_plan* p, const void* X, int64_t F, int prec, uint32_t mode,
+                   int32_t* doa, float* power, float* yhat, float* margin, float* y_opt,
+                   hipStream_t s);
+void launch_srp(svdphat_plan* p, const void* X, int64_t F, int32_t* doa, float* power,
+                float* y_opt, hipStream_t s);
+void build_w_fp32_frags(svdphat_plan* p);
+void* ws_get(svdphat_plan* p, hipStream_t s, size_t bytes);
+}  // namespace svdphat

@@ -1,0 +1,89 @@
+"""The C ABI library loads, exports every symbol the header declares, and
+validates arguments without a GPU (CPU only; no compute call is made)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1811_11785_amd as amd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for f in os.listdir(inc):
+        if f.endswith(".h"):
+            txt = open(os.path.join(inc, f)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(svdphat_[a-z_0-9]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_header_symbols():
+    L = amd.lib()
+    names = _declared()
+    assert "svdphat_locate" in names and "svdphat_plan_create" in names
+    for n in names:
+        assert hasattr(L, n), n
+    # the binding wraps every declared entry point
+    assert names <= set(amd.SIGNATURES)
+
+
+def test_version():
+    assert amd.svdphat_version() == 10000
+
+
+@pytest.mark.parametrize("kw,what", [
+    (dict(N=31), "N odd"), (dict(N=0), "N zero"), (dict(delta=1.0), "delta 1"),
+    (dict(delta=-1e-3), "delta negative"), (dict(fs=0.0), "fs zero"), (dict(c=-1.0), "c negative"),
+])
+def test_plan_create_rejects(kw, what):
+    mics = np.zeros((4, 3))
+    mics[:, 0] = np.arange(4) * 0.02
+    grid = np.eye(3)
+    args = dict(fs=16000.0, c=343.0, N=32, delta=1e-5)
+    args.update(kw)
+    with pytest.raises(amd.SvdphatError) as e:
+        amd.svdphat_plan_create(mics, grid, args["fs"], args["c"], args["N"], args["delta"])
+    assert e.value.code == amd.E_INVAL, what
+    assert amd.lib().svdphat_last_error().decode()
+
+
+def test_plan_create_rejects_bad_geometry():
+    grid = np.eye(3)
+    with pytest.raises(amd.SvdphatError) as e:
+        amd.svdphat_plan_create(np.zeros((1, 3)), grid, 16000.0, 343.0, 32, 1e-5)
+    assert e.value.code == amd.E_INVAL
+    g = grid.copy()
+    g[1] = 0.0
+    m = np.random.default_rng(0).standard_normal((4, 3)) * 0.03
+    with pytest.raises(amd.SvdphatError) as e:
+        amd.svdphat_plan_create(m, g, 16000.0, 343.0, 32, 1e-5)
+    assert e.value.code == amd.E_INVAL
+    with pytest.raises(amd.SvdphatError) as e:
+        amd.svdphat_plan_create(m, grid, 16000.0, 343.0, 32, 1e-5, flags=0x80)
+    assert e.value.code == amd.E_INVAL
+
+
+def test_null_arguments():
+    L = amd.lib()
+    assert L.svdphat_plan_create(None, 4, None, 3, 16000.0, 343.0, 32, 1e-5, 0, None) == amd.E_INVAL
+    assert L.svdphat_locate(None, None, 1, 0, 0, None, None, None, None, None, None) == amd.E_INVAL
+    assert L.svdphat_srp_locate(None, None, 1, None, None, None, None) == amd.E_INVAL
+    assert L.svdphat_plan_info(None, None) == amd.E_INVAL
+    L.svdphat_plan_destroy(None)
+
+
+def test_no_device_reported():
+    """Without a GPU a valid request fails with E_NODEV, not a crash."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    mics = np.random.default_rng(0).standard_normal((4, 3)) * 0.03
+    with pytest.raises(amd.SvdphatError) as e:
+        amd.svdphat_plan_create(mics, np.eye(3), 16000.0, 343.0, 32, 1e-5)
+    assert e.value.code == amd.E_NODEV

@@ -85,19 +85,28 @@ def test_rank_rule_cluster_extension():
 
 # ------------------------------------------------------------------ P2
 def test_p2_full_rank_equals_srp():
-    mics, grid, rng = _small(M=4, N=16, level=2, seed=3)
-    tau = oracle.tdoa_farfield(mics, grid, 16000.0, 343.0)
-    W = oracle.steering_matrix(tau, 16)
-    U, s, Vh, Kp, K = oracle.truncated_svd(W, 0.0)
-    X = rng.standard_normal((6, 4, 9)) + 1j * rng.standard_normal((6, 4, 9))
-    x = oracle.phat_vector(X)
-    y_srp = oracle.srp_phat_power(W, x)
-    y_svd = oracle.svd_phat_power(U, s, Vh, x)
-    assert np.max(np.abs(y_srp - y_svd)) <= 1e-10 * W.shape[1]
-    # stacked real form gives the same numbers
-    Ast, Ust = oracle.stacked_projection(U, s, Vh)
-    xs = np.concatenate([x.real, x.imag], axis=1)
-    assert np.allclose((xs @ Ast.T) @ Ust.T, y_svd, atol=1e-9)
+    """With every singular value kept, eqs. (12)-(14) reproduce eq. (9) to
+    rounding; with the numerical-rank cut (delta = 0) the difference is
+    bounded by the first dropped singular value times ||x||."""
+    for level, seed in ((0, 3), (2, 3)):
+        mics, grid, rng = _small(M=4, N=16, level=level, seed=seed)
+        tau = oracle.tdoa_farfield(mics, grid, 16000.0, 343.0)
+        W = oracle.steering_matrix(tau, 16)
+        U, s, Vh, Kp, K = oracle.truncated_svd(W, 0.0)
+        X = rng.standard_normal((6, 4, 9)) + 1j * rng.standard_normal((6, 4, 9))
+        x = oracle.phat_vector(X)
+        y_srp = oracle.srp_phat_power(W, x)
+        y_svd = oracle.svd_phat_power(U, s, Vh, x)
+        dropped = s[K] if K < s.size else 0.0
+        bound = dropped * np.linalg.norm(x, axis=1)[:, None] + 1e-10 * W.shape[1]
+        assert np.all(np.abs(y_srp - y_svd) <= bound)
+        if level == 0:
+            assert K == s.size  # full rank: equality to rounding
+            assert np.max(np.abs(y_srp - y_svd)) <= 1e-10 * W.shape[1]
+        # stacked real form gives the same numbers
+        Ast, Ust = oracle.stacked_projection(U, s, Vh)
+        xs = np.concatenate([x.real, x.imag], axis=1)
+        assert np.allclose((xs @ Ast.T) @ Ust.T, y_svd, atol=1e-9)
 
 
 # ------------------------------------------------------------------ P10 brute force
