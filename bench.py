@@ -1,0 +1,228 @@
+"""Benchmark: frames/s of SVD-PHAT on one MI355X on the planar 7-mic array
+(Table 2) with Q = 10242 directions (icosphere level 5), N = 512, hop 256,
+delta = 1e-5, 20000 seeded synthetic frames (plane-wave white-noise source,
+random direction and SNR U[0, 20] dB per 100-frame segment).
+
+One step = one call of the whole hot path over the 20000-frame batch already
+resident in HBM: PHAT, Z = S V^H X, Y = Re(U Z), argmax with FP32 rescoring
+(and hi/lo recomputation where the margin is small), power of the chosen
+direction.  The headline form is FP16 MFMA with FP32 accumulation; plain
+FP32 SRP-PHAT (eq. (9)) on the same batch is timed beside it.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+MFMA_FP16_PEAK_TFLOPS = 2500.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _timed(fn, steps, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(w, gold_doa, budget_s: float):
+    """The FP64 oracle timed on the host's cores on a bounded sample of the
+    same frames (its offline SVD is built first and timed separately)."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    t0 = time.perf_counter()
+    log("oracle plan (FP64 SVD of W) ...")
+    plan = oracle.make_plan(w["mics"], w["grid"], w["fs"], w["c"], w["N"], w["delta"])
+    plan_s = time.perf_counter() - t0
+    log(f"oracle plan {plan_s:.1f} s; timing oracle.locate for {budget_s:.0f} s")
+    X = w["X"]
+    done, chunk = 0, 256
+    t0 = time.perf_counter()
+    doas = []
+    while time.perf_counter() - t0 < budget_s and done < X.shape[0]:
+        r = oracle.locate(plan, X[done:done + chunk])
+        doas.append(r["doa"])
+        done += r["doa"].shape[0]
+    dt = time.perf_counter() - t0
+    doa = np.concatenate(doas)
+    return dict(value=done / dt, unit="frames/s", cores=int(cores), kind="oracle",
+                sample=f"first {done} of the {X.shape[0]} frames, FP64 numpy/LAPACK oracle.locate "
+                       f"(PHAT, Z = S V^H X, Y = Re(U Z), argmax, row power); offline SVD "
+                       f"{plan_s:.1f} s excluded"), plan_s, doa
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--frames", type=int, default=20000)
+    ap.add_argument("--srp-steps", type=int, default=3)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the frames of a batch are "
+              f"independent, so N GPUs would each run this benchmark on their own frames.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1811_11785_amd as amd
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    amd.lib()
+    w = synth.workload("planar_q10242", frames=args.frames)
+    F = w["X"].shape[0]
+    t0 = time.perf_counter()
+    plan = amd.Plan(w["mics"], w["grid"], w["fs"], w["c"], w["N"], w["delta"], keep_w=True)
+    plan_s = time.perf_counter() - t0
+    info = plan.info
+    log(f"plan built in {plan_s:.1f} s: K={info['K']} classes={info['n_classes']}")
+    X = torch.from_numpy(w["X"]).cuda()
+    dev = X.device
+    doa = torch.empty(F, dtype=torch.int32, device=dev)
+    power = torch.empty(F, dtype=torch.float32, device=dev)
+    yhat = torch.empty(F, dtype=torch.float32, device=dev)
+    margin = torch.empty(F, dtype=torch.float32, device=dev)
+    h = plan.handle
+
+    def svd_step(prec, mode):
+        return lambda: amd.svdphat_locate(h, X, prec, mode, doa, power, yhat, margin)
+
+    forms = {
+        "fp16": (amd.FP16, amd.RESCORE | amd.HILO),
+        "bf16": (amd.BF16, amd.RESCORE | amd.HILO),
+        "fp32": (amd.FP32, amd.RESCORE),
+    }
+    results = {}
+    for name, (prec, mode) in forms.items():
+        step = svd_step(prec, mode)
+        nw = args.warmup if name == "fp16" else 2
+        ns = args.steps if name == "fp16" else max(3, args.steps // 5)
+        _timed(step, nw, torch)
+        dt = _timed(step, ns, torch)
+        results[name] = dict(fps=F * ns / dt, ms_per_step=1e3 * dt / ns, steps=ns)
+        d = doa.cpu().numpy()
+        results[name]["doa"] = d
+        log(f"{name}: {results[name]['fps']:.4g} frames/s ({results[name]['ms_per_step']:.3f} ms/step)")
+    # plain FP32 SRP-PHAT on the same batch
+    srp = lambda: amd.svdphat_srp_locate(h, X, doa, power)
+    _timed(srp, 1, torch)
+    dt = _timed(srp, args.srp_steps, torch)
+    srp_fps = F * args.srp_steps / dt
+    srp_doa = doa.cpu().numpy()
+    log(f"plain fp32 srp: {srp_fps:.4g} frames/s")
+
+    # per-kernel durations with HIP events on the launch stream (same work)
+    amd.svdphat_timing_reset()
+    amd.svdphat_timing_enable(True)
+    prec, mode = forms["fp16"]
+    for _ in range(args.steps):
+        amd.svdphat_locate(h, X, prec, mode, doa, power, yhat, margin)
+    amd.svdphat_timing_enable(False)
+    kt = amd.svdphat_timing_read()
+    amd.svdphat_timing_reset()
+    amd.svdphat_timing_enable(True)
+    for _ in range(args.srp_steps):
+        amd.svdphat_srp_locate(h, X, doa, power)
+    amd.svdphat_timing_enable(False)
+    kt_srp = amd.svdphat_timing_read()
+    torch.cuda.synchronize()
+    kernels = {k: dict(avg_us=1e3 * v[0] / v[1], launches=v[1]) for k, v in kt.items()}
+    kernels_srp = {k: dict(avg_us=1e3 * v[0] / v[1], launches=v[1]) for k, v in kt_srp.items()}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
+
+    # roofline of the dominant kernel: algorithmic bytes / flops per launch
+    M, B, K2, ncls = info["M"], info["B"], 2 * info["K"], info["n_classes"]
+    L = info["L"]
+    x_bytes = F * M * B * 8
+    a_bytes = K2 * 2 * L * 2
+    if dom == "gemm1":
+        algo = x_bytes + a_bytes + F * K2 * 4
+        dur = kernels[dom]["avg_us"] * 1e-6
+        roof = dict(bound="hbm", achieved=algo / dur / 1e9, peak=HBM_PEAK_GBS, unit="GB/s", traffic=None)
+    elif dom == "gemm2":
+        flops = 2.0 * ncls * K2 * F
+        dur = kernels[dom]["avg_us"] * 1e-6
+        roof = dict(bound="mfma", achieved=flops / dur / 1e12, peak=MFMA_FP16_PEAK_TFLOPS, unit="TFLOP/s",
+                    traffic=None)
+    else:
+        algo = x_bytes
+        dur = kernels[dom]["avg_us"] * 1e-6
+        roof = dict(bound="hbm", achieved=algo / dur / 1e9, peak=HBM_PEAK_GBS, unit="GB/s", traffic=None)
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = dom
+
+    # accuracy against the stored FP64 oracle answers (first frames)
+    gold = dict(np.load(os.path.join(ROOT, "tests", "golden", "planar_q10242_oracle.npz")))
+    n = min(int(gold["frames"]), F)
+    judged = gold["margin"][:n] > 1e-5
+    acc = {}
+    for name in forms:
+        d = results[name]["doa"][:n]
+        acc[name] = dict(match_all=float(np.mean(d == gold["doa"][:n])),
+                         match_judged=float(np.mean(d[judged] == gold["doa"][:n][judged])),
+                         match_vs_fp64_srp=float(np.mean(d == gold["srp_doa"][:n])))
+    acc["srp_fp32"] = dict(match_vs_fp64_srp=float(np.mean(srp_doa[:n] == gold["srp_doa"][:n])),
+                           match_vs_fp64_svd=float(np.mean(srp_doa[:n] == gold["doa"][:n])))
+
+    cpu = None
+    if not args.no_cpu:
+        cpu, oracle_plan_s, _ = cpu_baseline(w, gold["doa"], args.cpu_budget)
+
+    head = results["fp16"]
+    out = {
+        "metric": "frames/s at Q=10242, 7 mics: mixed SVD-PHAT vs plain FP32; argmax match %",
+        "value": head["fps"],
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": head["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp16",
+        "data": "synthetic",
+        "config": {"workload": "planar_q10242", "array": "planar 7-mic (Table 2)", "Q": info["Q"],
+                   "K": info["K"], "n_classes": ncls, "N": info["N"], "frames_per_step": F,
+                   "delta": w["delta"], "form": "FP16 MFMA, FP32 accumulate, FP32 rescoring, hi/lo fallback"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "plain_fp32_srp_fps": srp_fps,
+        "speedup_vs_plain_fp32": head["fps"] / srp_fps,
+        "forms_fps": {k: v["fps"] for k, v in results.items()},
+        "argmax_match": acc,
+        "kernels_us": kernels,
+        "kernels_srp_us": kernels_srp,
+        "plan_build_s": plan_s,
+    }
+    if cpu is not None:
+        out["oracle_plan_s"] = oracle_plan_s
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -165,6 +165,21 @@ const char* svdphat_last_error(void);
 /* svdphat_sync -- waits for the stream and reports any pending device error. */
 int svdphat_sync(void* stream);
 
+/*
+ * Per-kernel timing (instrumentation, not part of the method).
+ * svdphat_timing_enable(1) brackets every kernel that the library launches
+ * with HIP events on the launch's stream; each call then waits for its own
+ * events before returning and adds the elapsed time to a process-wide table
+ * keyed by kernel name.  svdphat_timing_read returns entry `index` (0-based,
+ * names in lexicographic order): name (NUL-terminated, truncated to
+ * name_len), total milliseconds and launch count; E_INVAL past the last entry.
+ * svdphat_timing_reset clears the table.
+ */
+int svdphat_timing_enable(int enable);
+int svdphat_timing_reset(void);
+int svdphat_timing_read(int32_t index, char* name, int32_t name_len,
+                        double* total_ms, int64_t* launches);
+
 /* svdphat_version -- ABI version (major * 10000 + minor * 100 + patch). */
 int svdphat_version(void);
 

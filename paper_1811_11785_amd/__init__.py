@@ -62,6 +62,10 @@ SIGNATURES = {
                                      C.c_void_p, C.c_void_p]),
     "svdphat_plan_destroy": (None, [C.c_void_p]),
     "svdphat_sync": (C.c_int, [C.c_void_p]),
+    "svdphat_timing_enable": (C.c_int, [C.c_int]),
+    "svdphat_timing_reset": (C.c_int, []),
+    "svdphat_timing_read": (C.c_int, [C.c_int32, C.c_char_p, C.c_int32, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_int64)]),
 }
 
 
@@ -146,6 +150,28 @@ def svdphat_plan_destroy(plan):
 
 def svdphat_sync(stream=None):
     _check(lib().svdphat_sync(_stream(stream)))
+
+
+def svdphat_timing_enable(enable: bool):
+    _check(lib().svdphat_timing_enable(1 if enable else 0))
+
+
+def svdphat_timing_reset():
+    _check(lib().svdphat_timing_reset())
+
+
+def svdphat_timing_read() -> dict:
+    """{kernel name: (total ms, launches)} of the instrumented launches."""
+    out = {}
+    i = 0
+    buf = C.create_string_buffer(64)
+    while True:
+        ms, n = C.c_double(), C.c_int64()
+        if lib().svdphat_timing_read(i, buf, 64, C.byref(ms), C.byref(n)) != OK:
+            break
+        out[buf.value.decode()] = (ms.value, n.value)
+        i += 1
+    return out
 
 
 # ------------------------------------------------------------ convenience

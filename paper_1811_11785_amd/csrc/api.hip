@@ -84,6 +84,56 @@ static void require_device() {
 
 void build_plan(svdphat_plan* p, const double* mics, const double* grid);
 
+// ------------------------------------------------------------ timing
+namespace {
+struct TimingTable {
+    std::mutex mu;
+    bool on = false;
+    std::map<std::string, std::pair<double, int64_t>> t;
+};
+TimingTable& timing() {
+    static TimingTable tt;
+    return tt;
+}
+}  // namespace
+
+bool timing_on() { return timing().on; }
+
+void KernelTimer::begin(const char* name) {
+    if (!timing_on()) return;
+    Rec r{name, nullptr, nullptr};
+    SP_HIP(hipEventCreate(&r.a));
+    SP_HIP(hipEventCreate(&r.b));
+    SP_HIP(hipEventRecord(r.a, s));
+    recs.push_back(r);
+}
+void KernelTimer::end() {
+    if (!timing_on() || recs.empty()) return;
+    SP_HIP(hipEventRecord(recs.back().b, s));
+}
+void KernelTimer::flush() {
+    for (auto& r : recs) {
+        SP_HIP(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        SP_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        std::lock_guard<std::mutex> lk(timing().mu);
+        auto& e = timing().t[r.name];
+        e.first += ms;
+        e.second += 1;
+    }
+    for (auto& r : recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    recs.clear();
+}
+KernelTimer::~KernelTimer() {
+    for (auto& r : recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+}
+
 }  // namespace svdphat
 
 using namespace svdphat;
@@ -209,6 +259,36 @@ int svdphat_srp_locate(svdphat_plan* p, const void* X, int64_t F, int32_t* doa, 
 }
 
 void svdphat_plan_destroy(svdphat_plan* p) { free_plan(p); }
+
+int svdphat_timing_enable(int enable) {
+    return guarded([&] {
+        std::lock_guard<std::mutex> lk(timing().mu);
+        timing().on = enable != 0;
+    });
+}
+
+int svdphat_timing_reset(void) {
+    return guarded([&] {
+        std::lock_guard<std::mutex> lk(timing().mu);
+        timing().t.clear();
+    });
+}
+
+int svdphat_timing_read(int32_t index, char* name, int32_t name_len, double* total_ms, int64_t* launches) {
+    return guarded([&] {
+        std::lock_guard<std::mutex> lk(timing().mu);
+        SP_REQUIRE(index >= 0, SVDPHAT_E_INVAL, "negative index");
+        if (index >= (int32_t)timing().t.size()) fail(SVDPHAT_E_INVAL, "index past the last timed kernel");
+        auto it = timing().t.begin();
+        std::advance(it, index);
+        if (name && name_len > 0) {
+            std::strncpy(name, it->first.c_str(), (size_t)name_len - 1);
+            name[name_len - 1] = 0;
+        }
+        if (total_ms) *total_ms = it->second.first;
+        if (launches) *launches = it->second.second;
+    });
+}
 
 int svdphat_sync(void* stream) {
     return guarded([&] {

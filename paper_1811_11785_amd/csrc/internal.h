@@ -129,4 +129,22 @@ void launch_srp(svdphat_plan* p, const void* X, int64_t F, int32_t* doa, float* 
                 float* y_opt, hipStream_t s);
 void build_w_fp32_frags(svdphat_plan* p);
 void* ws_get(svdphat_plan* p, hipStream_t s, size_t bytes);
+
+// Per-kernel timing (instrumentation): while enabled, each launch is
+// bracketed by HIP events on its stream; `flush` waits for them and adds the
+// elapsed times to a process-wide table keyed by kernel name.
+bool timing_on();
+struct KernelTimer {
+    struct Rec {
+        const char* name;
+        hipEvent_t a, b;
+    };
+    hipStream_t s;
+    std::vector<Rec> recs;
+    explicit KernelTimer(hipStream_t st) : s(st) {}
+    void begin(const char* name);
+    void end();
+    void flush();
+    ~KernelTimer();
+};
 }  // namespace svdphat

@@ -702,7 +702,9 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
 
     const int M = p->M;
     const int64_t zstride = Fc * Rp;
+    KernelTimer kt(s);
     const size_t lds = (size_t)64 * (g.CW + XPAD) * sizeof(T);
+    kt.begin("gemm1");
     dim3 g1grid(ftiles, nsplit, nrg);
     if (M <= 8)
         k_gemm1<T, 64, 8, false><<<g1grid, 256, lds, s>>>(X, F, M, p->P, p->B, p->d_pi, p->d_pj, (const T*)p->A[prec],
@@ -713,18 +715,25 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
                                                            nullptr, nRB, g.BB, g.CW, g.nch, cps, zpart, zstride, Rp,
                                                            nullptr, nullptr);
     SP_HIP(hipGetLastError());
+    kt.end();
+    kt.begin("zprep");
     k_zprep<T><<<dim3((unsigned)(Fc / 4)), 256, 0, s>>>(zpart, nsplit, zstride, F, nullptr, Rp, z32, zfrag, zsc, zn,
                                                         prec == P_FP16 ? 1 : 0);
     SP_HIP(hipGetLastError());
+    kt.end();
     const float uinv = 1.f / p->uscale[prec];
+    kt.begin("gemm2");
     k_gemm2<T><<<dim3(p->ncls_pad / 256, (unsigned)(Fc / 64)), 256, 0, s>>>(
         (const T*)p->Ufr[prec], KSn, zfrag, F, p->ncls, zsc, uinv, pmax, Fc, ycls, p->ncls_pad);
     SP_HIP(hipGetLastError());
+    kt.end();
     if (y_opt) {
+        kt.begin("scatter_y");
         const int64_t tot = F * p->Q;
         // row of every direction: its class representative's row
         k_scatter_y<<<dim3((unsigned)((tot + 255) / 256)), 256, 0, s>>>(ycls, p->ncls_pad, p->d_rowof, p->Q, F, y_opt);
         SP_HIP(hipGetLastError());
+        kt.end();
     }
     const double u = unit_roundoff(prec);
     const double acc_err = 2.0 * Rp * std::ldexp(1.0, -24);
@@ -732,7 +741,9 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     const float ecoef = (float)(lin * p->kappa * 1.01);
     const int rescore = (mode & SVDPHAT_RESCORE) ? 1 : 0;
     const float hthr = prec == P_FP16 ? 1e-4f : 1e-3f;
-    auto finalize = [&](const float* zz, const float* znn, const int* fl, const int* fc, const float* zfirst) {
+    auto finalize = [&](const char* name, const float* zz, const float* znn, const int* fl, const int* fc,
+                        const float* zfirst) {
+        kt.begin(name);
         dim3 grid((unsigned)(Fc / 4));
         if (M <= 8)
             k_final<8><<<grid, 256, 0, s>>>(X, M, p->P, p->B, pmax, Fc, ntile, p->ncls, zz, Rp, znn, ecoef,
@@ -743,12 +754,14 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
                                              (float)p->kappa, rescore, p->U32T, p->d_rows, p->d_rep, p->d_tauN_all, F,
                                              fl, fc, zfirst, doa, power, yhat, margin, hthr, fl ? nullptr : hl, hc);
         SP_HIP(hipGetLastError());
+        kt.end();
     };
-    finalize(z32, zn, nullptr, nullptr, nullptr);
+    finalize("final", z32, zn, nullptr, nullptr, nullptr);
     if (hilo) {
         float* z32h = (float*)(w + o_z32h);
         float* znh = (float*)(w + o_znh);
         const size_t lds2 = (size_t)2 * 32 * (g.CW + XPAD) * sizeof(T);
+        kt.begin("gemm1_hilo");
         dim3 hg((unsigned)(Fc / 32), nsplit, nrg);
         if (M <= 8)
             k_gemm1<T, 32, 8, true><<<hg, 128, lds2, s>>>(X, F, M, p->P, p->B, p->d_pi, p->d_pj, (const T*)p->A[prec],
@@ -759,11 +772,15 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
                                                            (const T*)p->A[prec], (const T*)p->Alo[prec], nRB, g.BB,
                                                            g.CW, g.nch, cps, zpart, zstride, Rp, hl, hc);
         SP_HIP(hipGetLastError());
+        kt.end();
+        kt.begin("zprep_hilo");
         k_zprep<T><<<dim3((unsigned)(Fc / 4)), 256, 0, s>>>(zpart, nsplit, zstride, F, hc, Rp, z32h, nullptr, zsc,
                                                             znh, 0);
         SP_HIP(hipGetLastError());
-        finalize(z32h, znh, hl, hc, z32);
+        kt.end();
+        finalize("final_hilo", z32h, znh, hl, hc, z32);
     }
+    kt.flush();
     (void)EPL;
 }
 
@@ -813,20 +830,28 @@ void launch_srp(svdphat_plan* p, const void* Xv, int64_t F, int32_t* doa, float*
     const size_t o_v = take(sizeof(float) * ntile * Fp);
     const size_t o_i = take(sizeof(int) * ntile * Fp);
     char* w = (char*)ws_get(p, s, off);
+    KernelTimer kt(s);
     float* xfr = (float*)(w + o_x);
     float* pv = (float*)(w + o_v);
     int* pidx = (int*)(w + o_i);
+    kt.begin("srp_phat");
     const int64_t items = Fp * p->B;
     if (p->M <= 8)
         k_phat_frag<8><<<dim3((unsigned)((items + 255) / 256)), 256, 0, s>>>(X, F, Fp, p->M, p->P, p->B, Wks, xfr);
     else
         k_phat_frag<16><<<dim3((unsigned)((items + 255) / 256)), 256, 0, s>>>(X, F, Fp, p->M, p->P, p->B, Wks, xfr);
     SP_HIP(hipGetLastError());
+    kt.end();
+    kt.begin("srp_gemm");
     k_srp_gemm<<<dim3(ntile, (unsigned)(Fp / 128)), 256, 0, s>>>(p->Wfr, xfr, Wks, p->Q, F, pv, pidx, Fp, y_opt,
                                                                  p->Q);
     SP_HIP(hipGetLastError());
+    kt.end();
+    kt.begin("srp_reduce");
     k_srp_reduce<<<dim3((unsigned)((F + 255) / 256)), 256, 0, s>>>(pv, pidx, Fp, ntile, F, p->d_rep, doa, power);
     SP_HIP(hipGetLastError());
+    kt.end();
+    kt.flush();
 }
 
 }  // namespace svdphat
