@@ -106,6 +106,8 @@ struct svdphat_plan {
     void* Ufr[3] = {nullptr, nullptr, nullptr};  // GEMM2 operand per precision
     float uscale[3] = {1.f, 1.f, 1.f};           // exact power-of-two scale of U per precision
     float* U32T = nullptr;                       // [ntile][Rp][QTILE] FP32 rescoring rows
+    float* d_tkappa = nullptr;                   // [ntile] largest ||U_q|| of each tile
+    float* d_sig = nullptr;                      // [Rp] singular value of each stacked row of Z
     int32_t* d_rows = nullptr;                   // [ncls] direction index of row
     int32_t* d_rep = nullptr;                    // [Q]
     int32_t* d_rowof = nullptr;                  // [Q] scored row holding each direction's class

@@ -233,6 +233,34 @@ void build_plan(svdphat_plan* p, const double* mics, const double* grid) {
     p->rows.clear();
     for (int q = 0; q < Q; ++q)
         if ((p->flags & SVDPHAT_NO_DEDUP) || p->rep[q] == q) p->rows.push_back(q);
+    // Score rows in a space-filling-curve order of their directions (3-D
+    // Morton code of the unit vector): nearby directions, whose powers are
+    // close, share tiles, so few tiles are within the rescoring bound of the
+    // frame maximum.  Ties of the search are still broken by direction index.
+    {
+        auto spread = [](uint32_t v) {
+            uint64_t x = v & 0x3ff;
+            x = (x | (x << 16)) & 0x30000ff;
+            x = (x | (x << 8)) & 0x300f00f;
+            x = (x | (x << 4)) & 0x30c30c3;
+            x = (x | (x << 2)) & 0x9249249;
+            return x;
+        };
+        std::vector<std::pair<uint64_t, int32_t>> key;
+        key.reserve(p->rows.size());
+        for (int32_t q : p->rows) {
+            const double* sv = grid + 3 * q;
+            const double nn = std::sqrt(sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2]);
+            uint32_t c[3];
+            for (int d = 0; d < 3; ++d) {
+                double u = (sv[d] / nn + 1.0) * 0.5;
+                c[d] = (uint32_t)std::min(1023.0, std::max(0.0, std::floor(u * 1024.0)));
+            }
+            key.emplace_back(spread(c[0]) | (spread(c[1]) << 1) | (spread(c[2]) << 2), q);
+        }
+        std::sort(key.begin(), key.end());
+        for (size_t i = 0; i < key.size(); ++i) p->rows[i] = key[i].second;
+    }
     p->ncls = (int)p->rows.size();
     p->ncls_pad = round_up(p->ncls, 256);
 
@@ -366,6 +394,7 @@ void build_plan(svdphat_plan* p, const double* mics, const double* grid) {
     // ---- packing
     p->R = 2 * K;
     p->Rp = round_up(p->R, 32);
+    if (p->Rp > 1024) fail(SVDPHAT_E_UNSUPPORTED, "rank K above 512 is not supported");
     const int nRB = p->Rp / 16;
     p->g1[P_FP32] = make_layout(P, B, 4, Mf<float>::KSTEP, nRB, Mf<float>::EPL);
     p->g1[P_FP16] = make_layout(P, B, 2, Mf<_Float16>::KSTEP, nRB, Mf<_Float16>::EPL);
@@ -426,6 +455,20 @@ void build_plan(svdphat_plan* p, const double* mics, const double* grid) {
         void* d = nullptr;
         upload(t, &d, bytes);
         p->U32T = (float*)d;
+        // largest row norm of each tile (rounding bound of its rows)
+        std::vector<float> tk(ntile, 0.f);
+        for (int r = 0; r < p->ncls; ++r) {
+            double nrm = 0.0;
+            for (int k = 0; k < p->Rp; ++k) nrm += (double)Ust[(size_t)r * p->Rp + k] * Ust[(size_t)r * p->Rp + k];
+            tk[r / QTILE] = std::max(tk[r / QTILE], (float)(std::sqrt(nrm) * (1.0 + 1e-6)));
+        }
+        upload(tk, &d, bytes);
+        p->d_tkappa = (float*)d;
+        // singular value of each stacked row of Z (rows k and K + k: s_k)
+        std::vector<float> sg(p->Rp, 0.f);
+        for (int k = 0; k < K; ++k) sg[k] = sg[K + k] = (float)p->sigma[k];
+        upload(sg, &d, bytes);
+        p->d_sig = (float*)d;
     }
     {
         std::vector<int32_t> rows(p->rows);

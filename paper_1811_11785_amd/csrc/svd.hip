@@ -1,0 +1,832 @@
+// Online SVD-PHAT on gfx950 (Algorithm 1, online steps 1-4, Section 3) with
+// the exhaustive search of eq. (14).
+//
+//   k_gemm1   PHAT cross-spectra (eq. (3)) formed in LDS from the STFT and
+//             projected with MFMA: Z = S V^H X (eq. (12) with S folded into
+//             V^H), stacked real.  The reduction axis is split over the grid
+//             (partial Z per split) and, inside a workgroup, interleaved over
+//             the four waves, so each A fragment is read once per workgroup.
+//   k_zprep   sums the partial Z, keeps an FP32 copy and ||z||, and packs a
+//             copy in the GEMM2 operand type and fragment order (FP16 scaled
+//             by a power of two per frame).
+//   k_gemm2   Y = Re(U Z) (eqs. (13)-(14)) with MFMA.  Each wave holds the U
+//             fragments of one tile of 64 scored directions in registers and
+//             streams frames; its epilogue keeps one maximum per (frame, tile).
+//   k_final   per frame: every tile whose maximum is within the rounding bound
+//             of the frame maximum is rescored in FP32; best class, runner-up
+//             and margin; the power of the chosen direction from its row of W
+//             (Algorithm 1, online step 4); frames whose margin is within the
+//             modelled GEMM1 rounding are queued for a hi/lo recomputation.
+#include "device.h"
+
+namespace svdphat {
+
+namespace {
+
+constexpr int XPAD = 8;  // LDS row padding (elements) of the x tile
+
+// ------------------------------------------------------------------ GEMM1
+// Workgroup: 4 waves, NF frames, NRB row blocks of Z (row group blockIdx.z),
+// the chunks [blockIdx.y * cps, ...) of the reduction axis.  Per chunk, the
+// PHAT vector of BB bins x NF frames is formed in LDS (per-mic unit
+// normalisation, then X_i conj(X_j) for pairs i < j in order, rounded to T
+// and stored as (Re, Im) pairs), then the chunk's k-steps are shared out
+// round-robin to the waves; each wave accumulates all NRB x NF/16 output
+// blocks.  The four partial sums are added through LDS at the end.
+template <typename T, int NF, int NRB, int MAXM, bool HILO>
+__global__ __launch_bounds__(256) void k_gemm1(const float2* __restrict__ X, int64_t nfr, int M, int P, int B,
+                                               const T* __restrict__ A, const T* __restrict__ Alo, int nRB, int BB,
+                                               int CW, int nch, int cps, float* __restrict__ zpart, int64_t zstride,
+                                               int Rp, const int* __restrict__ flist, const int* __restrict__ fcount) {
+    constexpr int KS = Mf<T>::KSTEP, EPL = Mf<T>::EPL, FB = NF / 16;
+    typedef typename Vec<T>::t VT;
+    typedef typename Vec<T>::pair VP;
+    extern __shared__ __align__(16) char smem[];
+    T* xs = reinterpret_cast<T*>(smem);
+    const int ldx = CW + XPAD;
+    T* xl = xs + NF * ldx;
+
+    const int64_t n = flist ? (int64_t)*fcount : nfr;
+    const int64_t f0 = (int64_t)blockIdx.x * NF;
+    if (f0 >= n) return;
+    const int c0 = blockIdx.y * cps, c1 = min(nch, c0 + cps);
+    const int rbs = blockIdx.z * NRB;
+    const int nrb = min(NRB, nRB - rbs);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ks_chunk = CW / KS;
+    const int twoP = 2 * P;
+
+    for (int i = threadIdx.x; i < NF * ldx; i += 256) {
+        if (i % ldx >= BB * twoP) {
+            xs[i] = cvt<T>(0.f);
+            if (HILO) xl[i] = cvt<T>(0.f);
+        }
+    }
+    f4 acc[NRB][FB];
+#pragma unroll
+    for (int r = 0; r < NRB; ++r)
+#pragma unroll
+        for (int j = 0; j < FB; ++j) acc[r][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+    for (int ch = c0; ch < c1; ++ch) {
+        __syncthreads();
+        for (int it = threadIdx.x; it < NF * BB; it += 256) {
+            const int fl = it / BB, bl = it - (it / BB) * BB;
+            const int64_t fpos = f0 + fl;
+            const int bin = ch * BB + bl;
+            VP* dst = reinterpret_cast<VP*>(xs + fl * ldx + bl * twoP);
+            VP* dlo = reinterpret_cast<VP*>(xl + fl * ldx + bl * twoP);
+            if (fpos < n && bin < B) {
+                const int64_t f = flist ? (int64_t)flist[fpos] : fpos;
+                const float2* xf = X + f * M * B + bin;
+                float re[MAXM], im[MAXM];
+#pragma unroll
+                for (int m = 0; m < MAXM; ++m) {
+                    const float2 v = m < M ? xf[(int64_t)m * B] : float2{0.f, 0.f};
+                    re[m] = v.x;
+                    im[m] = v.y;
+                    unit(re[m], im[m]);
+                }
+                int p = 0;
+#pragma unroll
+                for (int i = 0; i < MAXM; ++i)
+#pragma unroll
+                    for (int j = i + 1; j < MAXM; ++j)
+                        if (j < M) {
+                            const float xr = re[i] * re[j] + im[i] * im[j];
+                            const float xi = im[i] * re[j] - re[i] * im[j];
+                            const T hr = cvt<T>(xr), hi = cvt<T>(xi);
+                            dst[p] = mkpair<T>(hr, hi);
+                            if (HILO) dlo[p] = mkpair<T>(cvt<T>(xr - (float)hr), cvt<T>(xi - (float)hi));
+                            ++p;
+                        }
+            } else {
+                for (int k = 0; k < P; ++k) {
+                    dst[k] = mkpair<T>(cvt<T>(0.f), cvt<T>(0.f));
+                    if (HILO) dlo[k] = mkpair<T>(cvt<T>(0.f), cvt<T>(0.f));
+                }
+            }
+        }
+        __syncthreads();
+        const int64_t cbase = (int64_t)ch * ks_chunk * nRB;
+        VT an[NRB], aln[NRB];
+        auto loadA = [&](int ks) {
+#pragma unroll
+            for (int r = 0; r < NRB; ++r)
+                if (r < nrb) {
+                    const int64_t off = ((cbase + (int64_t)ks * nRB + rbs + r) * 64 + lane) * EPL;
+                    an[r] = *reinterpret_cast<const VT*>(A + off);
+                    if (HILO) aln[r] = *reinterpret_cast<const VT*>(Alo + off);
+                }
+        };
+        if (wave < ks_chunk) loadA(wave);
+        for (int ks = wave; ks < ks_chunk; ks += 4) {
+            VT a[NRB], al[NRB];
+#pragma unroll
+            for (int r = 0; r < NRB; ++r) {
+                a[r] = an[r];
+                if (HILO) al[r] = aln[r];
+            }
+            if (ks + 4 < ks_chunk) loadA(ks + 4);
+            VT b[FB], bl[FB];
+#pragma unroll
+            for (int j = 0; j < FB; ++j) {
+                const T* bp = xs + (j * 16 + (lane & 15)) * ldx + ks * KS + EPL * (lane >> 4);
+                b[j] = *reinterpret_cast<const VT*>(bp);
+                if (HILO) bl[j] = *reinterpret_cast<const VT*>(bp + NF * ldx);
+            }
+#pragma unroll
+            for (int r = 0; r < NRB; ++r)
+                if (r < nrb)
+#pragma unroll
+                    for (int j = 0; j < FB; ++j) {
+                        acc[r][j] = mfma(a[r], b[j], acc[r][j]);
+                        if (HILO) {
+                            acc[r][j] = mfma(a[r], bl[j], acc[r][j]);
+                            acc[r][j] = mfma(al[r], b[j], acc[r][j]);
+                        }
+                    }
+        }
+    }
+    // add the four waves' partial sums through LDS
+    __syncthreads();
+    f4* red = reinterpret_cast<f4*>(smem);
+    for (int w = 1; w < 4; ++w) {
+        if (wave == w)
+#pragma unroll
+            for (int r = 0; r < NRB; ++r)
+#pragma unroll
+                for (int j = 0; j < FB; ++j) red[(r * FB + j) * 64 + lane] = acc[r][j];
+        __syncthreads();
+        if (wave == 0)
+#pragma unroll
+            for (int r = 0; r < NRB; ++r)
+#pragma unroll
+                for (int j = 0; j < FB; ++j) acc[r][j] += red[(r * FB + j) * 64 + lane];
+        __syncthreads();
+    }
+    if (wave != 0) return;
+    // D layout: lane holds rows 4*(lane/16) + e of column lane%16
+#pragma unroll
+    for (int j = 0; j < FB; ++j) {
+        const int64_t fpos = f0 + j * 16 + (lane & 15);
+        if (fpos >= n) continue;
+        float* zp = zpart + (int64_t)blockIdx.y * zstride + fpos * Rp;
+#pragma unroll
+        for (int r = 0; r < NRB; ++r)
+            if (r < nrb) *reinterpret_cast<f4*>(zp + (rbs + r) * 16 + 4 * (lane >> 4)) = acc[r][j];
+    }
+}
+
+// ------------------------------------------------------------------ Z prep
+// One wave per frame: z = sum of the split partials (FP32), ||z||, and the
+// GEMM2 operand copy in T (FP16: scaled by 2^e so that max |z| lies in
+// [2^13, 2^14)), in B-operand fragment order [frame/16][k-step][lane][EPL].
+template <typename T>
+__global__ __launch_bounds__(256) void k_zprep(const float* __restrict__ zpart, int nsplit, int64_t zstride,
+                                               int64_t nfr, const int* __restrict__ fcount, int Rp,
+                                               float* __restrict__ z32, T* __restrict__ zfrag,
+                                               float* __restrict__ zscale, float* __restrict__ znorm, int scale16) {
+    constexpr int KS = Mf<T>::KSTEP, EPL = Mf<T>::EPL;
+    const int64_t n = fcount ? (int64_t)*fcount : nfr;
+    const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (f >= n) return;
+    float mx = 0.f, ss = 0.f;
+    for (int r = lane; r < Rp; r += 64) {
+        float v = 0.f;
+        for (int s = 0; s < nsplit; ++s) v += zpart[(int64_t)s * zstride + f * Rp + r];
+        z32[f * Rp + r] = v;
+        mx = fmaxf(mx, fabsf(v));
+        ss += v * v;
+    }
+    mx = wave_max(mx);
+    ss = wave_sum(ss);
+    float sc = 1.f;
+    if (scale16 && mx > 0.f) {
+        int e;
+        frexpf(mx, &e);
+        sc = ldexpf(1.f, 14 - e);
+    }
+    if (lane == 0) {
+        if (zscale) zscale[f] = sc;
+        znorm[f] = sqrtf(ss);
+    }
+    if (zfrag) {
+        const int64_t fb = f >> 4;
+        const int nn = (int)(f & 15);
+        const int KSn = Rp / KS;
+        for (int r = lane; r < Rp; r += 64) {
+            const float v = z32[f * Rp + r] * sc;
+            const int ks = r / KS, kin = r % KS;
+            zfrag[((fb * KSn + ks) * 64 + nn + 16 * (kin / EPL)) * EPL + kin % EPL] = cvt<T>(v);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ GEMM2
+// Wave = one tile of 64 scored directions; workgroup = 4 tiles x a range of
+// FCH frames.  With UREG the wave keeps the tile's U fragments (KSN k-steps)
+// in registers and streams the frames 16 at a time; the epilogue writes one
+// maximum per (frame, tile), frame-major: pmax[f * ntile + tile].
+template <typename T, int KSN, bool UREG>
+__global__ __launch_bounds__(256) void k_gemm2(const T* __restrict__ U, int KSn, const T* __restrict__ zfrag,
+                                               int64_t nfr, int fch, int ncls, int ntile,
+                                               const float* __restrict__ zscale, float uinv,
+                                               float* __restrict__ pmax, float* __restrict__ ycls, int64_t yld) {
+    constexpr int EPL = Mf<T>::EPL;
+    typedef typename Vec<T>::t VT;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * 4 + wave;
+    if (tile >= ntile) return;
+    const int rb0 = tile * 4;
+    const int64_t fbeg = (int64_t)blockIdx.y * fch;
+    const int64_t fend = min<int64_t>(nfr, fbeg + fch);
+    VT a[4][UREG ? KSN : 1];
+    if (UREG) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int ks = 0; ks < KSN; ++ks)
+                if (ks < KSn)
+                    a[i][ks] = *reinterpret_cast<const VT*>(U + (((int64_t)(rb0 + i) * KSn + ks) * 64 + lane) * EPL);
+    }
+    bool rowok[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rowok[i][e] = (rb0 + i) * 16 + 4 * (lane >> 4) + e < ncls;
+
+    for (int64_t fb = fbeg >> 4; fb * 16 < fend; ++fb) {
+        f4 acc[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
+        const T* zb = zfrag + (fb * KSn * 64 + lane) * EPL;
+        if (UREG) {
+#pragma unroll
+            for (int ks = 0; ks < KSN; ++ks)
+                if (ks < KSn) {
+                    const VT b = *reinterpret_cast<const VT*>(zb + (int64_t)ks * 64 * EPL);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc[i] = mfma(a[i][ks], b, acc[i]);
+                }
+        } else {
+            for (int ks = 0; ks < KSn; ++ks) {
+                const VT b = *reinterpret_cast<const VT*>(zb + (int64_t)ks * 64 * EPL);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const VT ai = *reinterpret_cast<const VT*>(U + (((int64_t)(rb0 + i) * KSn + ks) * 64 + lane) * EPL);
+                    acc[i] = mfma(ai, b, acc[i]);
+                }
+            }
+        }
+        const int64_t f = fb * 16 + (lane & 15);
+        const bool live = f < fend;
+        const float inv = live ? uinv / zscale[f] : 0.f;
+        float m = -INFINITY;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (rowok[i][e]) m = fmaxf(m, acc[i][e]);
+        m = fmaxf(m, __shfl_xor(m, 16));
+        m = fmaxf(m, __shfl_xor(m, 32));
+        if (lane < 16 && live) pmax[f * ntile + tile] = m * inv;
+        if (ycls && live) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = (rb0 + i) * 16 + 4 * (lane >> 4) + e;
+                    if (row < ncls) ycls[f * yld + row] = acc[i][e] * inv;
+                }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ final
+struct FinalArgs {
+    const float2* X;
+    int M, P, B;
+    const float* pmax;      // [F][ntile]
+    int ntile, ncls;
+    const float* z32;       // [pos][Rp] z used for rescoring
+    const float* z32_first; // [F][Rp] z of the first pass (second pass only)
+    const float* znorm1;    // [F] ||z|| of the first pass
+    int Rp;
+    float ecoef;            // eps_t = kappa_t * (ecoef ||z1|| + 1.01 ||z - z1||)
+    int rescore;
+    const float* U32T;      // [ntile][Rp][64]
+    const float* tkappa;    // [ntile] max ||U_q|| in the tile
+    const float* sig;       // [Rp] singular value of each stacked row of Z
+    const int32_t* rows;    // [ncls] direction of each scored row
+    const int32_t* rep;     // [Q] class representative
+    const float* tauN;      // [Q][P] tau / N
+    int64_t nfr;
+    const int* flist;       // second pass: frames to redo
+    const int* fcount;
+    int32_t* doa;
+    float* power;
+    float* yhat;
+    float* margin;
+    float hilo_k;           // hi/lo trigger: y1 - y2 < hilo_k u ||(U_q1 - U_q2) sigma||
+    float u;                // unit roundoff of the GEMM1 operands
+    int* hlist;
+    int* hcount;
+};
+
+// One wave per frame.
+template <int MAXM, bool DEDUP>
+__global__ __launch_bounds__(256) void k_final(FinalArgs a) {
+    __shared__ float zs[4][1024];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t n = a.flist ? (int64_t)*a.fcount : a.nfr;
+    const int64_t pos = (int64_t)blockIdx.x * 4 + wave;
+    if (pos >= n) return;
+    const int64_t f = a.flist ? (int64_t)a.flist[pos] : pos;
+    const int Rp = a.Rp;
+    const float* z = a.z32 + pos * Rp;
+    float* zw = zs[wave];
+    float dz2 = 0.f;
+    for (int r = lane; r < Rp; r += 64) {
+        const float v = z[r];
+        zw[r] = v;
+        if (a.z32_first) {
+            const float d = v - a.z32_first[f * Rp + r];
+            dz2 += d * d;
+        }
+    }
+    const float ef = a.ecoef * a.znorm1[f] + (a.z32_first ? 1.01f * sqrtf(wave_sum(dz2)) : 0.f);
+    wave_sync();
+
+    // frame maximum over tiles and the tile holding it
+    const float* pm = a.pmax + f * a.ntile;
+    float ym = -INFINITY;
+    int tm = 0x7fffffff;
+    for (int t = lane; t < a.ntile; t += 64) {
+        const float v = pm[t];
+        if (better(v, t, ym, tm)) {
+            ym = v;
+            tm = t;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const float oy = __shfl_xor(ym, o);
+        const int ot = __shfl_xor(tm, o);
+        if (better(oy, ot, ym, tm)) {
+            ym = oy;
+            tm = ot;
+        }
+    }
+    if (tm < 0 || tm >= a.ntile) tm = 0;
+    const float thr = a.rescore ? ym - a.tkappa[tm] * ef : ym;
+
+    // rescore the candidate tiles in FP32: best (y1, q1, r1) and runner-up
+    float y1 = -INFINITY, y2 = -INFINITY, ncmax = -INFINITY;
+    int q1 = 0x7fffffff, q2 = 0x7fffffff, r1 = -1, r2 = -1;
+    for (int t0 = 0; t0 < a.ntile; t0 += 64) {
+        const int t = t0 + lane;
+        const float et = t < a.ntile ? (a.rescore ? a.tkappa[t] * ef : 0.f) : 0.f;
+        const float pv = t < a.ntile ? pm[t] : -INFINITY;
+        const bool cand = pv + et >= thr;
+        if (!cand) ncmax = fmaxf(ncmax, pv + et);
+        uint64_t mask = __ballot(cand);
+        while (mask) {
+            const int tt = t0 + __ffsll((unsigned long long)mask) - 1;
+            mask &= mask - 1;
+            const int row = tt * QTILE + lane;
+            const float* ut = a.U32T + (int64_t)tt * Rp * QTILE + lane;
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+            int r = 0;
+            for (; r + 4 <= Rp; r += 4) {
+                s0 = fmaf(ut[(int64_t)(r + 0) * QTILE], zw[r + 0], s0);
+                s1 = fmaf(ut[(int64_t)(r + 1) * QTILE], zw[r + 1], s1);
+                s2 = fmaf(ut[(int64_t)(r + 2) * QTILE], zw[r + 2], s2);
+                s3 = fmaf(ut[(int64_t)(r + 3) * QTILE], zw[r + 3], s3);
+            }
+            for (; r < Rp; ++r) s0 = fmaf(ut[(int64_t)r * QTILE], zw[r], s0);
+            const float y = (s0 + s1) + (s2 + s3);
+            if (row < a.ncls) {
+                const int q = a.rows[row];
+                if (better(y, q, y1, q1)) {
+                    if (DEDUP) {
+                        y2 = y1;
+                        q2 = q1;
+                        r2 = r1;
+                    }
+                    y1 = y;
+                    q1 = q;
+                    r1 = row;
+                } else if (DEDUP && better(y, q, y2, q2)) {
+                    y2 = y;
+                    q2 = q;
+                    r2 = row;
+                }
+            }
+        }
+    }
+    // wave-wide best and (scored rows being distinct classes) runner-up
+    for (int o = 32; o > 0; o >>= 1) {
+        const float oy1 = __shfl_xor(y1, o), oy2 = __shfl_xor(y2, o);
+        const int oq1 = __shfl_xor(q1, o), oq2 = __shfl_xor(q2, o);
+        const int or1 = __shfl_xor(r1, o), or2 = __shfl_xor(r2, o);
+        if (better(oy1, oq1, y1, q1)) {
+            // new best is the other lane's; runner-up is the better of mine-best and other's second
+            if (DEDUP) {
+                if (better(y1, q1, oy2, oq2)) {
+                    y2 = y1;
+                    q2 = q1;
+                    r2 = r1;
+                } else {
+                    y2 = oy2;
+                    q2 = oq2;
+                    r2 = or2;
+                }
+            }
+            y1 = oy1;
+            q1 = oq1;
+            r1 = or1;
+        } else if (DEDUP && better(oy1, oq1, y2, q2)) {
+            y2 = oy1;
+            q2 = oq1;
+            r2 = or1;
+        }
+    }
+    if (q1 < 0 || q1 == 0x7fffffff) {  // no finite candidate
+        q1 = a.rows[0];
+        r1 = 0;
+    }
+    const int cls = a.rep[q1];
+    if (!DEDUP) {
+        // runner-up over directions of other classes among the candidates
+        float sy = -INFINITY;
+        int sr = -1;
+        for (int t0 = 0; t0 < a.ntile; t0 += 64) {
+            const int t = t0 + lane;
+            const float et = t < a.ntile ? (a.rescore ? a.tkappa[t] * ef : 0.f) : 0.f;
+            const float pv = t < a.ntile ? pm[t] : -INFINITY;
+            uint64_t mask = __ballot(pv + et >= thr);
+            while (mask) {
+                const int tt = t0 + __ffsll((unsigned long long)mask) - 1;
+                mask &= mask - 1;
+                const int row = tt * QTILE + lane;
+                if (row < a.ncls && a.rep[a.rows[row]] != cls) {
+                    const float* ut = a.U32T + (int64_t)tt * Rp * QTILE + lane;
+                    float y = 0.f;
+                    for (int r = 0; r < Rp; ++r) y = fmaf(ut[(int64_t)r * QTILE], zw[r], y);
+                    if (y > sy) {
+                        sy = y;
+                        sr = row;
+                    }
+                }
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const float oy = __shfl_xor(sy, o);
+            const int orr = __shfl_xor(sr, o);
+            if (oy > sy) {
+                sy = oy;
+                sr = orr;
+            }
+        }
+        y2 = sy;
+        r2 = sr;
+    }
+    ncmax = wave_max(ncmax);
+    const float yr = fmaxf(y2, ncmax);
+    const float mg = (y1 - yr) / fmaxf(fabsf(y1), FLT_MIN);
+
+    // hi/lo trigger (first pass): GEMM1 rounding perturbs z_r by about u
+    // sigma_r (random signs), so y1 - y2 moves by about u ||(U_q1 - U_q2)
+    // sigma||; frames whose rescored gap is within hilo_k times that are redone
+    bool redo = false;
+    if (a.hlist && !a.flist) {
+        float d2 = 0.f;
+        if (r2 >= 0 && y2 >= ncmax) {
+            const float* u1 = a.U32T + (int64_t)(r1 / QTILE) * Rp * QTILE + r1 % QTILE;
+            const float* u2 = a.U32T + (int64_t)(r2 / QTILE) * Rp * QTILE + r2 % QTILE;
+            for (int r = lane; r < Rp; r += 64) {
+                const float d = (u1[(int64_t)r * QTILE] - u2[(int64_t)r * QTILE]) * a.sig[r];
+                d2 += d * d;
+            }
+            d2 = wave_sum(d2);
+        } else {
+            // runner-up not rescored: bound with the largest row difference
+            d2 = 4.f * a.sig[0] * a.sig[0];
+        }
+        redo = (y1 - yr) < a.hilo_k * a.u * sqrtf(d2);
+    }
+
+    // Algorithm 1 online step 4: power of the chosen direction from its row
+    // of W, Y = Re sum_{p,k} exp(2 pi i k tau_p / N) x_{p,k}
+    const float* tq = a.tauN + (int64_t)cls * a.P;
+    const float2* xf = a.X + f * a.M * a.B;
+    float acc = 0.f;
+    if (MAXM <= 8) {
+        // each lane takes bins b0 + lane + 64 j, j < NJ; the phase of bin
+        // b + 64 follows from that of bin b by one complex multiplication
+        constexpr int NJ = 5;
+        for (int b0 = 0; b0 < a.B; b0 += 64 * NJ) {
+            float nr[NJ][MAXM], ni[NJ][MAXM];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                for (int m = 0; m < MAXM; ++m) {
+                    const int bin = b0 + lane + 64 * j;
+                    float2 v = (bin < a.B && m < a.M) ? xf[(int64_t)m * a.B + bin] : float2{0.f, 0.f};
+                    nr[j][m] = v.x;
+                    ni[j][m] = v.y;
+                    unit(nr[j][m], ni[j][m]);
+                }
+            int p = 0;
+#pragma unroll
+            for (int i = 0; i < MAXM; ++i)
+#pragma unroll
+                for (int k = i + 1; k < MAXM; ++k)
+                    if (k < a.M) {
+                        const float tn = tq[p];
+                        float t0 = (float)(b0 + lane) * tn;
+                        t0 -= rintf(t0);
+                        float t1 = 64.f * tn;
+                        t1 -= rintf(t1);
+                        float wr = __builtin_amdgcn_cosf(t0), wi = __builtin_amdgcn_sinf(t0);
+                        const float sr = __builtin_amdgcn_cosf(t1), si = __builtin_amdgcn_sinf(t1);
+#pragma unroll
+                        for (int j = 0; j < NJ; ++j) {
+                            const float xr = nr[j][i] * nr[j][k] + ni[j][i] * ni[j][k];
+                            const float xi = ni[j][i] * nr[j][k] - nr[j][i] * ni[j][k];
+                            acc = fmaf(wr, xr, fmaf(-wi, xi, acc));
+                            const float nwr = wr * sr - wi * si;
+                            wi = wr * si + wi * sr;
+                            wr = nwr;
+                        }
+                        ++p;
+                    }
+        }
+    } else {
+        for (int bin = lane; bin < a.B; bin += 64) {
+            float re[MAXM], im[MAXM];
+#pragma unroll
+            for (int m = 0; m < MAXM; ++m) {
+                const float2 v = m < a.M ? xf[(int64_t)m * a.B + bin] : float2{0.f, 0.f};
+                re[m] = v.x;
+                im[m] = v.y;
+                unit(re[m], im[m]);
+            }
+            int p = 0;
+#pragma unroll
+            for (int i = 0; i < MAXM; ++i)
+#pragma unroll
+                for (int k = i + 1; k < MAXM; ++k)
+                    if (k < a.M) {
+                        const float xr = re[i] * re[k] + im[i] * im[k];
+                        const float xi = im[i] * re[k] - re[i] * im[k];
+                        float t = (float)bin * tq[p];
+                        t -= rintf(t);
+                        acc = fmaf(__builtin_amdgcn_cosf(t), xr, fmaf(-__builtin_amdgcn_sinf(t), xi, acc));
+                        ++p;
+                    }
+        }
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) {
+        a.doa[f] = cls;
+        a.power[f] = acc;
+        if (a.yhat) a.yhat[f] = y1;
+        if (a.margin) a.margin[f] = mg;
+        if (redo) {
+            const int k = atomicAdd(a.hcount, 1);
+            a.hlist[k] = (int)f;
+        }
+    }
+}
+
+// y_opt: every direction takes the value of its scored row
+__global__ void k_scatter_y(const float* __restrict__ ycls, int64_t yld, const int32_t* __restrict__ rowof, int Q,
+                            int64_t nfr, float* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nfr * Q) return;
+    const int64_t f = i / Q;
+    const int q = (int)(i % Q);
+    y[i] = ycls[f * yld + rowof[q]];
+}
+
+inline double unit_roundoff(int prec) {
+    return prec == P_FP32 ? std::ldexp(1.0, -24) : prec == P_FP16 ? std::ldexp(1.0, -11) : std::ldexp(1.0, -8);
+}
+
+// ------------------------------------------------------------------ launch
+template <typename T, int NF, bool HILO, int NRB>
+void launch_g1_nrb(dim3 grid, size_t lds, hipStream_t s, int M, const float2* X, int64_t F, svdphat_plan* p,
+                   int prec, const G1Layout& g, int cps, float* zpart, int64_t zstride, const int* fl,
+                   const int* fc) {
+    const int nRB = p->Rp / 16;
+    const T* A = (const T*)p->A[prec];
+    const T* Alo = (const T*)p->Alo[prec];
+    if (M <= 8)
+        k_gemm1<T, NF, NRB, 8, HILO><<<grid, 256, lds, s>>>(X, F, M, p->P, p->B, A, Alo, nRB, g.BB, g.CW, g.nch, cps,
+                                                            zpart, zstride, p->Rp, fl, fc);
+    else
+        k_gemm1<T, NF, NRB, 16, HILO><<<grid, 256, lds, s>>>(X, F, M, p->P, p->B, A, Alo, nRB, g.BB, g.CW, g.nch,
+                                                             cps, zpart, zstride, p->Rp, fl, fc);
+}
+
+template <typename T, int NF, bool HILO>
+int launch_g1(int ftiles, int nsplit, hipStream_t s, const float2* X, int64_t F, svdphat_plan* p, int prec,
+              const G1Layout& g, int cps, float* zpart, int64_t zstride, const int* fl, const int* fc) {
+    const int nRB = p->Rp / 16;
+    const int nrbw = nRB <= 12 ? nRB : 12;
+    const int NRB = nrbw <= 2 ? 2 : nrbw <= 4 ? 4 : nrbw <= 6 ? 6 : nrbw <= 8 ? 8 : nrbw <= 10 ? 10 : 12;
+    dim3 grid(ftiles, nsplit, cdiv(nRB, NRB));
+    const size_t xbytes = (size_t)(HILO ? 2 : 1) * NF * (g.CW + XPAD) * sizeof(T);
+    const size_t rbytes = (size_t)NRB * (NF / 16) * 64 * sizeof(f4);
+    const size_t lds = std::max(xbytes, rbytes);
+    switch (NRB) {
+        case 2: launch_g1_nrb<T, NF, HILO, 2>(grid, lds, s, p->M, X, F, p, prec, g, cps, zpart, zstride, fl, fc); break;
+        case 4: launch_g1_nrb<T, NF, HILO, 4>(grid, lds, s, p->M, X, F, p, prec, g, cps, zpart, zstride, fl, fc); break;
+        case 6: launch_g1_nrb<T, NF, HILO, 6>(grid, lds, s, p->M, X, F, p, prec, g, cps, zpart, zstride, fl, fc); break;
+        case 8: launch_g1_nrb<T, NF, HILO, 8>(grid, lds, s, p->M, X, F, p, prec, g, cps, zpart, zstride, fl, fc); break;
+        case 10: launch_g1_nrb<T, NF, HILO, 10>(grid, lds, s, p->M, X, F, p, prec, g, cps, zpart, zstride, fl, fc); break;
+        default: launch_g1_nrb<T, NF, HILO, 12>(grid, lds, s, p->M, X, F, p, prec, g, cps, zpart, zstride, fl, fc); break;
+    }
+    return NRB;
+}
+
+template <typename T>
+void launch_g2(svdphat_plan* p, int prec, const T* zfrag, int64_t F, const float* zsc, float* pmax, float* ycls,
+               hipStream_t s) {
+    constexpr int KS = Mf<T>::KSTEP;
+    const int KSn = p->Rp / KS;
+    const int ntile = p->ncls_pad / QTILE;
+    const int fch = 256;
+    dim3 grid(cdiv(ntile, 4), (unsigned)((F + fch - 1) / fch));
+    const float uinv = 1.f / p->uscale[prec];
+    const T* U = (const T*)p->Ufr[prec];
+    // U fragments of the tile stay in registers when they fit (<= 96 VGPRs)
+    constexpr int KREG = sizeof(T) == 4 ? 24 : 6;
+    if (KSn <= KREG)
+        k_gemm2<T, KREG, true><<<grid, 256, 0, s>>>(U, KSn, zfrag, F, fch, p->ncls, ntile, zsc, uinv, pmax, ycls,
+                                                     p->ncls_pad);
+    else
+        k_gemm2<T, 1, false><<<grid, 256, 0, s>>>(U, KSn, zfrag, F, fch, p->ncls, ntile, zsc, uinv, pmax, ycls,
+                                                   p->ncls_pad);
+}
+
+void launch_final(const FinalArgs& fa, int M, bool dedup, int64_t nwaves, hipStream_t s) {
+    dim3 grid((unsigned)((nwaves + 3) / 4));
+    if (M <= 8) {
+        if (dedup) k_final<8, true><<<grid, 256, 0, s>>>(fa);
+        else k_final<8, false><<<grid, 256, 0, s>>>(fa);
+    } else {
+        if (dedup) k_final<16, true><<<grid, 256, 0, s>>>(fa);
+        else k_final<16, false><<<grid, 256, 0, s>>>(fa);
+    }
+}
+
+template <typename T>
+void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t mode, int32_t* doa, float* power,
+                float* yhat, float* margin, float* y_opt, hipStream_t s) {
+    const G1Layout& g = p->g1[prec];
+    const int Rp = p->Rp, nRB = Rp / 16;
+    const int ntile = p->ncls_pad / QTILE;
+    const int64_t Fc = round_up64(F, 64);
+    const int ftiles = (int)(Fc / 64);
+    const int nrg = cdiv(nRB, 12);
+    int nsplit = std::max(1, std::min(std::min(g.nch, 8), cdiv(1024, ftiles * nrg)));
+    const int cps = cdiv(g.nch, nsplit);
+    nsplit = cdiv(g.nch, cps);
+    const bool hilo = (mode & SVDPHAT_HILO) && prec != P_FP32;
+    // the hi/lo pass covers few frames: more splits keep the grid busy
+    int hsplit = g.nch, hcps = 1;
+
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += round_up64((int64_t)bytes, 256);
+        return o;
+    };
+    const int maxsplit = std::max(nsplit, hilo ? hsplit : 1);
+    const size_t o_zpart = take(sizeof(float) * maxsplit * Fc * Rp);
+    const size_t o_z32 = take(sizeof(float) * Fc * Rp);
+    const size_t o_z32h = hilo ? take(sizeof(float) * Fc * Rp) : 0;
+    const size_t o_zfrag = take(sizeof(T) * Fc * Rp);
+    const size_t o_zsc = take(sizeof(float) * Fc);
+    const size_t o_zn = take(sizeof(float) * Fc);
+    const size_t o_znh = hilo ? take(sizeof(float) * Fc) : 0;
+    const size_t o_pmax = take(sizeof(float) * ntile * Fc);
+    const size_t o_hl = hilo ? take(sizeof(int) * Fc) : 0;
+    const size_t o_hc = hilo ? take(sizeof(int) * 64) : 0;
+    const size_t o_y = y_opt ? take(sizeof(float) * Fc * p->ncls_pad) : 0;
+    char* w = (char*)ws_get(p, s, off);
+    float* zpart = (float*)(w + o_zpart);
+    float* z32 = (float*)(w + o_z32);
+    T* zfrag = (T*)(w + o_zfrag);
+    float* zsc = (float*)(w + o_zsc);
+    float* zn = (float*)(w + o_zn);
+    float* pmax = (float*)(w + o_pmax);
+    float* ycls = y_opt ? (float*)(w + o_y) : nullptr;
+    int* hl = hilo ? (int*)(w + o_hl) : nullptr;
+    int* hc = hilo ? (int*)(w + o_hc) : nullptr;
+    // the GEMM2 operand's padding frames must read as zero
+    if (Fc != F) SP_HIP(hipMemsetAsync(zfrag + F * Rp, 0, sizeof(T) * (Fc - F) * Rp, s));
+    if (hilo) SP_HIP(hipMemsetAsync(hc, 0, sizeof(int), s));
+
+    const int64_t zstride = Fc * Rp;
+    KernelTimer kt(s);
+    kt.begin("gemm1");
+    launch_g1<T, 64, false>(ftiles, nsplit, s, X, F, p, prec, g, cps, zpart, zstride, nullptr, nullptr);
+    SP_HIP(hipGetLastError());
+    kt.end();
+    kt.begin("zprep");
+    k_zprep<T><<<dim3((unsigned)(Fc / 4)), 256, 0, s>>>(zpart, nsplit, zstride, F, nullptr, Rp, z32, zfrag, zsc, zn,
+                                                        prec == P_FP16 ? 1 : 0);
+    SP_HIP(hipGetLastError());
+    kt.end();
+    kt.begin("gemm2");
+    launch_g2<T>(p, prec, zfrag, F, zsc, pmax, ycls, s);
+    SP_HIP(hipGetLastError());
+    kt.end();
+    if (y_opt) {
+        kt.begin("scatter_y");
+        const int64_t tot = F * p->Q;
+        k_scatter_y<<<dim3((unsigned)((tot + 255) / 256)), 256, 0, s>>>(ycls, p->ncls_pad, p->d_rowof, p->Q, F, y_opt);
+        SP_HIP(hipGetLastError());
+        kt.end();
+    }
+    // eps of a tile = kappa_t (2u + u^2 + 2 Rp 2^-24) ||z|| bounds |y_lowprec -
+    // y_fp32| for its rows (operand rounding of U and z, FP32 accumulation of
+    // both products; Cauchy-Schwarz with the tile's largest ||U_q||)
+    const double u = unit_roundoff(prec);
+    const double accum = 2.0 * Rp * std::ldexp(1.0, -24);
+    const double lin = prec == P_FP32 ? accum : (2.0 * u + u * u + accum);
+    FinalArgs fa{};
+    fa.X = X;
+    fa.M = p->M;
+    fa.P = p->P;
+    fa.B = p->B;
+    fa.pmax = pmax;
+    fa.ntile = ntile;
+    fa.ncls = p->ncls;
+    fa.z32 = z32;
+    fa.z32_first = nullptr;
+    fa.znorm1 = zn;
+    fa.Rp = Rp;
+    fa.ecoef = (float)(lin * 1.01);
+    fa.rescore = (mode & SVDPHAT_RESCORE) ? 1 : 0;
+    fa.U32T = p->U32T;
+    fa.tkappa = p->d_tkappa;
+    fa.sig = p->d_sig;
+    fa.rows = p->d_rows;
+    fa.rep = p->d_rep;
+    fa.tauN = p->d_tauN_all;
+    fa.nfr = F;
+    fa.doa = doa;
+    fa.power = power;
+    fa.yhat = yhat;
+    fa.margin = margin;
+    fa.hilo_k = 4.f;
+    fa.u = (float)u;
+    fa.hlist = hl;
+    fa.hcount = hc;
+    const bool dedup = !(p->flags & SVDPHAT_NO_DEDUP);
+    kt.begin("final");
+    launch_final(fa, p->M, dedup, F, s);
+    SP_HIP(hipGetLastError());
+    kt.end();
+    if (hilo) {
+        float* z32h = (float*)(w + o_z32h);
+        float* znh = (float*)(w + o_znh);
+        kt.begin("gemm1_hilo");
+        launch_g1<T, 32, true>((int)(Fc / 32), hsplit, s, X, F, p, prec, g, hcps, zpart, zstride, hl, hc);
+        SP_HIP(hipGetLastError());
+        kt.end();
+        kt.begin("zprep_hilo");
+        k_zprep<T><<<dim3((unsigned)(Fc / 4)), 256, 0, s>>>(zpart, hsplit, zstride, F, hc, Rp, z32h, nullptr, nullptr,
+                                                            znh, 0);
+        SP_HIP(hipGetLastError());
+        kt.end();
+        FinalArgs fb = fa;
+        fb.z32 = z32h;
+        fb.z32_first = z32;
+        fb.flist = hl;
+        fb.fcount = hc;
+        fb.hlist = nullptr;
+        kt.begin("final_hilo");
+        launch_final(fb, p->M, dedup, F, s);
+        SP_HIP(hipGetLastError());
+        kt.end();
+    }
+    kt.flush();
+}
+
+}  // namespace
+
+void launch_locate(svdphat_plan* p, const void* X, int64_t F, int prec, uint32_t mode, int32_t* doa, float* power,
+                   float* yhat, float* margin, float* y_opt, hipStream_t s) {
+    const float2* x = (const float2*)X;
+    if (prec == P_FP32) run_locate<float>(p, x, F, prec, mode, doa, power, yhat, margin, y_opt, s);
+    else if (prec == P_FP16) run_locate<_Float16>(p, x, F, prec, mode, doa, power, yhat, margin, y_opt, s);
+    else run_locate<__bf16>(p, x, F, prec, mode, doa, power, yhat, margin, y_opt, s);
+}
+
+}  // namespace svdphat
