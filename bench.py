@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--srp-steps", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="first run one plain device copy of this many MB (a known-size reference "
+                         "for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the frames of a batch are "
@@ -93,6 +96,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     amd.lib()
+    if args.calib_copy_mb:
+        n = args.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = synth.workload("planar_q10242", frames=args.frames)
     F = w["X"].shape[0]
     t0 = time.perf_counter()
@@ -144,12 +154,19 @@ def main():
     amd.svdphat_timing_enable(False)
     kt = amd.svdphat_timing_read()
     amd.svdphat_timing_reset()
+    # event counts in a pass of their own (their atomics would skew the timing)
+    amd.svdphat_timing_enable(False, counts=True)
+    amd.svdphat_locate(h, X, prec, mode, doa, power, yhat, margin)
+    amd.svdphat_timing_enable(False)
+    kc = amd.svdphat_timing_read()
+    amd.svdphat_timing_reset()
     amd.svdphat_timing_enable(True)
     for _ in range(args.srp_steps):
         amd.svdphat_srp_locate(h, X, doa, power)
     amd.svdphat_timing_enable(False)
     kt_srp = amd.svdphat_timing_read()
     torch.cuda.synchronize()
+    counts = {k[6:]: v[0] / max(v[1], 1) for k, v in kc.items() if k.startswith("count:")}
     kernels = {k: dict(avg_us=1e3 * v[0] / v[1], launches=v[1]) for k, v in kt.items()}
     kernels_srp = {k: dict(avg_us=1e3 * v[0] / v[1], launches=v[1]) for k, v in kt_srp.items()}
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
@@ -217,6 +234,7 @@ def main():
         "argmax_match": acc,
         "kernels_us": kernels,
         "kernels_srp_us": kernels_srp,
+        "per_frame_counts": counts,
         "plan_build_s": plan_s,
     }
     if cpu is not None:

@@ -167,12 +167,18 @@ int svdphat_sync(void* stream);
 
 /*
  * Per-kernel timing (instrumentation, not part of the method).
- * svdphat_timing_enable(1) brackets every kernel that the library launches
- * with HIP events on the launch's stream; each call then waits for its own
- * events before returning and adds the elapsed time to a process-wide table
- * keyed by kernel name.  svdphat_timing_read returns entry `index` (0-based,
+ * svdphat_timing_enable(enable): bit 0 brackets every kernel that the
+ * library launches with HIP events on the launch's stream; each call then
+ * waits for its own events before returning and adds the elapsed time to a
+ * process-wide table keyed by kernel name.  Bit 1 makes the search kernels
+ * count events (atomic counters, which slow them; keep it apart from
+ * timing).  svdphat_timing_read returns entry `index` (0-based,
  * names in lexicographic order): name (NUL-terminated, truncated to
  * name_len), total milliseconds and launch count; E_INVAL past the last entry.
+ * Entries named "count:*" hold event counts in place of milliseconds and
+ * the number of frames they were counted over in place of launches
+ * ("count:final_tiles_rescored": direction tiles rescored in FP32;
+ * "count:frames_hilo": frames recomputed with the hi/lo product).
  * svdphat_timing_reset clears the table.
  */
 int svdphat_timing_enable(int enable);

@@ -152,8 +152,9 @@ def svdphat_sync(stream=None):
     _check(lib().svdphat_sync(_stream(stream)))
 
 
-def svdphat_timing_enable(enable: bool):
-    _check(lib().svdphat_timing_enable(1 if enable else 0))
+def svdphat_timing_enable(enable, counts: bool = False):
+    """enable: kernel timing on/off; counts: event counters (not with timing)."""
+    _check(lib().svdphat_timing_enable((1 if enable else 0) | (2 if counts else 0)))
 
 
 def svdphat_timing_reset():

@@ -89,6 +89,7 @@ namespace {
 struct TimingTable {
     std::mutex mu;
     bool on = false;
+    bool counts = false;
     std::map<std::string, std::pair<double, int64_t>> t;
 };
 TimingTable& timing() {
@@ -98,6 +99,14 @@ TimingTable& timing() {
 }  // namespace
 
 bool timing_on() { return timing().on; }
+bool counting_on() { return timing().counts; }
+
+void timing_count(const char* name, double count, int64_t calls) {
+    std::lock_guard<std::mutex> lk(timing().mu);
+    auto& e = timing().t[name];
+    e.first += count;
+    e.second += calls;
+}
 
 void KernelTimer::begin(const char* name) {
     if (!timing_on()) return;
@@ -263,7 +272,8 @@ void svdphat_plan_destroy(svdphat_plan* p) { free_plan(p); }
 int svdphat_timing_enable(int enable) {
     return guarded([&] {
         std::lock_guard<std::mutex> lk(timing().mu);
-        timing().on = enable != 0;
+        timing().on = (enable & 1) != 0;
+        timing().counts = (enable & 2) != 0;
     });
 }
 

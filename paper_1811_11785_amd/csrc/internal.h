@@ -66,6 +66,9 @@ constexpr int QTILE = 64;
 // Layout of the stacked-real GEMM1 operand for one element type: the
 // reduction axis (bins x pairs x {re, im}, bin-major) is cut into chunks of
 // BB bins; chunk width CW = round_up(BB * 2P, KSTEP) stacked values.
+// Chunks of BB bins must fit the GEMM1 workgroup's item budget: 64 frames x
+// BB <= 256 x (3 items per thread for M <= 8, 1 for M <= 16).
+constexpr int G1_MAX_ITEMS8 = 768, G1_MAX_ITEMS16 = 256;
 struct G1Layout {
     int BB = 0;       // bins per chunk
     int CW = 0;       // stacked values per chunk (padded)
@@ -136,6 +139,9 @@ void* ws_get(svdphat_plan* p, hipStream_t s, size_t bytes);
 // bracketed by HIP events on its stream; `flush` waits for them and adds the
 // elapsed times to a process-wide table keyed by kernel name.
 bool timing_on();
+bool counting_on();
+// adds an event count to the timing table (entries named count:*)
+void timing_count(const char* name, double count, int64_t calls);
 struct KernelTimer {
     struct Rec {
         const char* name;

@@ -76,20 +76,22 @@ float from_t(T v) { return (float)v; }
 // Chunk layout of the GEMM1 reduction axis for one element type.  The x
 // tile of 64 frames x CW values must fit in 64 KB of LDS; among the bin
 // counts that fit, prefer little padding, then bigger chunks.
-G1Layout make_layout(int P, int B, int esize, int kstep, int nRB, int epl) {
+G1Layout make_layout(int P, int B, int M, int esize, int kstep, int nRB, int epl) {
     G1Layout g;
     const int budget = 65536 / (64 * esize) - 8;  // CW + pad per frame row
-    double best = 1e9;
-    for (int bb = 1; bb <= B; ++bb) {
-        int cw = round_up(bb * 2 * P, kstep);
+    const int max_bb = (M <= 8 ? G1_MAX_ITEMS8 : G1_MAX_ITEMS16) / 64;
+    double best = -1.0;
+    for (int bb = 1; bb <= std::min(B, max_bb); ++bb) {
+        const int cw = round_up(bb * 2 * P, kstep);
         if (cw > budget) break;
-        double waste = 1.0 - (double)(bb * 2 * P) / cw;
-        // last-chunk padding also counts
-        int nch = cdiv(B, bb);
-        double tail = (double)(nch * bb - B) / (nch * bb);
-        double score = waste + tail + 0.02 / bb;
-        if (score < best) {
-            best = score;
+        const int ks = cw / kstep;
+        const int nch = cdiv(B, bb);
+        // useful fraction of the chunk, of the last chunk, of the four waves'
+        // round-robin k-steps, and a per-chunk overhead of about one k-step
+        const double eff = (double)(bb * 2 * P) / cw * (double)B / (nch * bb) * (double)ks / (4 * cdiv(ks, 4)) *
+                           (double)ks / (ks + 4);
+        if (eff > best) {
+            best = eff;
             g.BB = bb;
             g.CW = cw;
         }
@@ -98,7 +100,6 @@ G1Layout make_layout(int P, int B, int esize, int kstep, int nRB, int epl) {
     g.nch = cdiv(B, g.BB);
     g.ks_chunk = g.CW / kstep;
     g.elems = (int64_t)g.nch * g.ks_chunk * nRB * 64 * epl;
-    (void)epl;
     return g;
 }
 
@@ -396,9 +397,9 @@ void build_plan(svdphat_plan* p, const double* mics, const double* grid) {
     p->Rp = round_up(p->R, 32);
     if (p->Rp > 1024) fail(SVDPHAT_E_UNSUPPORTED, "rank K above 512 is not supported");
     const int nRB = p->Rp / 16;
-    p->g1[P_FP32] = make_layout(P, B, 4, Mf<float>::KSTEP, nRB, Mf<float>::EPL);
-    p->g1[P_FP16] = make_layout(P, B, 2, Mf<_Float16>::KSTEP, nRB, Mf<_Float16>::EPL);
-    p->g1[P_BF16] = make_layout(P, B, 2, Mf<__bf16>::KSTEP, nRB, Mf<__bf16>::EPL);
+    p->g1[P_FP32] = make_layout(P, B, M, 4, Mf<float>::KSTEP, nRB, Mf<float>::EPL);
+    p->g1[P_FP16] = make_layout(P, B, M, 2, Mf<_Float16>::KSTEP, nRB, Mf<_Float16>::EPL);
+    p->g1[P_BF16] = make_layout(P, B, M, 2, Mf<__bf16>::KSTEP, nRB, Mf<__bf16>::EPL);
     int64_t bytes = 0;
     {
         std::vector<float> a32, dummy;

@@ -19,11 +19,15 @@
 //             modelled GEMM1 rounding are queued for a hi/lo recomputation.
 #include "device.h"
 
+#include <type_traits>
+
 namespace svdphat {
 
 namespace {
 
 constexpr int XPAD = 8;  // LDS row padding (elements) of the x tile
+constexpr int G1_IPT8 = 3;   // chunk items per thread, arrays of up to 8 microphones
+constexpr int G1_IPT16 = 1;  // and of up to 16
 
 // ------------------------------------------------------------------ GEMM1
 // Workgroup: 4 waves, NF frames, NRB row blocks of Z (row group blockIdx.z),
@@ -33,7 +37,7 @@ constexpr int XPAD = 8;  // LDS row padding (elements) of the x tile
 // and stored as (Re, Im) pairs), then the chunk's k-steps are shared out
 // round-robin to the waves; each wave accumulates all NRB x NF/16 output
 // blocks.  The four partial sums are added through LDS at the end.
-template <typename T, int NF, int NRB, int MAXM, bool HILO>
+template <typename T, int NF, int NRB, int MAXM, int IPT, bool HILO>
 __global__ __launch_bounds__(256) void k_gemm1(const float2* __restrict__ X, int64_t nfr, int M, int P, int B,
                                                const T* __restrict__ A, const T* __restrict__ Alo, int nRB, int BB,
                                                int CW, int nch, int cps, float* __restrict__ zpart, int64_t zstride,
@@ -68,25 +72,70 @@ __global__ __launch_bounds__(256) void k_gemm1(const float2* __restrict__ X, int
 #pragma unroll
         for (int j = 0; j < FB; ++j) acc[r][j] = f4{0.f, 0.f, 0.f, 0.f};
 
+    // STFT values of the next chunk are loaded into registers before the
+    // current chunk's MFMA phase, so their latency hides behind it.  Item
+    // it = (frame it / BB, bin it % BB); at most IPT items per thread; the
+    // item's frame and base address do not change from chunk to chunk.
+    float2 xv[IPT][MAXM];
+    const float2* xbase[IPT];
+    int bofs[IPT];
+    bool ilive[IPT];
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const int it = threadIdx.x + 256 * k;
+        const int fl = it / BB, bl = it - (it / BB) * BB;
+        const int64_t fpos = f0 + fl;
+        ilive[k] = it < NF * BB && fpos < n;
+        const int64_t f = ilive[k] ? (flist ? (int64_t)flist[fpos] : fpos) : 0;
+        xbase[k] = X + f * M * B + bl;
+        bofs[k] = bl;
+    }
+    auto fetch = [&](int ch) {
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            const bool live = ilive[k] && ch * BB + bofs[k] < B;
+            const float2* xf = xbase[k] + ch * BB;
+#pragma unroll
+            for (int m = 0; m < MAXM; ++m) xv[k][m] = (live && m < M) ? xf[(int64_t)m * B] : float2{0.f, 0.f};
+        }
+    };
+    fetch(c0);
     for (int ch = c0; ch < c1; ++ch) {
         __syncthreads();
-        for (int it = threadIdx.x; it < NF * BB; it += 256) {
-            const int fl = it / BB, bl = it - (it / BB) * BB;
-            const int64_t fpos = f0 + fl;
-            const int bin = ch * BB + bl;
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            const int it = threadIdx.x + 256 * k;
+            if (it >= NF * BB) break;
+            const int fl = it / BB, bl = bofs[k];
             VP* dst = reinterpret_cast<VP*>(xs + fl * ldx + bl * twoP);
             VP* dlo = reinterpret_cast<VP*>(xl + fl * ldx + bl * twoP);
-            if (fpos < n && bin < B) {
-                const int64_t f = flist ? (int64_t)flist[fpos] : fpos;
-                const float2* xf = X + f * M * B + bin;
-                float re[MAXM], im[MAXM];
+            float re[MAXM], im[MAXM];
+#pragma unroll
+            for (int m = 0; m < MAXM; ++m) {
+                re[m] = xv[k][m].x;
+                im[m] = xv[k][m].y;
+                unit(re[m], im[m]);
+            }
+            if constexpr (std::is_same<T, _Float16>::value && !HILO) {
+                // FP16 operands: the pair products are formed in packed f16,
+                // (Re, Im) = (re_i, im_i) re_j + (im_i, -re_i) im_j
+                h2 a[MAXM], c[MAXM];
 #pragma unroll
                 for (int m = 0; m < MAXM; ++m) {
-                    const float2 v = m < M ? xf[(int64_t)m * B] : float2{0.f, 0.f};
-                    re[m] = v.x;
-                    im[m] = v.y;
-                    unit(re[m], im[m]);
+                    a[m] = h2{(_Float16)re[m], (_Float16)im[m]};
+                    c[m] = h2{(_Float16)im[m], (_Float16)(-re[m])};
                 }
+                int p = 0;
+#pragma unroll
+                for (int i = 0; i < MAXM; ++i)
+#pragma unroll
+                    for (int j = i + 1; j < MAXM; ++j)
+                        if (j < M) {
+                            const h2 rj = h2{a[j].x, a[j].x}, ij = h2{a[j].y, a[j].y};
+                            dst[p] = a[i] * rj + c[i] * ij;
+                            ++p;
+                        }
+            } else {
                 int p = 0;
 #pragma unroll
                 for (int i = 0; i < MAXM; ++i)
@@ -100,14 +149,10 @@ __global__ __launch_bounds__(256) void k_gemm1(const float2* __restrict__ X, int
                             if (HILO) dlo[p] = mkpair<T>(cvt<T>(xr - (float)hr), cvt<T>(xi - (float)hi));
                             ++p;
                         }
-            } else {
-                for (int k = 0; k < P; ++k) {
-                    dst[k] = mkpair<T>(cvt<T>(0.f), cvt<T>(0.f));
-                    if (HILO) dlo[k] = mkpair<T>(cvt<T>(0.f), cvt<T>(0.f));
-                }
             }
         }
         __syncthreads();
+        if (ch + 1 < c1) fetch(ch + 1);
         const int64_t cbase = (int64_t)ch * ks_chunk * nRB;
         VT an[NRB], aln[NRB];
         auto loadA = [&](int ks) {
@@ -227,13 +272,15 @@ __global__ __launch_bounds__(256) void k_zprep(const float* __restrict__ zpart, 
 // ------------------------------------------------------------------ GEMM2
 // Wave = one tile of 64 scored directions; workgroup = 4 tiles x a range of
 // FCH frames.  With UREG the wave keeps the tile's U fragments (KSN k-steps)
-// in registers and streams the frames 16 at a time; the epilogue writes one
-// maximum per (frame, tile), frame-major: pmax[f * ntile + tile].
+// in registers and streams the frames 16 at a time (the next frames' Z
+// fragments are loaded during the current MFMAs); the epilogue writes one
+// maximum per (frame, tile), tile-major: pmax[tile * pstride + f].
 template <typename T, int KSN, bool UREG>
 __global__ __launch_bounds__(256) void k_gemm2(const T* __restrict__ U, int KSn, const T* __restrict__ zfrag,
                                                int64_t nfr, int fch, int ncls, int ntile,
                                                const float* __restrict__ zscale, float uinv,
-                                               float* __restrict__ pmax, float* __restrict__ ycls, int64_t yld) {
+                                               float* __restrict__ pmax, int64_t pstride, float* __restrict__ ycls,
+                                               int64_t yld) {
     constexpr int EPL = Mf<T>::EPL;
     typedef typename Vec<T>::t VT;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -257,20 +304,30 @@ __global__ __launch_bounds__(256) void k_gemm2(const T* __restrict__ U, int KSn,
 #pragma unroll
         for (int e = 0; e < 4; ++e) rowok[i][e] = (rb0 + i) * 16 + 4 * (lane >> 4) + e < ncls;
 
+    VT bn[UREG ? KSN : 1];
+    auto loadB = [&](int64_t fb) {
+        const T* zb = zfrag + (fb * KSn * 64 + lane) * EPL;
+#pragma unroll
+        for (int ks = 0; ks < (UREG ? KSN : 1); ++ks)
+            if (ks < KSn) bn[ks] = *reinterpret_cast<const VT*>(zb + (int64_t)ks * 64 * EPL);
+    };
+    if (UREG && fbeg < fend) loadB(fbeg >> 4);
     for (int64_t fb = fbeg >> 4; fb * 16 < fend; ++fb) {
         f4 acc[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
-        const T* zb = zfrag + (fb * KSn * 64 + lane) * EPL;
         if (UREG) {
+            VT b[KSN];
+#pragma unroll
+            for (int ks = 0; ks < KSN; ++ks) b[ks] = bn[ks];
+            if ((fb + 1) * 16 < fend) loadB(fb + 1);
 #pragma unroll
             for (int ks = 0; ks < KSN; ++ks)
-                if (ks < KSn) {
-                    const VT b = *reinterpret_cast<const VT*>(zb + (int64_t)ks * 64 * EPL);
+                if (ks < KSn)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) acc[i] = mfma(a[i][ks], b, acc[i]);
-                }
+                    for (int i = 0; i < 4; ++i) acc[i] = mfma(a[i][ks], b[ks], acc[i]);
         } else {
+            const T* zb = zfrag + (fb * KSn * 64 + lane) * EPL;
             for (int ks = 0; ks < KSn; ++ks) {
                 const VT b = *reinterpret_cast<const VT*>(zb + (int64_t)ks * 64 * EPL);
 #pragma unroll
@@ -291,7 +348,7 @@ __global__ __launch_bounds__(256) void k_gemm2(const T* __restrict__ U, int KSn,
                 if (rowok[i][e]) m = fmaxf(m, acc[i][e]);
         m = fmaxf(m, __shfl_xor(m, 16));
         m = fmaxf(m, __shfl_xor(m, 32));
-        if (lane < 16 && live) pmax[f * ntile + tile] = m * inv;
+        if (lane < 16 && live) pmax[(int64_t)tile * pstride + f] = m * inv;
         if (ycls && live) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
@@ -308,7 +365,8 @@ __global__ __launch_bounds__(256) void k_gemm2(const T* __restrict__ U, int KSn,
 struct FinalArgs {
     const float2* X;
     int M, P, B;
-    const float* pmax;      // [F][ntile]
+    const float* pmax;      // [ntile][pstride]
+    int64_t pstride;
     int ntile, ncls;
     const float* z32;       // [pos][Rp] z used for rescoring
     const float* z32_first; // [F][Rp] z of the first pass (second pass only)
@@ -333,6 +391,7 @@ struct FinalArgs {
     float u;                // unit roundoff of the GEMM1 operands
     int* hlist;
     int* hcount;
+    unsigned long long* stats;  // optional: [0] tiles rescored, [1] frames queued for hi/lo
 };
 
 // One wave per frame.
@@ -360,11 +419,12 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a) {
     wave_sync();
 
     // frame maximum over tiles and the tile holding it
-    const float* pm = a.pmax + f * a.ntile;
+    const float* pm = a.pmax + f;
+    const int64_t ps = a.pstride;
     float ym = -INFINITY;
     int tm = 0x7fffffff;
     for (int t = lane; t < a.ntile; t += 64) {
-        const float v = pm[t];
+        const float v = pm[t * ps];
         if (better(v, t, ym, tm)) {
             ym = v;
             tm = t;
@@ -384,13 +444,15 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a) {
     // rescore the candidate tiles in FP32: best (y1, q1, r1) and runner-up
     float y1 = -INFINITY, y2 = -INFINITY, ncmax = -INFINITY;
     int q1 = 0x7fffffff, q2 = 0x7fffffff, r1 = -1, r2 = -1;
+    int ncand = 0;
     for (int t0 = 0; t0 < a.ntile; t0 += 64) {
         const int t = t0 + lane;
         const float et = t < a.ntile ? (a.rescore ? a.tkappa[t] * ef : 0.f) : 0.f;
-        const float pv = t < a.ntile ? pm[t] : -INFINITY;
+        const float pv = t < a.ntile ? pm[t * ps] : -INFINITY;
         const bool cand = pv + et >= thr;
         if (!cand) ncmax = fmaxf(ncmax, pv + et);
         uint64_t mask = __ballot(cand);
+        ncand += __popcll(mask);
         while (mask) {
             const int tt = t0 + __ffsll((unsigned long long)mask) - 1;
             mask &= mask - 1;
@@ -464,7 +526,7 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a) {
         for (int t0 = 0; t0 < a.ntile; t0 += 64) {
             const int t = t0 + lane;
             const float et = t < a.ntile ? (a.rescore ? a.tkappa[t] * ef : 0.f) : 0.f;
-            const float pv = t < a.ntile ? pm[t] : -INFINITY;
+            const float pv = t < a.ntile ? pm[t * ps] : -INFINITY;
             uint64_t mask = __ballot(pv + et >= thr);
             while (mask) {
                 const int tt = t0 + __ffsll((unsigned long long)mask) - 1;
@@ -598,6 +660,10 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a) {
             const int k = atomicAdd(a.hcount, 1);
             a.hlist[k] = (int)f;
         }
+        if (a.stats) {
+            atomicAdd(a.stats, (unsigned long long)ncand);
+            if (redo) atomicAdd(a.stats + 1, 1ull);
+        }
     }
 }
 
@@ -623,12 +689,14 @@ void launch_g1_nrb(dim3 grid, size_t lds, hipStream_t s, int M, const float2* X,
     const int nRB = p->Rp / 16;
     const T* A = (const T*)p->A[prec];
     const T* Alo = (const T*)p->Alo[prec];
+    if (NF * g.BB > 256 * (M <= 8 ? G1_IPT8 : G1_IPT16))
+        fail(SVDPHAT_E_UNSUPPORTED, "GEMM1 chunk larger than the workgroup's item budget");
     if (M <= 8)
-        k_gemm1<T, NF, NRB, 8, HILO><<<grid, 256, lds, s>>>(X, F, M, p->P, p->B, A, Alo, nRB, g.BB, g.CW, g.nch, cps,
-                                                            zpart, zstride, p->Rp, fl, fc);
+        k_gemm1<T, NF, NRB, 8, G1_IPT8, HILO><<<grid, 256, lds, s>>>(X, F, M, p->P, p->B, A, Alo, nRB, g.BB, g.CW,
+                                                                     g.nch, cps, zpart, zstride, p->Rp, fl, fc);
     else
-        k_gemm1<T, NF, NRB, 16, HILO><<<grid, 256, lds, s>>>(X, F, M, p->P, p->B, A, Alo, nRB, g.BB, g.CW, g.nch,
-                                                             cps, zpart, zstride, p->Rp, fl, fc);
+        k_gemm1<T, NF, NRB, 16, G1_IPT16, HILO><<<grid, 256, lds, s>>>(X, F, M, p->P, p->B, A, Alo, nRB, g.BB, g.CW,
+                                                                       g.nch, cps, zpart, zstride, p->Rp, fl, fc);
 }
 
 template <typename T, int NF, bool HILO>
@@ -653,8 +721,8 @@ int launch_g1(int ftiles, int nsplit, hipStream_t s, const float2* X, int64_t F,
 }
 
 template <typename T>
-void launch_g2(svdphat_plan* p, int prec, const T* zfrag, int64_t F, const float* zsc, float* pmax, float* ycls,
-               hipStream_t s) {
+void launch_g2(svdphat_plan* p, int prec, const T* zfrag, int64_t F, const float* zsc, float* pmax,
+               int64_t pstride, float* ycls, hipStream_t s) {
     constexpr int KS = Mf<T>::KSTEP;
     const int KSn = p->Rp / KS;
     const int ntile = p->ncls_pad / QTILE;
@@ -665,11 +733,11 @@ void launch_g2(svdphat_plan* p, int prec, const T* zfrag, int64_t F, const float
     // U fragments of the tile stay in registers when they fit (<= 96 VGPRs)
     constexpr int KREG = sizeof(T) == 4 ? 24 : 6;
     if (KSn <= KREG)
-        k_gemm2<T, KREG, true><<<grid, 256, 0, s>>>(U, KSn, zfrag, F, fch, p->ncls, ntile, zsc, uinv, pmax, ycls,
-                                                     p->ncls_pad);
+        k_gemm2<T, KREG, true><<<grid, 256, 0, s>>>(U, KSn, zfrag, F, fch, p->ncls, ntile, zsc, uinv, pmax,
+                                                     pstride, ycls, p->ncls_pad);
     else
-        k_gemm2<T, 1, false><<<grid, 256, 0, s>>>(U, KSn, zfrag, F, fch, p->ncls, ntile, zsc, uinv, pmax, ycls,
-                                                   p->ncls_pad);
+        k_gemm2<T, 1, false><<<grid, 256, 0, s>>>(U, KSn, zfrag, F, fch, p->ncls, ntile, zsc, uinv, pmax, pstride,
+                                                   ycls, p->ncls_pad);
 }
 
 void launch_final(const FinalArgs& fa, int M, bool dedup, int64_t nwaves, hipStream_t s) {
@@ -717,7 +785,10 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     const size_t o_hl = hilo ? take(sizeof(int) * Fc) : 0;
     const size_t o_hc = hilo ? take(sizeof(int) * 64) : 0;
     const size_t o_y = y_opt ? take(sizeof(float) * Fc * p->ncls_pad) : 0;
+    const size_t o_st = take(sizeof(unsigned long long) * 4);
     char* w = (char*)ws_get(p, s, off);
+    unsigned long long* stats = counting_on() ? (unsigned long long*)(w + o_st) : nullptr;
+    if (stats) SP_HIP(hipMemsetAsync(stats, 0, sizeof(unsigned long long) * 4, s));
     float* zpart = (float*)(w + o_zpart);
     float* z32 = (float*)(w + o_z32);
     T* zfrag = (T*)(w + o_zfrag);
@@ -743,7 +814,7 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     SP_HIP(hipGetLastError());
     kt.end();
     kt.begin("gemm2");
-    launch_g2<T>(p, prec, zfrag, F, zsc, pmax, ycls, s);
+    launch_g2<T>(p, prec, zfrag, F, zsc, pmax, Fc, ycls, s);
     SP_HIP(hipGetLastError());
     kt.end();
     if (y_opt) {
@@ -765,6 +836,7 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     fa.P = p->P;
     fa.B = p->B;
     fa.pmax = pmax;
+    fa.pstride = Fc;
     fa.ntile = ntile;
     fa.ncls = p->ncls;
     fa.z32 = z32;
@@ -788,6 +860,7 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     fa.u = (float)u;
     fa.hlist = hl;
     fa.hcount = hc;
+    fa.stats = stats;
     const bool dedup = !(p->flags & SVDPHAT_NO_DEDUP);
     kt.begin("final");
     launch_final(fa, p->M, dedup, F, s);
@@ -811,12 +884,20 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
         fb.flist = hl;
         fb.fcount = hc;
         fb.hlist = nullptr;
+        fb.stats = nullptr;
         kt.begin("final_hilo");
         launch_final(fb, p->M, dedup, F, s);
         SP_HIP(hipGetLastError());
         kt.end();
     }
     kt.flush();
+    if (stats) {
+        unsigned long long h[4] = {0, 0, 0, 0};
+        SP_HIP(hipMemcpyAsync(h, stats, sizeof(h), hipMemcpyDeviceToHost, s));
+        SP_HIP(hipStreamSynchronize(s));
+        timing_count("count:final_tiles_rescored", (double)h[0], F);
+        timing_count("count:frames_hilo", (double)h[1], F);
+    }
 }
 
 }  // namespace
