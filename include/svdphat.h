@@ -156,6 +156,47 @@ int svdphat_locate(svdphat_plan* plan, const void* X, int64_t F,
 int svdphat_srp_locate(svdphat_plan* plan, const void* X, int64_t F,
                        int32_t* doa, float* power, float* y_opt, void* stream);
 
+/*
+ * Ragged batches: many arrays, each with its own plan (microphones, grid,
+ * rank), located in one HIP-graph launch.  The frames of every array are
+ * independent (Section 2 omits the frame index without loss of generality),
+ * so their searches run side by side; each array follows svdphat_locate
+ * with precision SVDPHAT_FP16 and mode SVDPHAT_RESCORE.
+ *
+ * svdphat_ragged_create
+ *   plans       host array of n plans (not owned; they must outlive the batch
+ *               and be created without SVDPHAT_NO_DEDUP, on one device).
+ *   max_frames  host, n maximum frame counts (>= 1); workspace and work lists
+ *               are sized for them.
+ *   flags       SVDPHAT_RAGGED_TUNE: time candidate tile settings per array
+ *               shape (GEMM1 split, GEMM2 frames per workgroup) and keep the
+ *               fastest; otherwise use cached or default settings.
+ *   tune_cache  path of a JSON-lines cache of tuned settings keyed by GPU
+ *               architecture and shape (read, and appended when tuning), or
+ *               NULL.
+ *   Synchronous.  Errors: E_INVAL, E_UNSUPPORTED (a plan without classes),
+ *   E_NOMEM, E_DEVICE.
+ * svdphat_ragged_locate
+ *   X, doa, power  host arrays of n device pointers: STFT frames
+ *                  complex64 [F_i][M_i][N_i/2+1], int32 [F_i], f32 [F_i].
+ *   F              host, n frame counts, 0 <= F_i <= max_frames_i.
+ *   Copies the per-array descriptors and launches the graph on `stream`;
+ *   returns without waiting.
+ * svdphat_ragged_info -- how many shapes were tuned now / taken from the cache.
+ * svdphat_ragged_destroy -- NULL is a no-op.
+ */
+#define SVDPHAT_RAGGED_TUNE 0x1u
+typedef struct svdphat_ragged svdphat_ragged;
+int svdphat_ragged_create(svdphat_plan* const* plans, int32_t n,
+                          const int64_t* max_frames, uint32_t flags,
+                          const char* tune_cache, svdphat_ragged** out);
+int svdphat_ragged_locate(svdphat_ragged* ragged, const void* const* X,
+                          const int64_t* F, int32_t* const* doa,
+                          float* const* power, void* stream);
+int svdphat_ragged_info(const svdphat_ragged* ragged, int64_t* tuned,
+                        int64_t* from_cache);
+void svdphat_ragged_destroy(svdphat_ragged* ragged);
+
 /* svdphat_plan_destroy -- frees the plan and its device memory; NULL is a no-op. */
 void svdphat_plan_destroy(svdphat_plan* plan);
 

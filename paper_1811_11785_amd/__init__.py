@@ -23,6 +23,7 @@ OK, E_INVAL, E_NOMEM, E_DEVICE, E_NUMERIC, E_NODEV, E_UNSUPPORTED = 0, -1, -2, -
 KEEP_W, NO_DEDUP = 0x1, 0x2
 FP32, BF16, FP16 = 0, 1, 2
 RESCORE, HILO = 0x1, 0x2
+RAGGED_TUNE = 0x1
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16}
 
 
@@ -62,6 +63,12 @@ SIGNATURES = {
                                      C.c_void_p, C.c_void_p]),
     "svdphat_plan_destroy": (None, [C.c_void_p]),
     "svdphat_sync": (C.c_int, [C.c_void_p]),
+    "svdphat_ragged_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_int64),
+                                        C.c_uint32, C.c_char_p, C.POINTER(C.c_void_p)]),
+    "svdphat_ragged_locate": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                        C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p]),
+    "svdphat_ragged_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "svdphat_ragged_destroy": (None, [C.c_void_p]),
     "svdphat_timing_enable": (C.c_int, [C.c_int]),
     "svdphat_timing_reset": (C.c_int, []),
     "svdphat_timing_read": (C.c_int, [C.c_int32, C.c_char_p, C.c_int32, C.POINTER(C.c_double),
@@ -175,6 +182,36 @@ def svdphat_timing_read() -> dict:
     return out
 
 
+def svdphat_ragged_create(plans, max_frames, flags=0, tune_cache=None):
+    n = len(plans)
+    arr = (C.c_void_p * n)(*[p.value if isinstance(p, C.c_void_p) else p for p in plans])
+    mf = (C.c_int64 * n)(*[int(v) for v in max_frames])
+    out = C.c_void_p()
+    _check(lib().svdphat_ragged_create(arr, n, mf, int(flags),
+                                       None if tune_cache is None else str(tune_cache).encode(),
+                                       C.byref(out)))
+    return out
+
+
+def svdphat_ragged_locate(ragged, Xs, doas, powers, stream=None):
+    n = len(Xs)
+    X = (C.c_void_p * n)(*[x.data_ptr() if x.shape[0] else None for x in Xs])
+    F = (C.c_int64 * n)(*[x.shape[0] for x in Xs])
+    D = (C.c_void_p * n)(*[d.data_ptr() if d.numel() else None for d in doas])
+    P = (C.c_void_p * n)(*[p.data_ptr() if p.numel() else None for p in powers])
+    _check(lib().svdphat_ragged_locate(ragged, X, F, D, P, _stream(stream)))
+
+
+def svdphat_ragged_info(ragged):
+    t, c = C.c_int64(), C.c_int64()
+    _check(lib().svdphat_ragged_info(ragged, C.byref(t), C.byref(c)))
+    return t.value, c.value
+
+
+def svdphat_ragged_destroy(ragged):
+    lib().svdphat_ragged_destroy(ragged)
+
+
 # ------------------------------------------------------------ convenience
 class Plan:
     """Offline plan (Algorithm 1, offline) and online search on device tensors."""
@@ -227,6 +264,36 @@ class Plan:
     def close(self):
         if self._h is not None:
             svdphat_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ragged:
+    """Many plans located together in one graph launch (FP16 + rescoring)."""
+
+    def __init__(self, plans, max_frames, tune=False, tune_cache=None):
+        self.plans = list(plans)   # keep the plans alive
+        self._h = svdphat_ragged_create([p.handle for p in self.plans], max_frames,
+                                        RAGGED_TUNE if tune else 0, tune_cache)
+
+    def locate(self, Xs, stream=None):
+        import torch
+        doas = [torch.empty(x.shape[0], dtype=torch.int32, device=x.device) for x in Xs]
+        powers = [torch.empty(x.shape[0], dtype=torch.float32, device=x.device) for x in Xs]
+        svdphat_ragged_locate(self._h, Xs, doas, powers, stream)
+        return doas, powers
+
+    def info(self):
+        return svdphat_ragged_info(self._h)
+
+    def close(self):
+        if self._h is not None:
+            svdphat_ragged_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -269,6 +269,52 @@ int svdphat_srp_locate(svdphat_plan* p, const void* X, int64_t F, int32_t* doa, 
 
 void svdphat_plan_destroy(svdphat_plan* p) { free_plan(p); }
 
+int svdphat_ragged_create(svdphat_plan* const* plans, int32_t n, const int64_t* max_frames, uint32_t flags,
+                          const char* tune_cache, svdphat_ragged** out) {
+    return guarded([&] {
+        SP_REQUIRE(out != nullptr, SVDPHAT_E_INVAL, "out is NULL");
+        *out = nullptr;
+        SP_REQUIRE(plans && max_frames && n >= 1, SVDPHAT_E_INVAL, "need n >= 1 plans and their frame counts");
+        SP_REQUIRE((flags & ~(uint32_t)SVDPHAT_RAGGED_TUNE) == 0, SVDPHAT_E_INVAL, "unknown flags");
+        for (int i = 0; i < n; ++i) {
+            SP_REQUIRE(plans[i] != nullptr, SVDPHAT_E_INVAL, "NULL plan " + std::to_string(i));
+            SP_REQUIRE(max_frames[i] >= 1 && max_frames[i] < ((int64_t)1 << 31), SVDPHAT_E_INVAL,
+                       "max_frames out of range for array " + std::to_string(i));
+            SP_REQUIRE(plans[i]->device == plans[0]->device, SVDPHAT_E_INVAL, "plans on different devices");
+            SP_REQUIRE(!(plans[i]->flags & SVDPHAT_NO_DEDUP), SVDPHAT_E_UNSUPPORTED,
+                       "ragged batches need plans with one scored row per class");
+        }
+        SP_HIP(hipSetDevice(plans[0]->device));
+        svdphat_ragged* r = ragged_new(plans, n, max_frames);
+        try {
+            ragged_build(r, flags, tune_cache);
+        } catch (...) {
+            ragged_destroy(r);
+            throw;
+        }
+        *out = r;
+    });
+}
+
+int svdphat_ragged_locate(svdphat_ragged* r, const void* const* X, const int64_t* F, int32_t* const* doa,
+                          float* const* power, void* stream) {
+    return guarded([&] {
+        SP_REQUIRE(r && X && F && doa && power, SVDPHAT_E_INVAL, "NULL argument");
+        ragged_locate(r, X, F, doa, power, (hipStream_t)stream);
+    });
+}
+
+int svdphat_ragged_info(const svdphat_ragged* r, int64_t* tuned, int64_t* from_cache) {
+    return guarded([&] {
+        SP_REQUIRE(r, SVDPHAT_E_INVAL, "NULL ragged batch");
+        ragged_stats(r, tuned, from_cache);
+    });
+}
+
+void svdphat_ragged_destroy(svdphat_ragged* r) {
+    if (r) ragged_destroy(r);
+}
+
 int svdphat_timing_enable(int enable) {
     return guarded([&] {
         std::lock_guard<std::mutex> lk(timing().mu);

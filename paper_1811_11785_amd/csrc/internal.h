@@ -77,6 +77,82 @@ struct G1Layout {
     int64_t elems = 0;  // packed elements of A (all row blocks)
 };
 
+// Arguments of the per-frame search kernel (rescoring, margin, power).
+struct FinalArgs {
+    const float2* X;
+    int M, P, B;
+    const float* pmax;      // [ntile][pstride]
+    int64_t pstride;
+    int ntile, ncls;
+    const float* z32;       // [pos][Rp] z used for rescoring
+    const float* z32_first; // [F][Rp] z of the first pass (second pass only)
+    const float* znorm1;    // [F] ||z|| of the first pass
+    int Rp;
+    float ecoef;            // eps_t = kappa_t * (ecoef ||z1|| + 1.01 ||z - z1||)
+    int rescore;
+    const float* U32T;      // [ntile][Rp][64]
+    const float* tkappa;    // [ntile] max ||U_q|| in the tile
+    const float* sig;       // [Rp] singular value of each stacked row of Z
+    const int32_t* rows;    // [ncls] direction of each scored row
+    const int32_t* rep;     // [Q] class representative
+    const float* tauN;      // [Q][P] tau / N
+    int64_t nfr;
+    const int* flist;       // second pass: frames to redo
+    const int* fcount;
+    int32_t* doa;
+    float* power;
+    float* yhat;
+    float* margin;
+    float hilo_k;           // hi/lo trigger: y1 - y2 < hilo_k u ||(U_q1 - U_q2) sigma||
+    float u;                // unit roundoff of the GEMM1 operands
+    int* hlist;
+    int* hcount;
+    unsigned long long* stats;  // optional: [0] tiles rescored, [1] frames queued for hi/lo
+};
+
+// Everything the four search stages need for one array of a ragged batch
+// (device-resident; one entry per array).
+struct RDesc {
+    // GEMM1
+    const float2* X;
+    int64_t F;
+    int M, P, B;
+    const void* A;
+    int nRB, BB, CW, nch, cps, nsplit, Rp;
+    float* zpart;
+    int64_t zstride;
+    // Z prep
+    float* z32;
+    void* zfrag;
+    float* zsc;
+    float* zn;
+    // GEMM2
+    const void* U;
+    int KSn, ncls, ntile, fch;
+    float uinv;
+    float* pmax;
+    int64_t pstride;
+    // search
+    FinalArgs fin;
+};
+
+// One grouped launch: a device work list of (array, x, y, z) items run by one
+// kernel instance (template class `cls`) of stage `stage`.
+struct GroupLaunch {
+    int stage = 0;     // 0 GEMM1, 1 Z prep, 2 GEMM2, 3 search
+    int cls = 0;       // template class within the stage
+    int4* work = nullptr;
+    int nwork = 0;
+    size_t lds = 0;
+};
+void launch_grouped(const GroupLaunch& g, const RDesc* d, hipStream_t s);
+int g1_nrb_class(int nRB);
+size_t g1_lds_bytes(int NRB, int CW);
+void g1_split(const svdphat_plan* p, int64_t F, int want, int* nsplit, int* cps);
+// times one GEMM1 + Z prep (nsplit) and one GEMM2 (fch) of plan p on F
+// synthetic frames in FP16; returns microseconds
+void tune_time(svdphat_plan* p, int64_t F, int nsplit, int fch, double* us_g1, double* us_g2, hipStream_t s);
+
 struct Workspace {
     int64_t cap_frames = 0;
     void* buf = nullptr;
@@ -134,6 +210,12 @@ void launch_srp(svdphat_plan* p, const void* X, int64_t F, int32_t* doa, float* 
                 float* y_opt, hipStream_t s);
 void build_w_fp32_frags(svdphat_plan* p);
 void* ws_get(svdphat_plan* p, hipStream_t s, size_t bytes);
+svdphat_ragged* ragged_new(svdphat_plan* const* plans, int n, const int64_t* maxF);
+void ragged_build(svdphat_ragged* r, uint32_t flags, const char* cache_path);
+void ragged_locate(svdphat_ragged* r, const void* const* X, const int64_t* F, int32_t* const* doa,
+                   float* const* power, hipStream_t s);
+void ragged_destroy(svdphat_ragged* r);
+void ragged_stats(const svdphat_ragged* r, int64_t* tuned, int64_t* cached);
 
 // Per-kernel timing (instrumentation): while enabled, each launch is
 // bracketed by HIP events on its stream; `flush` waits for them and adds the

@@ -38,10 +38,11 @@ constexpr int G1_IPT16 = 1;  // and of up to 16
 // round-robin to the waves; each wave accumulates all NRB x NF/16 output
 // blocks.  The four partial sums are added through LDS at the end.
 template <typename T, int NF, int NRB, int MAXM, int IPT, bool HILO>
-__global__ __launch_bounds__(256) void k_gemm1(const float2* __restrict__ X, int64_t nfr, int M, int P, int B,
-                                               const T* __restrict__ A, const T* __restrict__ Alo, int nRB, int BB,
-                                               int CW, int nch, int cps, float* __restrict__ zpart, int64_t zstride,
-                                               int Rp, const int* __restrict__ flist, const int* __restrict__ fcount) {
+__device__ __forceinline__ void gemm1_body(int bx, int by, int bz, const float2* __restrict__ X, int64_t nfr,
+                                           int M, int P, int B, const T* __restrict__ A, const T* __restrict__ Alo,
+                                           int nRB, int BB, int CW, int nch, int cps, float* __restrict__ zpart,
+                                           int64_t zstride, int Rp, const int* __restrict__ flist,
+                                           const int* __restrict__ fcount) {
     constexpr int KS = Mf<T>::KSTEP, EPL = Mf<T>::EPL, FB = NF / 16;
     typedef typename Vec<T>::t VT;
     typedef typename Vec<T>::pair VP;
@@ -51,10 +52,10 @@ __global__ __launch_bounds__(256) void k_gemm1(const float2* __restrict__ X, int
     T* xl = xs + NF * ldx;
 
     const int64_t n = flist ? (int64_t)*fcount : nfr;
-    const int64_t f0 = (int64_t)blockIdx.x * NF;
+    const int64_t f0 = (int64_t)bx * NF;
     if (f0 >= n) return;
-    const int c0 = blockIdx.y * cps, c1 = min(nch, c0 + cps);
-    const int rbs = blockIdx.z * NRB;
+    const int c0 = by * cps, c1 = min(nch, c0 + cps);
+    const int rbs = bz * NRB;
     const int nrb = min(NRB, nRB - rbs);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ks_chunk = CW / KS;
@@ -216,11 +217,20 @@ __global__ __launch_bounds__(256) void k_gemm1(const float2* __restrict__ X, int
     for (int j = 0; j < FB; ++j) {
         const int64_t fpos = f0 + j * 16 + (lane & 15);
         if (fpos >= n) continue;
-        float* zp = zpart + (int64_t)blockIdx.y * zstride + fpos * Rp;
+        float* zp = zpart + (int64_t)by * zstride + fpos * Rp;
 #pragma unroll
         for (int r = 0; r < NRB; ++r)
             if (r < nrb) *reinterpret_cast<f4*>(zp + (rbs + r) * 16 + 4 * (lane >> 4)) = acc[r][j];
     }
+}
+
+template <typename T, int NF, int NRB, int MAXM, int IPT, bool HILO>
+__global__ __launch_bounds__(256) void k_gemm1(const float2* __restrict__ X, int64_t nfr, int M, int P, int B,
+                                               const T* __restrict__ A, const T* __restrict__ Alo, int nRB, int BB,
+                                               int CW, int nch, int cps, float* __restrict__ zpart, int64_t zstride,
+                                               int Rp, const int* __restrict__ flist, const int* __restrict__ fcount) {
+    gemm1_body<T, NF, NRB, MAXM, IPT, HILO>(blockIdx.x, blockIdx.y, blockIdx.z, X, nfr, M, P, B, A, Alo, nRB, BB, CW,
+                                            nch, cps, zpart, zstride, Rp, flist, fcount);
 }
 
 // ------------------------------------------------------------------ Z prep
@@ -228,13 +238,13 @@ __global__ __launch_bounds__(256) void k_gemm1(const float2* __restrict__ X, int
 // GEMM2 operand copy in T (FP16: scaled by 2^e so that max |z| lies in
 // [2^13, 2^14)), in B-operand fragment order [frame/16][k-step][lane][EPL].
 template <typename T>
-__global__ __launch_bounds__(256) void k_zprep(const float* __restrict__ zpart, int nsplit, int64_t zstride,
-                                               int64_t nfr, const int* __restrict__ fcount, int Rp,
-                                               float* __restrict__ z32, T* __restrict__ zfrag,
-                                               float* __restrict__ zscale, float* __restrict__ znorm, int scale16) {
+__device__ __forceinline__ void zprep_body(int bx, const float* __restrict__ zpart, int nsplit, int64_t zstride,
+                                           int64_t nfr, const int* __restrict__ fcount, int Rp,
+                                           float* __restrict__ z32, T* __restrict__ zfrag,
+                                           float* __restrict__ zscale, float* __restrict__ znorm, int scale16) {
     constexpr int KS = Mf<T>::KSTEP, EPL = Mf<T>::EPL;
     const int64_t n = fcount ? (int64_t)*fcount : nfr;
-    const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t f = (int64_t)bx * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (f >= n) return;
     float mx = 0.f, ss = 0.f;
@@ -269,6 +279,14 @@ __global__ __launch_bounds__(256) void k_zprep(const float* __restrict__ zpart, 
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_zprep(const float* __restrict__ zpart, int nsplit, int64_t zstride,
+                                               int64_t nfr, const int* __restrict__ fcount, int Rp,
+                                               float* __restrict__ z32, T* __restrict__ zfrag,
+                                               float* __restrict__ zscale, float* __restrict__ znorm, int scale16) {
+    zprep_body<T>(blockIdx.x, zpart, nsplit, zstride, nfr, fcount, Rp, z32, zfrag, zscale, znorm, scale16);
+}
+
 // ------------------------------------------------------------------ GEMM2
 // Wave = one tile of 64 scored directions; workgroup = 4 tiles x a range of
 // FCH frames.  With UREG the wave keeps the tile's U fragments (KSN k-steps)
@@ -276,18 +294,17 @@ __global__ __launch_bounds__(256) void k_zprep(const float* __restrict__ zpart, 
 // fragments are loaded during the current MFMAs); the epilogue writes one
 // maximum per (frame, tile), tile-major: pmax[tile * pstride + f].
 template <typename T, int KSN, bool UREG>
-__global__ __launch_bounds__(256) void k_gemm2(const T* __restrict__ U, int KSn, const T* __restrict__ zfrag,
-                                               int64_t nfr, int fch, int ncls, int ntile,
-                                               const float* __restrict__ zscale, float uinv,
-                                               float* __restrict__ pmax, int64_t pstride, float* __restrict__ ycls,
-                                               int64_t yld) {
+__device__ __forceinline__ void gemm2_body(int bx, int by, const T* __restrict__ U, int KSn,
+                                           const T* __restrict__ zfrag, int64_t nfr, int fch, int ncls, int ntile,
+                                           const float* __restrict__ zscale, float uinv, float* __restrict__ pmax,
+                                           int64_t pstride, float* __restrict__ ycls, int64_t yld) {
     constexpr int EPL = Mf<T>::EPL;
     typedef typename Vec<T>::t VT;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = blockIdx.x * 4 + wave;
+    const int tile = bx * 4 + wave;
     if (tile >= ntile) return;
     const int rb0 = tile * 4;
-    const int64_t fbeg = (int64_t)blockIdx.y * fch;
+    const int64_t fbeg = (int64_t)by * fch;
     const int64_t fend = min<int64_t>(nfr, fbeg + fch);
     VT a[4][UREG ? KSN : 1];
     if (UREG) {
@@ -361,46 +378,26 @@ __global__ __launch_bounds__(256) void k_gemm2(const T* __restrict__ U, int KSn,
     }
 }
 
+template <typename T, int KSN, bool UREG>
+__global__ __launch_bounds__(256) void k_gemm2(const T* __restrict__ U, int KSn, const T* __restrict__ zfrag,
+                                               int64_t nfr, int fch, int ncls, int ntile,
+                                               const float* __restrict__ zscale, float uinv,
+                                               float* __restrict__ pmax, int64_t pstride, float* __restrict__ ycls,
+                                               int64_t yld) {
+    gemm2_body<T, KSN, UREG>(blockIdx.x, blockIdx.y, U, KSn, zfrag, nfr, fch, ncls, ntile, zscale, uinv, pmax,
+                             pstride, ycls, yld);
+}
+
 // ------------------------------------------------------------------ final
-struct FinalArgs {
-    const float2* X;
-    int M, P, B;
-    const float* pmax;      // [ntile][pstride]
-    int64_t pstride;
-    int ntile, ncls;
-    const float* z32;       // [pos][Rp] z used for rescoring
-    const float* z32_first; // [F][Rp] z of the first pass (second pass only)
-    const float* znorm1;    // [F] ||z|| of the first pass
-    int Rp;
-    float ecoef;            // eps_t = kappa_t * (ecoef ||z1|| + 1.01 ||z - z1||)
-    int rescore;
-    const float* U32T;      // [ntile][Rp][64]
-    const float* tkappa;    // [ntile] max ||U_q|| in the tile
-    const float* sig;       // [Rp] singular value of each stacked row of Z
-    const int32_t* rows;    // [ncls] direction of each scored row
-    const int32_t* rep;     // [Q] class representative
-    const float* tauN;      // [Q][P] tau / N
-    int64_t nfr;
-    const int* flist;       // second pass: frames to redo
-    const int* fcount;
-    int32_t* doa;
-    float* power;
-    float* yhat;
-    float* margin;
-    float hilo_k;           // hi/lo trigger: y1 - y2 < hilo_k u ||(U_q1 - U_q2) sigma||
-    float u;                // unit roundoff of the GEMM1 operands
-    int* hlist;
-    int* hcount;
-    unsigned long long* stats;  // optional: [0] tiles rescored, [1] frames queued for hi/lo
-};
+
 
 // One wave per frame.
 template <int MAXM, bool DEDUP>
-__global__ __launch_bounds__(256) void k_final(FinalArgs a) {
+__device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
     __shared__ float zs[4][1024];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t n = a.flist ? (int64_t)*a.fcount : a.nfr;
-    const int64_t pos = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t pos = (int64_t)bx * 4 + wave;
     if (pos >= n) return;
     const int64_t f = a.flist ? (int64_t)a.flist[pos] : pos;
     const int Rp = a.Rp;
@@ -667,6 +664,58 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a) {
     }
 }
 
+template <int MAXM, bool DEDUP>
+__global__ __launch_bounds__(256) void k_final(FinalArgs a) {
+    final_body<MAXM, DEDUP>(blockIdx.x, a);
+}
+
+
+// ------------------------------------------------------------------ grouped
+// Ragged batches: one launch per stage and template class walks a device
+// work list of (array, x, y, z) items; each item runs the same body as the
+// single-plan kernel with that array's descriptor (FP16 operands).
+template <int NRB, int MAXM, int IPT>
+__global__ __launch_bounds__(256) void k_gemm1_grouped(const RDesc* __restrict__ d, const int4* __restrict__ work) {
+    const int4 w = work[blockIdx.x];
+    const RDesc& a = d[w.x];
+    gemm1_body<_Float16, 64, NRB, MAXM, IPT, false>(w.y, w.z, w.w, a.X, a.F, a.M, a.P, a.B,
+                                                    (const _Float16*)a.A, nullptr, a.nRB, a.BB, a.CW, a.nch, a.cps,
+                                                    a.zpart, a.zstride, a.Rp, nullptr, nullptr);
+}
+
+__global__ __launch_bounds__(256) void k_zprep_grouped(const RDesc* __restrict__ d, const int4* __restrict__ work) {
+    const int4 w = work[blockIdx.x];
+    const RDesc& a = d[w.x];
+    zprep_body<_Float16>(w.y, a.zpart, a.nsplit, a.zstride, a.F, nullptr, a.Rp, a.z32, (_Float16*)a.zfrag, a.zsc,
+                         a.zn, 1);
+}
+
+template <int KSN, bool UREG>
+__global__ __launch_bounds__(256) void k_gemm2_grouped(const RDesc* __restrict__ d, const int4* __restrict__ work) {
+    const int4 w = work[blockIdx.x];
+    const RDesc& a = d[w.x];
+    gemm2_body<_Float16, KSN, UREG>(w.y, w.z, (const _Float16*)a.U, a.KSn, (const _Float16*)a.zfrag, a.F, a.fch,
+                                    a.ncls, a.ntile, a.zsc, a.uinv, a.pmax, a.pstride, nullptr, 0);
+}
+
+template <int MAXM>
+__global__ __launch_bounds__(256) void k_final_grouped(const RDesc* __restrict__ d, const int4* __restrict__ work) {
+    const int4 w = work[blockIdx.x];
+    const RDesc& a = d[w.x];
+    final_body<MAXM, true>(w.y, a.fin);
+}
+
+// synthetic STFT values for the tuner (any finite values do)
+__global__ void k_fill_synth(float2* X, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t h = (uint32_t)(i * 2654435761u) ^ 0x9e3779b9u;
+    h ^= h >> 16;
+    h *= 0x7feb352du;
+    h ^= h >> 15;
+    X[i] = float2{(float)(h & 0xffff) / 32768.f - 1.f, (float)(h >> 16) / 32768.f - 1.f};
+}
+
 // y_opt: every direction takes the value of its scored row
 __global__ void k_scatter_y(const float* __restrict__ ycls, int64_t yld, const int32_t* __restrict__ rowof, int Q,
                             int64_t nfr, float* __restrict__ y) {
@@ -682,6 +731,19 @@ inline double unit_roundoff(int prec) {
 }
 
 // ------------------------------------------------------------------ launch
+
+// Split of GEMM1's reduction axis: `want` splits (0: enough workgroups for
+// about four per CU), rounded so that every split gets the same chunk count.
+void g1_split_layout(const G1Layout& g, int Rp, int64_t F, int want, int* nsplit, int* cps) {
+    const int ftiles = (int)(round_up64(F, 64) / 64);
+    const int nrg = cdiv(Rp / 16, 12);
+    int ns = want > 0 ? want : std::max(1, std::min(8, cdiv(1024, ftiles * nrg)));
+    ns = std::max(1, std::min(ns, g.nch));
+    const int c = cdiv(g.nch, ns);
+    *cps = c;
+    *nsplit = cdiv(g.nch, c);
+}
+
 template <typename T, int NF, bool HILO, int NRB>
 void launch_g1_nrb(dim3 grid, size_t lds, hipStream_t s, int M, const float2* X, int64_t F, svdphat_plan* p,
                    int prec, const G1Layout& g, int cps, float* zpart, int64_t zstride, const int* fl,
@@ -755,14 +817,12 @@ template <typename T>
 void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t mode, int32_t* doa, float* power,
                 float* yhat, float* margin, float* y_opt, hipStream_t s) {
     const G1Layout& g = p->g1[prec];
-    const int Rp = p->Rp, nRB = Rp / 16;
+    const int Rp = p->Rp;
     const int ntile = p->ncls_pad / QTILE;
     const int64_t Fc = round_up64(F, 64);
     const int ftiles = (int)(Fc / 64);
-    const int nrg = cdiv(nRB, 12);
-    int nsplit = std::max(1, std::min(std::min(g.nch, 8), cdiv(1024, ftiles * nrg)));
-    const int cps = cdiv(g.nch, nsplit);
-    nsplit = cdiv(g.nch, cps);
+    int nsplit, cps;
+    g1_split_layout(g, Rp, F, 0, &nsplit, &cps);
     const bool hilo = (mode & SVDPHAT_HILO) && prec != P_FP32;
     // the hi/lo pass covers few frames: more splits keep the grid busy
     int hsplit = g.nch, hcps = 1;
@@ -798,8 +858,8 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     float* ycls = y_opt ? (float*)(w + o_y) : nullptr;
     int* hl = hilo ? (int*)(w + o_hl) : nullptr;
     int* hc = hilo ? (int*)(w + o_hc) : nullptr;
-    // the GEMM2 operand's padding frames must read as zero
-    if (Fc != F) SP_HIP(hipMemsetAsync(zfrag + F * Rp, 0, sizeof(T) * (Fc - F) * Rp, s));
+    // (the GEMM2 operand's padding frames feed only padding columns, whose
+    // results are never written)
     if (hilo) SP_HIP(hipMemsetAsync(hc, 0, sizeof(int), s));
 
     const int64_t zstride = Fc * Rp;
@@ -901,6 +961,110 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
 }
 
 }  // namespace
+
+
+int g1_nrb_class(int nRB) {
+    const int w = nRB <= 12 ? nRB : 12;
+    return w <= 2 ? 2 : w <= 4 ? 4 : w <= 6 ? 6 : w <= 8 ? 8 : w <= 10 ? 10 : 12;
+}
+
+size_t g1_lds_bytes(int NRB, int CW) {
+    return std::max((size_t)64 * (CW + XPAD) * sizeof(_Float16), (size_t)NRB * 4 * 64 * sizeof(f4));
+}
+
+void g1_split(const svdphat_plan* p, int64_t F, int want, int* nsplit, int* cps) {
+    g1_split_layout(p->g1[P_FP16], p->Rp, F, want, nsplit, cps);
+}
+
+// Grouped launch classes: GEMM1 cls = NRB class * 2 + (M > 8); GEMM2 cls =
+// 1 if the tile's U fragments stay in registers; search cls = (M > 8).
+void launch_grouped(const GroupLaunch& g, const RDesc* d, hipStream_t s) {
+    if (g.nwork <= 0) return;
+    dim3 grid((unsigned)g.nwork);
+    if (g.stage == 0) {
+        const int nrb = g.cls / 2;
+        const bool big = g.cls % 2;
+#define SP_G1(N)                                                                                       \
+    if (nrb == N) {                                                                                    \
+        if (big) k_gemm1_grouped<N, 16, G1_IPT16><<<grid, 256, g.lds, s>>>(d, g.work);                 \
+        else k_gemm1_grouped<N, 8, G1_IPT8><<<grid, 256, g.lds, s>>>(d, g.work);                       \
+        return;                                                                                        \
+    }
+        SP_G1(2) SP_G1(4) SP_G1(6) SP_G1(8) SP_G1(10) SP_G1(12)
+#undef SP_G1
+        fail(SVDPHAT_E_UNSUPPORTED, "grouped GEMM1 class");
+    } else if (g.stage == 1) {
+        k_zprep_grouped<<<grid, 256, 0, s>>>(d, g.work);
+    } else if (g.stage == 2) {
+        if (g.cls) k_gemm2_grouped<6, true><<<grid, 256, 0, s>>>(d, g.work);
+        else k_gemm2_grouped<1, false><<<grid, 256, 0, s>>>(d, g.work);
+    } else {
+        if (g.cls) k_final_grouped<16><<<grid, 256, 0, s>>>(d, g.work);
+        else k_final_grouped<8><<<grid, 256, 0, s>>>(d, g.work);
+    }
+}
+
+void tune_time(svdphat_plan* p, int64_t F, int nsplit_want, int fch, double* us_g1, double* us_g2, hipStream_t s) {
+    const G1Layout& g = p->g1[P_FP16];
+    const int Rp = p->Rp;
+    const int64_t Fc = round_up64(F, 64);
+    int nsplit, cps;
+    g1_split_layout(g, Rp, F, nsplit_want, &nsplit, &cps);
+    const int ntile = p->ncls_pad / QTILE;
+    const size_t nx = (size_t)F * p->M * p->B;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += round_up64((int64_t)bytes, 256);
+        return o;
+    };
+    const size_t o_x = take(nx * sizeof(float2));
+    const size_t o_zp = take(sizeof(float) * nsplit * Fc * Rp);
+    const size_t o_z = take(sizeof(float) * Fc * Rp);
+    const size_t o_zf = take(sizeof(_Float16) * Fc * Rp);
+    const size_t o_sc = take(sizeof(float) * Fc);
+    const size_t o_zn = take(sizeof(float) * Fc);
+    const size_t o_pm = take(sizeof(float) * ntile * Fc);
+    char* w = (char*)ws_get(p, s, off);
+    float2* X = (float2*)(w + o_x);
+    k_fill_synth<<<dim3((unsigned)((nx + 255) / 256)), 256, 0, s>>>(X, (int64_t)nx);
+    float* zpart = (float*)(w + o_zp);
+    hipEvent_t e[3];
+    for (auto& ev : e) SP_HIP(hipEventCreate(&ev));
+    const int reps = 3;
+    for (int it = 0; it <= reps; ++it) {
+        if (it == 1) SP_HIP(hipEventRecord(e[0], s));
+        launch_g1<_Float16, 64, false>((int)(Fc / 64), nsplit, s, X, F, p, P_FP16, g, cps, zpart, Fc * Rp, nullptr,
+                                       nullptr);
+        k_zprep<_Float16><<<dim3((unsigned)(Fc / 4)), 256, 0, s>>>(zpart, nsplit, Fc * Rp, F, nullptr, Rp,
+                                                                   (float*)(w + o_z), (_Float16*)(w + o_zf),
+                                                                   (float*)(w + o_sc), (float*)(w + o_zn), 1);
+    }
+    SP_HIP(hipEventRecord(e[1], s));
+    const int KSn = Rp / Mf<_Float16>::KSTEP;
+    dim3 grid(cdiv(ntile, 4), (unsigned)((F + fch - 1) / fch));
+    for (int it = 0; it < reps; ++it) {
+        if (KSn <= 6)
+            k_gemm2<_Float16, 6, true><<<grid, 256, 0, s>>>((const _Float16*)p->Ufr[P_FP16], KSn,
+                                                            (const _Float16*)(w + o_zf), F, fch, p->ncls, ntile,
+                                                            (const float*)(w + o_sc), 1.f, (float*)(w + o_pm), Fc,
+                                                            nullptr, 0);
+        else
+            k_gemm2<_Float16, 1, false><<<grid, 256, 0, s>>>((const _Float16*)p->Ufr[P_FP16], KSn,
+                                                             (const _Float16*)(w + o_zf), F, fch, p->ncls, ntile,
+                                                             (const float*)(w + o_sc), 1.f, (float*)(w + o_pm), Fc,
+                                                             nullptr, 0);
+    }
+    SP_HIP(hipEventRecord(e[2], s));
+    SP_HIP(hipGetLastError());
+    SP_HIP(hipEventSynchronize(e[2]));
+    float a = 0.f, b = 0.f;
+    SP_HIP(hipEventElapsedTime(&a, e[0], e[1]));
+    SP_HIP(hipEventElapsedTime(&b, e[1], e[2]));
+    for (auto& ev : e) (void)hipEventDestroy(ev);
+    *us_g1 = 1e3 * a / reps;
+    *us_g2 = 1e3 * b / reps;
+}
 
 void launch_locate(svdphat_plan* p, const void* X, int64_t F, int prec, uint32_t mode, int32_t* doa, float* power,
                    float* yhat, float* margin, float* y_opt, hipStream_t s) {

@@ -264,3 +264,25 @@ def workload(name: str, frames: int | None = None, seed_offset: int = 0):
         X = X[:F]
     return dict(mics=mics, grid=grid, X=np.ascontiguousarray(X), dirs=dirs,
                 delta=1e-5, **STFT)
+
+
+def ragged_workload(n_arrays: int = 256, seed_offset: int = 0, frames_range=(64, 1024),
+                    levels=(3, 4, 5)):
+    """Many independent arrays: M ~ U{4..16} microphones at random positions
+    within an aperture ~ U[5, 20] cm, grid level ~ U(levels) (642 / 2562 /
+    10242 directions), delta ~ U{1e-3, 1e-5}, F ~ U[frames_range] frames of
+    one plane-wave source at a random direction with SNR ~ U[0, 20] dB,
+    N = 512, hop 256.  Returns a list of dicts (mics, grid_level, delta, X)."""
+    rng = np.random.default_rng(SEED0 + 4 + 1000 * seed_offset)
+    out = []
+    for _ in range(n_arrays):
+        M = int(rng.integers(4, 17))
+        mics = random_array(M, rng.uniform(0.05, 0.20), rng)
+        level = int(rng.choice(levels))
+        delta = float(rng.choice([1e-3, 1e-5]))
+        F = int(rng.integers(frames_range[0], frames_range[1] + 1))
+        u = random_direction(rng)
+        X = plane_wave_td(mics, [u], F, STFT["N"], STFT["hop"], STFT["fs"], STFT["c"], rng,
+                          snr_db=rng.uniform(0.0, 20.0)).astype(np.complex64)
+        out.append(dict(mics=mics, level=level, delta=delta, X=np.ascontiguousarray(X)))
+    return out
