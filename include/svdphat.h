@@ -197,6 +197,56 @@ int svdphat_ragged_info(const svdphat_ragged* ragged, int64_t* tuned,
                         int64_t* from_cache);
 void svdphat_ragged_destroy(svdphat_ragged* ragged);
 
+/*
+ * Learned proposal.  Section 3 replaces the O(Q) scan of eq. (14) by a k-d
+ * tree search; here a small network proposes where to look instead: an MLP
+ * maps the normalised projection f = [Re Z; Im Z] / ||Z|| (Z of eq. (12))
+ * through f -> GELU(W1 f + b1) -> GELU(W2 . + b2) -> W3 . + b3 (exact erf
+ * GELU, `hidden` units) to C coarse cells of the direction grid (the cell of
+ * a direction is its nearest coarse direction, ties within 1e-12 to the lowest
+ * cell).  The scored directions of the topk most probable cells are rescored
+ * exactly in FP32; frames whose top probability is below conf_min take the
+ * full search (svdphat_locate, FP16 + rescoring) instead.
+ *
+ * svdphat_proposal_create  fine: a plan (not owned; must outlive the
+ *   proposal; created without SVDPHAT_NO_DEDUP); coarse_xyz: host C x 3
+ *   directions; hidden: multiple of 64 in [64, 1024]; seed: weight init.
+ * svdphat_proposal_train_step  one Adam step (lr; beta 0.9 / 0.999, eps 1e-8)
+ *   on F device frames X [F][M][N/2+1]: labels are the cells of the method's
+ *   own argmax (svdphat_locate FP16, rescoring, hi/lo), the loss is the mean
+ *   softmax cross-entropy (written to *loss_host).  FP16 operands on MFMA,
+ *   FP32 accumulation and master weights.  Synchronous.
+ * svdphat_proposal_locate  doa [F] int32, power [F] f32 as svdphat_locate,
+ *   fell_back [F] u8 = 1 where the full search was used.  Asynchronous.
+ * svdphat_proposal_params  copies the FP32 parameters to (set = 0) or from
+ *   (set = 1) a host buffer of svdphat_proposal_nparams() floats laid out
+ *   W1 [hidden][2K], b1 [hidden], W2 [hidden][hidden], b2 [hidden],
+ *   W3 [C][hidden], b3 [C], row-major.
+ * svdphat_proposal_grad  testing aid: mean loss and its gradient (same layout)
+ *   for host features [F][2K] and labels [F].
+ * svdphat_proposal_cells  host [Q]: cell of every fine direction.
+ */
+typedef struct svdphat_proposal svdphat_proposal;
+int svdphat_proposal_create(svdphat_plan* fine, const double* coarse_xyz,
+                            int32_t C, int32_t hidden, uint64_t seed,
+                            svdphat_proposal** out);
+int svdphat_proposal_train_step(svdphat_proposal* proposal, const void* X,
+                                int64_t F, float lr, float* loss_host,
+                                void* stream);
+int svdphat_proposal_locate(svdphat_proposal* proposal, const void* X,
+                            int64_t F, int32_t topk, float conf_min,
+                            int32_t* doa, float* power, uint8_t* fell_back,
+                            void* stream);
+int64_t svdphat_proposal_nparams(const svdphat_proposal* proposal);
+int svdphat_proposal_params(svdphat_proposal* proposal, float* host,
+                            int64_t n, int32_t set);
+int svdphat_proposal_grad(svdphat_proposal* proposal, const float* features,
+                          const int32_t* labels, int64_t F, float* grad,
+                          float* loss_host);
+int svdphat_proposal_cells(const svdphat_proposal* proposal,
+                           int32_t* cell_of_direction);
+void svdphat_proposal_destroy(svdphat_proposal* proposal);
+
 /* svdphat_plan_destroy -- frees the plan and its device memory; NULL is a no-op. */
 void svdphat_plan_destroy(svdphat_plan* plan);
 

@@ -69,6 +69,18 @@ SIGNATURES = {
                                         C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p]),
     "svdphat_ragged_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "svdphat_ragged_destroy": (None, [C.c_void_p]),
+    "svdphat_proposal_create": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_uint64,
+                                          C.POINTER(C.c_void_p)]),
+    "svdphat_proposal_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_float,
+                                              C.POINTER(C.c_float), C.c_void_p]),
+    "svdphat_proposal_locate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_float,
+                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "svdphat_proposal_nparams": (C.c_int64, [C.c_void_p]),
+    "svdphat_proposal_params": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
+    "svdphat_proposal_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                        C.POINTER(C.c_float)]),
+    "svdphat_proposal_cells": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "svdphat_proposal_destroy": (None, [C.c_void_p]),
     "svdphat_timing_enable": (C.c_int, [C.c_int]),
     "svdphat_timing_reset": (C.c_int, []),
     "svdphat_timing_read": (C.c_int, [C.c_int32, C.c_char_p, C.c_int32, C.POINTER(C.c_double),
@@ -294,6 +306,72 @@ class Ragged:
     def close(self):
         if self._h is not None:
             svdphat_ragged_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Proposal:
+    """Learned coarse-cell proposal over a fine plan (see svdphat.h)."""
+
+    def __init__(self, plan, coarse, hidden=256, seed=0):
+        self.plan = plan
+        coarse = np.ascontiguousarray(coarse, dtype=np.float64)
+        self.C = coarse.shape[0]
+        out = C.c_void_p()
+        _check(lib().svdphat_proposal_create(plan.handle, coarse.ctypes.data, self.C, hidden, seed,
+                                             C.byref(out)))
+        self._h = out
+
+    def train_step(self, X, lr=1e-3, stream=None):
+        loss = C.c_float()
+        _check(lib().svdphat_proposal_train_step(self._h, _ptr(X), X.shape[0], lr, C.byref(loss),
+                                                 _stream(stream)))
+        return loss.value
+
+    def locate(self, X, topk=8, conf_min=0.5, stream=None):
+        import torch
+        F = X.shape[0]
+        doa = torch.empty(F, dtype=torch.int32, device=X.device)
+        power = torch.empty(F, dtype=torch.float32, device=X.device)
+        fell = torch.empty(F, dtype=torch.uint8, device=X.device)
+        _check(lib().svdphat_proposal_locate(self._h, _ptr(X), F, topk, conf_min, _ptr(doa), _ptr(power),
+                                             _ptr(fell), _stream(stream)))
+        return dict(doa=doa, power=power, fell_back=fell)
+
+    def nparams(self):
+        return lib().svdphat_proposal_nparams(self._h)
+
+    def get_params(self):
+        buf = np.zeros(self.nparams(), dtype=np.float32)
+        _check(lib().svdphat_proposal_params(self._h, buf.ctypes.data, buf.size, 0))
+        return buf
+
+    def set_params(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.float32)
+        _check(lib().svdphat_proposal_params(self._h, buf.ctypes.data, buf.size, 1))
+
+    def grad(self, features, labels):
+        features = np.ascontiguousarray(features, dtype=np.float32)
+        labels = np.ascontiguousarray(labels, dtype=np.int32)
+        g = np.zeros(self.nparams(), dtype=np.float32)
+        loss = C.c_float()
+        _check(lib().svdphat_proposal_grad(self._h, features.ctypes.data, labels.ctypes.data,
+                                           features.shape[0], g.ctypes.data, C.byref(loss)))
+        return loss.value, g
+
+    def cells(self):
+        out = np.zeros(self.plan.info["Q"], dtype=np.int32)
+        _check(lib().svdphat_proposal_cells(self._h, out.ctypes.data))
+        return out
+
+    def close(self):
+        if self._h is not None:
+            lib().svdphat_proposal_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -315,6 +315,91 @@ void svdphat_ragged_destroy(svdphat_ragged* r) {
     if (r) ragged_destroy(r);
 }
 
+int svdphat_proposal_create(svdphat_plan* fine, const double* coarse_xyz, int32_t C, int32_t hidden, uint64_t seed,
+                            svdphat_proposal** out) {
+    return guarded([&] {
+        SP_REQUIRE(out != nullptr, SVDPHAT_E_INVAL, "out is NULL");
+        *out = nullptr;
+        SP_REQUIRE(fine && coarse_xyz, SVDPHAT_E_INVAL, "NULL plan or coarse grid");
+        SP_REQUIRE(C >= 1 && C <= 1024, SVDPHAT_E_INVAL, "C must be in [1, 1024]");
+        SP_REQUIRE(hidden >= 64 && hidden <= 1024 && hidden % 64 == 0, SVDPHAT_E_INVAL,
+                   "hidden must be a multiple of 64 in [64, 1024]");
+        SP_REQUIRE(!(fine->flags & SVDPHAT_NO_DEDUP), SVDPHAT_E_UNSUPPORTED,
+                   "the proposal needs a plan with one scored row per class");
+        SP_HIP(hipSetDevice(fine->device));
+        svdphat_proposal* pr = new svdphat_proposal();
+        pr->plan = fine;
+        try {
+            proposal_build(pr, coarse_xyz, C, hidden, seed);
+        } catch (...) {
+            proposal_free(pr);
+            throw;
+        }
+        *out = pr;
+    });
+}
+
+int svdphat_proposal_train_step(svdphat_proposal* pr, const void* X, int64_t F, float lr, float* loss_host,
+                                void* stream) {
+    return guarded([&] {
+        SP_REQUIRE(pr && X && F >= 1 && F < ((int64_t)1 << 31), SVDPHAT_E_INVAL, "bad proposal, X or F");
+        SP_REQUIRE(std::isfinite(lr) && lr > 0.f, SVDPHAT_E_INVAL, "lr must be > 0");
+        SP_HIP(hipSetDevice(pr->plan->device));
+        const float l = proposal_train_step(pr, (const float2*)X, F, lr, (hipStream_t)stream);
+        if (loss_host) *loss_host = l;
+    });
+}
+
+int svdphat_proposal_locate(svdphat_proposal* pr, const void* X, int64_t F, int32_t topk, float conf_min,
+                            int32_t* doa, float* power, uint8_t* fell_back, void* stream) {
+    return guarded([&] {
+        SP_REQUIRE(pr, SVDPHAT_E_INVAL, "NULL proposal");
+        SP_REQUIRE(F >= 0 && F < ((int64_t)1 << 31), SVDPHAT_E_INVAL, "F out of range");
+        SP_REQUIRE(topk >= 1 && topk <= pr->C, SVDPHAT_E_INVAL, "topk must be in [1, C]");
+        if (F == 0) return;
+        SP_REQUIRE(X && doa && power && fell_back, SVDPHAT_E_INVAL, "NULL X or output");
+        SP_HIP(hipSetDevice(pr->plan->device));
+        proposal_locate(pr, (const float2*)X, F, topk, conf_min, doa, power, fell_back, (hipStream_t)stream);
+    });
+}
+
+int svdphat_proposal_params(svdphat_proposal* pr, float* host, int64_t n, int32_t set) {
+    return guarded([&] {
+        SP_REQUIRE(pr, SVDPHAT_E_INVAL, "NULL proposal");
+        const int64_t need = proposal_nparams(pr);
+        if (!host) {
+            SP_REQUIRE(n == 0, SVDPHAT_E_INVAL, "NULL buffer");
+            return;
+        }
+        SP_REQUIRE(n == need, SVDPHAT_E_INVAL, "parameter count must be " + std::to_string(need));
+        SP_HIP(hipSetDevice(pr->plan->device));
+        proposal_params(pr, host, set != 0);
+    });
+}
+
+int64_t svdphat_proposal_nparams(const svdphat_proposal* pr) { return pr ? proposal_nparams(pr) : -1; }
+
+int svdphat_proposal_grad(svdphat_proposal* pr, const float* features, const int32_t* labels, int64_t F,
+                          float* grad, float* loss_host) {
+    return guarded([&] {
+        SP_REQUIRE(pr && features && labels && grad && F >= 1, SVDPHAT_E_INVAL, "NULL argument or F < 1");
+        for (int64_t f = 0; f < F; ++f)
+            SP_REQUIRE(labels[f] >= 0 && labels[f] < pr->C, SVDPHAT_E_INVAL, "label out of range");
+        SP_HIP(hipSetDevice(pr->plan->device));
+        const float l = proposal_grad(pr, features, labels, F, grad);
+        if (loss_host) *loss_host = l;
+    });
+}
+
+int svdphat_proposal_cells(const svdphat_proposal* pr, int32_t* cell_of_direction) {
+    return guarded([&] {
+        SP_REQUIRE(pr && cell_of_direction, SVDPHAT_E_INVAL, "NULL argument");
+        std::memcpy(cell_of_direction, pr->cell_of_dir.data(), pr->cell_of_dir.size() * sizeof(int32_t));
+    });
+}
+
+void svdphat_proposal_destroy(svdphat_proposal* pr) { proposal_free(pr); }
+
 int svdphat_timing_enable(int enable) {
     return guarded([&] {
         std::lock_guard<std::mutex> lk(timing().mu);

@@ -85,4 +85,82 @@ __device__ __forceinline__ bool better(float a, int ia, float b, int ib) {
     return a > b || (a == b && ia < ib);
 }
 
+
+// Algorithm 1, online step 4: the power of one direction from its row of W,
+// Y = Re sum_{p,k} exp(2 pi i k tau_p / N) x_{p,k}, for one frame (xf =
+// [M][B] STFT values, tq = tau_p / N of the direction's pairs).  One wave;
+// returns this lane's partial sum (the caller reduces over the wave).
+template <int MAXM>
+__device__ __forceinline__ float direction_power(const float2* __restrict__ xf, int M, int B,
+                                                 const float* __restrict__ tq, int lane) {
+    float acc = 0.f;
+    if (MAXM <= 8) {
+        // each lane takes bins b0 + lane + 64 j, j < NJ; the phase of bin
+        // b + 64 follows from that of bin b by one complex multiplication
+        constexpr int NJ = 5;
+        for (int b0 = 0; b0 < B; b0 += 64 * NJ) {
+            float nr[NJ][MAXM], ni[NJ][MAXM];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                for (int m = 0; m < MAXM; ++m) {
+                    const int bin = b0 + lane + 64 * j;
+                    float2 v = (bin < B && m < M) ? xf[(int64_t)m * B + bin] : float2{0.f, 0.f};
+                    nr[j][m] = v.x;
+                    ni[j][m] = v.y;
+                    unit(nr[j][m], ni[j][m]);
+                }
+            int p = 0;
+#pragma unroll
+            for (int i = 0; i < MAXM; ++i)
+#pragma unroll
+                for (int k = i + 1; k < MAXM; ++k)
+                    if (k < M) {
+                        const float tn = tq[p];
+                        float t0 = (float)(b0 + lane) * tn;
+                        t0 -= rintf(t0);
+                        float t1 = 64.f * tn;
+                        t1 -= rintf(t1);
+                        float wr = __builtin_amdgcn_cosf(t0), wi = __builtin_amdgcn_sinf(t0);
+                        const float sr = __builtin_amdgcn_cosf(t1), si = __builtin_amdgcn_sinf(t1);
+#pragma unroll
+                        for (int j = 0; j < NJ; ++j) {
+                            const float xr = nr[j][i] * nr[j][k] + ni[j][i] * ni[j][k];
+                            const float xi = ni[j][i] * nr[j][k] - nr[j][i] * ni[j][k];
+                            acc = fmaf(wr, xr, fmaf(-wi, xi, acc));
+                            const float nwr = wr * sr - wi * si;
+                            wi = wr * si + wi * sr;
+                            wr = nwr;
+                        }
+                        ++p;
+                    }
+        }
+    } else {
+        for (int bin = lane; bin < B; bin += 64) {
+            float re[MAXM], im[MAXM];
+#pragma unroll
+            for (int m = 0; m < MAXM; ++m) {
+                const float2 v = m < M ? xf[(int64_t)m * B + bin] : float2{0.f, 0.f};
+                re[m] = v.x;
+                im[m] = v.y;
+                unit(re[m], im[m]);
+            }
+            int p = 0;
+#pragma unroll
+            for (int i = 0; i < MAXM; ++i)
+#pragma unroll
+                for (int k = i + 1; k < MAXM; ++k)
+                    if (k < M) {
+                        const float xr = re[i] * re[k] + im[i] * im[k];
+                        const float xi = im[i] * re[k] - re[i] * im[k];
+                        float t = (float)bin * tq[p];
+                        t -= rintf(t);
+                        acc = fmaf(__builtin_amdgcn_cosf(t), xr, fmaf(-__builtin_amdgcn_sinf(t), xi, acc));
+                        ++p;
+                    }
+        }
+    }
+    return acc;
+}
+
 }  // namespace svdphat

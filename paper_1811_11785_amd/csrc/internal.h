@@ -151,6 +151,20 @@ size_t g1_lds_bytes(int NRB, int CW);
 void g1_split(const svdphat_plan* p, int64_t F, int want, int* nsplit, int* cps);
 // times one GEMM1 + Z prep (nsplit) and one GEMM2 (fch) of plan p on F
 // synthetic frames in FP16; returns microseconds
+void proposal_build(svdphat_proposal* pr, const double* coarse, int C, int H, uint64_t seed);
+float proposal_train_step(svdphat_proposal* pr, const float2* X, int64_t F, float lr, hipStream_t s);
+void proposal_locate(svdphat_proposal* pr, const float2* X, int64_t F, int topk, float conf_min, int32_t* doa,
+                     float* power, uint8_t* fell, hipStream_t s);
+int64_t proposal_nparams(const svdphat_proposal* pr);
+void proposal_params(svdphat_proposal* pr, float* host, bool set);
+float proposal_grad(svdphat_proposal* pr, const float* feat, const int32_t* lab, int64_t F, float* grad);
+void proposal_free(svdphat_proposal* pr);
+int64_t front_zpart_floats(const svdphat_plan* p, int64_t F);
+void front_fp16(svdphat_plan* p, const float2* X, int64_t F, float* zpart, float* z32, _Float16* zfrag, float* zsc,
+                float* zn, hipStream_t s);
+void back_list_fp16(svdphat_plan* p, const float2* X, int64_t Fmax, const int* flist, const int* fcount,
+                    const _Float16* zfrag, const float* zsc, const float* z32pos, const float* zn_frame,
+                    float* pmax, int64_t pstride, int32_t* doa, float* power, float* margin, hipStream_t s);
 void tune_time(svdphat_plan* p, int64_t F, int nsplit, int fch, double* us_g1, double* us_g2, hipStream_t s);
 
 struct Workspace {
@@ -168,6 +182,7 @@ struct svdphat_plan {
     uint32_t flags = 0;
     double residual = 0, fro2 = 0, kappa = 0;  // kappa = max_q ||U_q||
     std::vector<double> tau;     // [Q][P] delays in samples, eq. (2)
+    std::vector<double> grid;    // [Q][3] unit directions
     std::vector<int32_t> rep;    // [Q] class representative
     std::vector<int32_t> rows;   // [ncls] direction index of each scored row
     std::vector<double> sigma;   // all singular values, descending
@@ -201,8 +216,32 @@ struct svdphat_plan {
     std::map<void*, svdphat::Workspace> ws;  // per stream
 };
 
+// Learned proposal state (see the proposal calls of the ABI).
+struct svdphat_proposal {
+    svdphat_plan* plan = nullptr;
+    int C = 0, Cp = 0, H = 0, D = 0, D0 = 0;  // cells, padded cells, hidden, input (2K), padded input (Rp)
+    std::vector<int32_t> cell_of_dir;         // [Q]
+    int32_t* d_cell_of_dir = nullptr;         // [Q]
+    int32_t* d_cell_start = nullptr;          // [C + 1] CSR over scored rows
+    int32_t* d_cell_rows = nullptr;           // [ncls]
+    float* d_U32R = nullptr;                  // [ncls][Rp] FP32 rows, row-major
+    // parameters: FP32 master, Adam moments, FP16 copies and transposes
+    int64_t off[6] = {0, 0, 0, 0, 0, 0};     // W1 b1 W2 b2 W3 b3 inside the flat arrays
+    int64_t nparam = 0;
+    float* P = nullptr;
+    float* Mm = nullptr;
+    float* Vv = nullptr;
+    _Float16* Wh[3] = {nullptr, nullptr, nullptr};  // [out][in]
+    _Float16* Wt[3] = {nullptr, nullptr, nullptr};  // [in][out]
+    int64_t step = 0;
+    // workspace
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    int* d_count = nullptr;  // [4]
+};
+
 namespace svdphat {
-// launchers (kernels.hip)
+// launchers
 void launch_locate(svdphat_plan* p, const void* X, int64_t F, int prec, uint32_t mode,
                    int32_t* doa, float* power, float* yhat, float* margin, float* y_opt,
                    hipStream_t s);

@@ -218,9 +218,11 @@ void build_plan(svdphat_plan* p, const double* mics, const double* grid) {
             pj.push_back((int8_t)j);
         }
     p->tau.resize((size_t)Q * P);
+    p->grid.resize((size_t)Q * 3);
     for (int q = 0; q < Q; ++q) {
         const double* s = grid + 3 * q;
         double n = std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+        for (int d = 0; d < 3; ++d) p->grid[3 * (size_t)q + d] = s[d] / n;
         for (int k = 0; k < P; ++k) {
             const double* ri = mics + 3 * pi[k];
             const double* rj = mics + 3 * pj[k];

@@ -1,0 +1,740 @@
+// Learned coarse-cell proposal for the search of eq. (14) (Section 3 replaces
+// the O(Q) scan by a k-d tree over the normalised rows; this replaces it by
+// a small network): an MLP maps the normalised projection
+// f = [Re Z; Im Z] / ||Z|| (Z of eq. (12), S folded in) to C coarse cells of
+// the direction grid; the scored directions inside the top cells are rescored
+// exactly in FP32, and frames whose top probability is below a threshold fall
+// back to the full search.  The network is trained on the GPU on
+// (f, cell of the method's own argmax) pairs with hand-written FP16 MFMA
+// kernels (forward, backward, weight gradients), FP32 master weights and Adam.
+//
+// Network: f (2K) -> GELU(W1 f + b1) (H) -> GELU(W2 . + b2) (H) -> W3 . + b3
+// (C), exact erf GELU, softmax cross-entropy.
+#include "device.h"
+
+#include <cstring>
+#include <random>
+
+namespace svdphat {
+
+namespace {
+
+constexpr int GT = 64;   // output tile (rows and columns) of the MLP GEMM
+constexpr int GK = 32;   // reduction step
+constexpr int GPAD = 8;
+
+enum { EPI_GELU = 0, EPI_BIAS = 1, EPI_DGELU = 2, EPI_F32 = 3 };
+
+__device__ __forceinline__ float gelu_f(float v) { return 0.5f * v * (1.f + erff(v * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_d(float v) {
+    return 0.5f * (1.f + erff(v * 0.70710678118654752f)) + v * 0.39894228040143268f * __expf(-0.5f * v * v);
+}
+
+// C(m, n) = sum_k A(m, k) B(n, k) for m < M, n < N, k in [kbeg, kend), f16
+// operands, FP32 accumulation on 16x16x32 MFMA.  A(m, k) = A[m*lda + k]
+// (AT false) or A[k*lda + m] (AT true); B(n, k) = B[n*ldb + k] (BT false)
+// or B[k*ldb + n] (BT true).  Workgroup: 4 waves, 64 x 64 outputs, each
+// wave 16 rows x 64 columns.  Epilogues:
+//   EPI_GELU   pre = acc + bias[n] -> out32 (pre-activation), out16 = GELU(pre)
+//   EPI_BIAS   out32 = acc + bias[n]
+//   EPI_DGELU  out16 = acc * GELU'(pre32[m, n])
+//   EPI_F32    out32[split][m][n] = acc (split-K partials over blockIdx.z)
+template <bool AT, bool BT, int EPI>
+__global__ __launch_bounds__(256) void k_mlp_gemm(const _Float16* __restrict__ A, int lda,
+                                                  const _Float16* __restrict__ Bm, int ldb, int M, int N, int K,
+                                                  int ksplit, const float* __restrict__ bias,
+                                                  const float* __restrict__ pre32, float* __restrict__ out32,
+                                                  _Float16* __restrict__ out16, int ldo) {
+    __shared__ __align__(16) _Float16 As[GT][GK + GPAD];
+    __shared__ __align__(16) _Float16 Bs[GT][GK + GPAD];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int m0 = blockIdx.x * GT, n0 = blockIdx.y * GT;
+    const int kper = (K + ksplit - 1) / ksplit;
+    const int kbeg = blockIdx.z * kper, kend = min(K, kbeg + kper);
+    f4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
+        // stage 64 x 32 tiles of A and B with the reduction axis contiguous
+        if (!AT) {
+            const int r = tid >> 2, kk = (tid & 3) * 8;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int m = m0 + r, k = k0 + kk + e;
+                As[r][kk + e] = (m < M && k < kend) ? A[(int64_t)m * lda + k] : (_Float16)0.f;
+            }
+        } else {
+            const int kk = tid >> 3, r = (tid & 7) * 8;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int m = m0 + r + e, k = k0 + kk;
+                As[r + e][kk] = (m < M && k < kend) ? A[(int64_t)k * lda + m] : (_Float16)0.f;
+            }
+        }
+        if (!BT) {
+            const int r = tid >> 2, kk = (tid & 3) * 8;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int n = n0 + r, k = k0 + kk + e;
+                Bs[r][kk + e] = (n < N && k < kend) ? Bm[(int64_t)n * ldb + k] : (_Float16)0.f;
+            }
+        } else {
+            const int kk = tid >> 3, r = (tid & 7) * 8;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int n = n0 + r + e, k = k0 + kk;
+                Bs[r + e][kk] = (n < N && k < kend) ? Bm[(int64_t)k * ldb + n] : (_Float16)0.f;
+            }
+        }
+        __syncthreads();
+        const h8 a = *reinterpret_cast<const h8*>(&As[wave * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const h8 b = *reinterpret_cast<const h8*>(&Bs[j * 16 + (lane & 15)][8 * (lane >> 4)]);
+            acc[j] = mfma(a, b, acc[j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int m = m0 + wave * 16 + 4 * (lane >> 4) + e;
+            const int n = n0 + j * 16 + (lane & 15);
+            if (m >= M || n >= N) continue;
+            const float v = acc[j][e];
+            const int64_t o = (int64_t)m * ldo + n;
+            if (EPI == EPI_GELU) {
+                const float pv = v + bias[n];
+                out32[o] = pv;
+                out16[o] = (_Float16)gelu_f(pv);
+            } else if (EPI == EPI_BIAS) {
+                out32[o] = v + bias[n];
+            } else if (EPI == EPI_DGELU) {
+                out16[o] = (_Float16)(v * gelu_d(pre32[o]));
+            } else {
+                out32[(int64_t)blockIdx.z * M * ldo + o] = v;
+            }
+        }
+}
+
+// f = z / ||z|| in f16 (0 for z = 0); z32 rows [F][Rp] already stacked.
+__global__ void k_features(const float* __restrict__ z32, const float* __restrict__ zn, int64_t F, int Rp,
+                           _Float16* __restrict__ feat) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= F * Rp) return;
+    const int64_t f = i / Rp;
+    const float n = zn[f];
+    feat[i] = (_Float16)(n > 0.f ? z32[i] / n : 0.f);
+}
+
+__global__ void k_labels(const int32_t* __restrict__ doa, const int32_t* __restrict__ cell_of_dir, int64_t F,
+                         int32_t* __restrict__ lab) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < F) lab[f] = cell_of_dir[doa[f]];
+}
+
+// Softmax cross-entropy, one wave per frame: loss[f] = -log p[label], and
+// d logits = p - onehot (summed over frames, i.e. the mean loss scaled by F;
+// the weight update divides by F).
+__global__ __launch_bounds__(256) void k_xent(const float* __restrict__ logits, int ld, int C,
+                                              const int32_t* __restrict__ lab, int64_t F, _Float16* __restrict__ dlog,
+                                              float* __restrict__ loss) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t f = (int64_t)blockIdx.x * 4 + wave;
+    if (f >= F) return;
+    const float* l = logits + f * ld;
+    float mx = -INFINITY;
+    for (int c = lane; c < C; c += 64) mx = fmaxf(mx, l[c]);
+    mx = wave_max(mx);
+    float se = 0.f;
+    for (int c = lane; c < C; c += 64) se += __expf(l[c] - mx);
+    se = wave_sum(se);
+    const int y = lab[f];
+    for (int c = lane; c < ld; c += 64) {
+        const float p = c < C ? __expf(l[c] - mx) / se : 0.f;
+        dlog[f * ld + c] = (_Float16)(p - (c == y ? 1.f : 0.f));
+    }
+    if (lane == 0) loss[f] = -(l[y] - mx - __logf(se));
+}
+
+// Column sums over frames of an f16 matrix [F][ld] (bias gradients).
+__global__ void k_colsum(const _Float16* __restrict__ d, int64_t F, int N, int ld, float* __restrict__ out) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.f;
+    for (int64_t f = 0; f < F; ++f) s += (float)d[f * ld + n];
+    out[n] = s;
+}
+
+struct AdamSeg {
+    int64_t off;       // offset in the flat parameter arrays
+    int rows, cols;    // weight shape (cols = 1 for a bias)
+    int parts;         // split-K partials of the gradient
+    const float* g;    // [parts][rows][cols] (weights) or [rows] (bias)
+    _Float16* wh;      // f16 copy [rows][cols] or null
+    _Float16* wt;      // f16 transpose [cols][rows] or null
+    int ldh, ldt;      // leading dimensions of the copies
+};
+
+// Adam (Kingma & Ba) with bias correction; gradients are the sum over the
+// batch's frames and are divided by F here.
+__global__ void k_adam(AdamSeg sg, float* __restrict__ P, float* __restrict__ Mm, float* __restrict__ Vv, float inv_f,
+                       float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = (int64_t)sg.rows * sg.cols;
+    if (i >= n) return;
+    float g = 0.f;
+    for (int s = 0; s < sg.parts; ++s) g += sg.g[(int64_t)s * n + i];
+    g *= inv_f;
+    const int64_t o = sg.off + i;
+    const float m = b1 * Mm[o] + (1.f - b1) * g;
+    const float v = b2 * Vv[o] + (1.f - b2) * g * g;
+    Mm[o] = m;
+    Vv[o] = v;
+    const float p = P[o] - lr * (m / c1) / (sqrtf(v / c2) + eps);
+    P[o] = p;
+    const int r = (int)(i / sg.cols), c = (int)(i % sg.cols);
+    if (sg.wh) sg.wh[(int64_t)r * sg.ldh + c] = (_Float16)p;
+    if (sg.wt) sg.wt[(int64_t)c * sg.ldt + r] = (_Float16)p;
+}
+
+// f16 copies of the FP32 weights (after set_params)
+__global__ void k_cast_w(const float* __restrict__ W, int rows, int cols, _Float16* __restrict__ wh, int ldh,
+                         _Float16* __restrict__ wt, int ldt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)rows * cols) return;
+    const int r = (int)(i / cols), c = (int)(i % cols);
+    wh[(int64_t)r * ldh + c] = (_Float16)W[i];
+    wt[(int64_t)c * ldt + r] = (_Float16)W[i];
+}
+
+// Inference, one wave per frame: softmax top probability; if below conf_min
+// the frame is queued for the full search; otherwise the scored directions
+// of the topk most probable cells are rescored in FP32 (U rows . z) and the
+// best one's power is taken from its row of W.
+template <int MAXM>
+__global__ __launch_bounds__(256) void k_propose(const float* __restrict__ logits, int ld, int C, int topk,
+                                                 float conf_min, const float* __restrict__ z32, int Rp,
+                                                 const float* __restrict__ U32R, const int32_t* __restrict__ cstart,
+                                                 const int32_t* __restrict__ crows, const int32_t* __restrict__ rows,
+                                                 const float2* __restrict__ X, int M, int P, int B,
+                                                 const float* __restrict__ tauN, int64_t F, int32_t* __restrict__ doa,
+                                                 float* __restrict__ power, uint8_t* __restrict__ fell,
+                                                 int* __restrict__ flist, int* __restrict__ fcount) {
+    __shared__ float zs[4][1024];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t f = (int64_t)blockIdx.x * 4 + wave;
+    if (f >= F) return;
+    const float* l = logits + f * ld;
+    // logits of this frame's cells, up to 1024 cells in registers
+    float lv[16];
+    float mx = -INFINITY;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int c = lane + 64 * j;
+        lv[j] = c < C ? l[c] : -INFINITY;
+        mx = fmaxf(mx, lv[j]);
+    }
+    mx = wave_max(mx);
+    float se = 0.f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) se += lv[j] > -INFINITY ? __expf(lv[j] - mx) : 0.f;
+    se = wave_sum(se);
+    const float p1 = 1.f / se;
+    if (p1 < conf_min) {
+        if (lane == 0) {
+            fell[f] = 1;
+            const int k = atomicAdd(fcount, 1);
+            flist[k] = (int)f;
+        }
+        return;
+    }
+    float* zw = zs[wave];
+    for (int r = lane; r < Rp; r += 64) zw[r] = z32[f * Rp + r];
+    wave_sync();
+    float by = -INFINITY;
+    int bq = 0x7fffffff;
+    for (int t = 0; t < topk; ++t) {
+        // next most probable cell (lowest index on ties)
+        float v = -INFINITY;
+        int c = 0x7fffffff;
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (better(lv[j], lane + 64 * j, v, c)) {
+                v = lv[j];
+                c = lane + 64 * j;
+            }
+        for (int o = 32; o > 0; o >>= 1) {
+            const float ov = __shfl_xor(v, o);
+            const int oc = __shfl_xor(c, o);
+            if (better(ov, oc, v, c)) {
+                v = ov;
+                c = oc;
+            }
+        }
+        if (c >= C || v == -INFINITY) break;
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (lane + 64 * j == c) lv[j] = -INFINITY;
+        for (int i = cstart[c] + lane; i < cstart[c + 1]; i += 64) {
+            const int row = crows[i];
+            const float* u = U32R + (int64_t)row * Rp;
+            float s0 = 0.f, s1 = 0.f;
+            for (int r = 0; r < Rp; r += 2) {
+                s0 = fmaf(u[r], zw[r], s0);
+                s1 = fmaf(u[r + 1], zw[r + 1], s1);
+            }
+            const float y = s0 + s1;
+            const int q = rows[row];
+            if (better(y, q, by, bq)) {
+                by = y;
+                bq = q;
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const float oy = __shfl_xor(by, o);
+        const int oq = __shfl_xor(bq, o);
+        if (better(oy, oq, by, bq)) {
+            by = oy;
+            bq = oq;
+        }
+    }
+    if (bq < 0 || bq == 0x7fffffff) bq = rows[0];
+    float acc = direction_power<MAXM>(X + f * M * B, M, B, tauN + (int64_t)bq * P, lane);
+    acc = wave_sum(acc);
+    if (lane == 0) {
+        doa[f] = bq;
+        power[f] = acc;
+        fell[f] = 0;
+    }
+}
+
+// Gathers the z of the listed frames to positions 0..count-1 in the GEMM2
+// operand layout (FP16, per-frame power-of-two scale) and as FP32 rows.
+__global__ __launch_bounds__(256) void k_gather_z(const int* __restrict__ flist, const int* __restrict__ fcount,
+                                                  const float* __restrict__ z32, int Rp, float* __restrict__ zg32,
+                                                  _Float16* __restrict__ zgfrag, float* __restrict__ zgsc) {
+    constexpr int KS = Mf<_Float16>::KSTEP, EPL = Mf<_Float16>::EPL;
+    const int64_t pos = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (pos >= *fcount) return;
+    const int64_t f = flist[pos];
+    float mx = 0.f;
+    for (int r = lane; r < Rp; r += 64) {
+        const float v = z32[f * Rp + r];
+        zg32[pos * Rp + r] = v;
+        mx = fmaxf(mx, fabsf(v));
+    }
+    mx = wave_max(mx);
+    float sc = 1.f;
+    if (mx > 0.f) {
+        int e;
+        frexpf(mx, &e);
+        sc = ldexpf(1.f, 14 - e);
+    }
+    if (lane == 0) zgsc[pos] = sc;
+    const int64_t fb = pos >> 4;
+    const int nn = (int)(pos & 15);
+    const int KSn = Rp / KS;
+    for (int r = lane; r < Rp; r += 64) {
+        const int ks = r / KS, kin = r % KS;
+        zgfrag[((fb * KSn + ks) * 64 + nn + 16 * (kin / EPL)) * EPL + kin % EPL] = (_Float16)(zg32[pos * Rp + r] * sc);
+    }
+}
+
+template <bool AT, bool BT, int EPI>
+void mlp_gemm(const _Float16* A, int lda, const _Float16* Bm, int ldb, int M, int N, int K, int ksplit,
+              const float* bias, const float* pre32, float* out32, _Float16* out16, int ldo, hipStream_t s) {
+    dim3 grid(cdiv(M, GT), cdiv(N, GT), ksplit);
+    k_mlp_gemm<AT, BT, EPI><<<grid, 256, 0, s>>>(A, lda, Bm, ldb, M, N, K, ksplit, bias, pre32, out32, out16, ldo);
+    SP_HIP(hipGetLastError());
+}
+
+struct PW {  // workspace carve-up for F frames
+    float *zpart, *z32, *zsc, *zn, *a1, *a2, *logits, *loss, *g[6], *pmax, *zg32, *zgsc;
+    _Float16 *zfrag, *feat, *h1, *h2, *dlog, *d2, *d1, *zgfrag;
+    int32_t *lab, *doa, *flist;
+    float* pw;
+    int64_t Fc;
+};
+
+constexpr int WSPLIT = 8;  // split-K partials of the weight gradients
+
+PW carve(svdphat_proposal* pr, int64_t F, hipStream_t s) {
+    svdphat_plan* p = pr->plan;
+    const int64_t Fc = round_up64(std::max<int64_t>(F, 1), 64);
+    const int H = pr->H, Cp = pr->Cp, D0 = pr->D0, Rp = p->Rp;
+    const int ntile = p->ncls_pad / QTILE;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        size_t o = off;
+        off += round_up64((int64_t)b, 256);
+        return o;
+    };
+    const size_t o_zp = take(sizeof(float) * front_zpart_floats(p, F));
+    const size_t o_z = take(sizeof(float) * Fc * Rp), o_sc = take(sizeof(float) * Fc), o_zn = take(sizeof(float) * Fc);
+    const size_t o_zf = take(sizeof(_Float16) * Fc * Rp), o_ft = take(sizeof(_Float16) * Fc * D0);
+    const size_t o_a1 = take(sizeof(float) * Fc * H), o_h1 = take(sizeof(_Float16) * Fc * H);
+    const size_t o_a2 = take(sizeof(float) * Fc * H), o_h2 = take(sizeof(_Float16) * Fc * H);
+    const size_t o_lg = take(sizeof(float) * Fc * Cp), o_dl = take(sizeof(_Float16) * Fc * Cp);
+    const size_t o_d2 = take(sizeof(_Float16) * Fc * H), o_d1 = take(sizeof(_Float16) * Fc * H);
+    const size_t o_ls = take(sizeof(float) * Fc), o_lab = take(sizeof(int32_t) * Fc), o_doa = take(sizeof(int32_t) * Fc);
+    const size_t o_pw = take(sizeof(float) * Fc), o_fl = take(sizeof(int32_t) * Fc);
+    const size_t o_g0 = take(sizeof(float) * WSPLIT * H * D0), o_g1 = take(sizeof(float) * H);
+    const size_t o_g2 = take(sizeof(float) * WSPLIT * H * H), o_g3 = take(sizeof(float) * H);
+    const size_t o_g4 = take(sizeof(float) * WSPLIT * Cp * H), o_g5 = take(sizeof(float) * Cp);
+    const size_t o_pm = take(sizeof(float) * ntile * Fc), o_zg = take(sizeof(float) * Fc * Rp);
+    const size_t o_zgf = take(sizeof(_Float16) * Fc * Rp), o_zgs = take(sizeof(float) * Fc);
+    if (pr->ws_bytes < off) {
+        if (pr->ws) {
+            SP_HIP(hipStreamSynchronize(s));
+            (void)hipFree(pr->ws);
+            pr->ws = nullptr;
+            pr->ws_bytes = 0;
+        }
+        if (hipMalloc(&pr->ws, off) != hipSuccess) {
+            pr->ws = nullptr;
+            fail(SVDPHAT_E_NOMEM, "proposal workspace of " + std::to_string(off) + " bytes");
+        }
+        pr->ws_bytes = off;
+    }
+    char* w = (char*)pr->ws;
+    PW o;
+    o.Fc = Fc;
+    o.zpart = (float*)(w + o_zp);
+    o.z32 = (float*)(w + o_z);
+    o.zsc = (float*)(w + o_sc);
+    o.zn = (float*)(w + o_zn);
+    o.zfrag = (_Float16*)(w + o_zf);
+    o.feat = (_Float16*)(w + o_ft);
+    o.a1 = (float*)(w + o_a1);
+    o.h1 = (_Float16*)(w + o_h1);
+    o.a2 = (float*)(w + o_a2);
+    o.h2 = (_Float16*)(w + o_h2);
+    o.logits = (float*)(w + o_lg);
+    o.dlog = (_Float16*)(w + o_dl);
+    o.d2 = (_Float16*)(w + o_d2);
+    o.d1 = (_Float16*)(w + o_d1);
+    o.loss = (float*)(w + o_ls);
+    o.lab = (int32_t*)(w + o_lab);
+    o.doa = (int32_t*)(w + o_doa);
+    o.pw = (float*)(w + o_pw);
+    o.flist = (int32_t*)(w + o_fl);
+    o.g[0] = (float*)(w + o_g0);
+    o.g[1] = (float*)(w + o_g1);
+    o.g[2] = (float*)(w + o_g2);
+    o.g[3] = (float*)(w + o_g3);
+    o.g[4] = (float*)(w + o_g4);
+    o.g[5] = (float*)(w + o_g5);
+    o.pmax = (float*)(w + o_pm);
+    o.zg32 = (float*)(w + o_zg);
+    o.zgfrag = (_Float16*)(w + o_zgf);
+    o.zgsc = (float*)(w + o_zgs);
+    return o;
+}
+
+// forward pass on features o.feat for F frames -> o.logits
+void forward(svdphat_proposal* pr, const PW& o, int64_t F, hipStream_t s) {
+    const int H = pr->H, Cp = pr->Cp, D0 = pr->D0;
+    mlp_gemm<false, false, EPI_GELU>(o.feat, D0, pr->Wh[0], D0, (int)F, H, D0, 1, pr->P + pr->off[1], nullptr, o.a1,
+                                     o.h1, H, s);
+    mlp_gemm<false, false, EPI_GELU>(o.h1, H, pr->Wh[1], H, (int)F, H, H, 1, pr->P + pr->off[3], nullptr, o.a2, o.h2,
+                                     H, s);
+    mlp_gemm<false, false, EPI_BIAS>(o.h2, H, pr->Wh[2], H, (int)F, Cp, H, 1, pr->P + pr->off[5], nullptr, o.logits,
+                                     nullptr, Cp, s);
+}
+
+// backward pass from o.dlog (summed over frames) -> gradient partials o.g
+void backward(svdphat_proposal* pr, const PW& o, int64_t F, hipStream_t s) {
+    const int H = pr->H, Cp = pr->Cp, D0 = pr->D0;
+    const int ks = std::max(1, std::min(WSPLIT, (int)((F + 255) / 256)));
+    auto zero = [&](float* g, size_t n) { SP_HIP(hipMemsetAsync(g, 0, n * sizeof(float), s)); };
+    // layer 3: dW3[c][h] = sum_f dlog[f][c] h2[f][h]; db3; dh2 = dlog W3, da2 = dh2 GELU'(a2)
+    zero(o.g[4], (size_t)WSPLIT * Cp * H);
+    mlp_gemm<true, true, EPI_F32>(o.dlog, Cp, o.h2, H, Cp, H, (int)F, ks, nullptr, nullptr, o.g[4], nullptr, H, s);
+    k_colsum<<<dim3(cdiv(Cp, 256)), 256, 0, s>>>(o.dlog, F, Cp, Cp, o.g[5]);
+    mlp_gemm<false, false, EPI_DGELU>(o.dlog, Cp, pr->Wt[2], Cp, (int)F, H, Cp, 1, nullptr, o.a2, nullptr, o.d2, H, s);
+    // layer 2
+    zero(o.g[2], (size_t)WSPLIT * H * H);
+    mlp_gemm<true, true, EPI_F32>(o.d2, H, o.h1, H, H, H, (int)F, ks, nullptr, nullptr, o.g[2], nullptr, H, s);
+    k_colsum<<<dim3(cdiv(H, 256)), 256, 0, s>>>(o.d2, F, H, H, o.g[3]);
+    mlp_gemm<false, false, EPI_DGELU>(o.d2, H, pr->Wt[1], H, (int)F, H, H, 1, nullptr, o.a1, nullptr, o.d1, H, s);
+    // layer 1
+    zero(o.g[0], (size_t)WSPLIT * H * D0);
+    mlp_gemm<true, true, EPI_F32>(o.d1, H, o.feat, D0, H, D0, (int)F, ks, nullptr, nullptr, o.g[0], nullptr, D0, s);
+    k_colsum<<<dim3(cdiv(H, 256)), 256, 0, s>>>(o.d1, F, H, H, o.g[1]);
+    SP_HIP(hipGetLastError());
+}
+
+void adam(svdphat_proposal* pr, const PW& o, int64_t F, float lr, hipStream_t s) {
+    const int H = pr->H, Cp = pr->Cp, D0 = pr->D0;
+    pr->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - std::pow(b1, (float)pr->step), c2 = 1.f - std::pow(b2, (float)pr->step);
+    const int ks = std::max(1, std::min(WSPLIT, (int)((F + 255) / 256)));
+    AdamSeg seg[6] = {
+        {pr->off[0], H, D0, ks, o.g[0], pr->Wh[0], pr->Wt[0], D0, H},
+        {pr->off[1], H, 1, 1, o.g[1], nullptr, nullptr, 0, 0},
+        {pr->off[2], H, H, ks, o.g[2], pr->Wh[1], pr->Wt[1], H, H},
+        {pr->off[3], H, 1, 1, o.g[3], nullptr, nullptr, 0, 0},
+        {pr->off[4], Cp, H, ks, o.g[4], pr->Wh[2], pr->Wt[2], H, Cp},
+        {pr->off[5], Cp, 1, 1, o.g[5], nullptr, nullptr, 0, 0},
+    };
+    for (auto& sg : seg) {
+        const int64_t n = (int64_t)sg.rows * sg.cols;
+        k_adam<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(sg, pr->P, pr->Mm, pr->Vv, 1.f / (float)F, lr, b1,
+                                                                  b2, 1e-8f, c1, c2);
+    }
+    SP_HIP(hipGetLastError());
+}
+
+void cast_weights(svdphat_proposal* pr, hipStream_t s) {
+    const int H = pr->H, Cp = pr->Cp, D0 = pr->D0;
+    const int dims[3][2] = {{H, D0}, {H, H}, {Cp, H}};
+    const int offs[3] = {0, 2, 4};
+    for (int l = 0; l < 3; ++l) {
+        const int64_t n = (int64_t)dims[l][0] * dims[l][1];
+        k_cast_w<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(pr->P + pr->off[offs[l]], dims[l][0], dims[l][1],
+                                                                    pr->Wh[l], dims[l][1], pr->Wt[l], dims[l][0]);
+    }
+    SP_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void proposal_build(svdphat_proposal* pr, const double* coarse, int C, int H, uint64_t seed) {
+    svdphat_plan* p = pr->plan;
+    pr->C = C;
+    pr->Cp = round_up(C, 64);
+    pr->H = H;
+    pr->D = 2 * p->K;
+    pr->D0 = p->Rp;
+    SP_HIP(hipSetDevice(p->device));
+    // cell of every direction: nearest coarse direction (largest cosine; ties
+    // within 1e-12 to the lowest cell)
+    const int Q = p->Q;
+    std::vector<double> cu(3 * (size_t)C);
+    for (int c = 0; c < C; ++c) {
+        const double* v = coarse + 3 * c;
+        const double n = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        SP_REQUIRE(n > 0.0 && std::isfinite(n), SVDPHAT_E_INVAL, "zero or non-finite coarse direction");
+        for (int d = 0; d < 3; ++d) cu[3 * c + d] = v[d] / n;
+    }
+    pr->cell_of_dir.resize(Q);
+    std::vector<double> dots(C);
+    for (int q = 0; q < Q; ++q) {
+        const double* sq = &p->grid[3 * (size_t)q];
+        double best = -2.0;
+        for (int c = 0; c < C; ++c) {
+            dots[c] = sq[0] * cu[3 * c] + sq[1] * cu[3 * c + 1] + sq[2] * cu[3 * c + 2];
+            best = std::max(best, dots[c]);
+        }
+        int bc = 0;
+        while (dots[bc] < best - 1e-12) ++bc;
+        pr->cell_of_dir[q] = bc;
+    }
+    int64_t bytes = 0;
+    auto up = [&](const void* h, size_t n, void** d) {
+        if (hipMalloc(d, std::max<size_t>(n, 4)) != hipSuccess) {
+            *d = nullptr;
+            fail(SVDPHAT_E_NOMEM, "proposal allocation of " + std::to_string(n) + " bytes");
+        }
+        if (n) SP_HIP(hipMemcpy(*d, h, n, hipMemcpyHostToDevice));
+        bytes += (int64_t)n;
+    };
+    up(pr->cell_of_dir.data(), sizeof(int32_t) * Q, (void**)&pr->d_cell_of_dir);
+    // scored rows grouped by the cell of their direction (CSR)
+    std::vector<int32_t> start(C + 1, 0), rowsc(p->ncls);
+    for (int r = 0; r < p->ncls; ++r) ++start[pr->cell_of_dir[p->rows[r]] + 1];
+    for (int c = 0; c < C; ++c) start[c + 1] += start[c];
+    std::vector<int32_t> fillp(start.begin(), start.end() - 1);
+    for (int r = 0; r < p->ncls; ++r) rowsc[fillp[pr->cell_of_dir[p->rows[r]]]++] = r;
+    up(start.data(), sizeof(int32_t) * (C + 1), (void**)&pr->d_cell_start);
+    up(rowsc.data(), sizeof(int32_t) * p->ncls, (void**)&pr->d_cell_rows);
+    // FP32 stacked U rows, row-major [ncls][Rp]
+    std::vector<float> ur((size_t)p->ncls * p->Rp, 0.f);
+    const int K = p->K;
+    for (int r = 0; r < p->ncls; ++r) {
+        const int q = p->rows[r];
+        for (int k = 0; k < K; ++k) {
+            ur[(size_t)r * p->Rp + k] = (float)p->U[((size_t)q * K + k) * 2];
+            ur[(size_t)r * p->Rp + K + k] = (float)(-p->U[((size_t)q * K + k) * 2 + 1]);
+        }
+    }
+    up(ur.data(), sizeof(float) * ur.size(), (void**)&pr->d_U32R);
+    // parameters: W ~ N(0, 2 / fan_in) (real inputs), biases 0; padded
+    // input columns and padded cells stay 0
+    const int D0 = pr->D0, Cp = pr->Cp, D = pr->D;
+    pr->off[0] = 0;
+    pr->off[1] = pr->off[0] + (int64_t)H * D0;
+    pr->off[2] = pr->off[1] + H;
+    pr->off[3] = pr->off[2] + (int64_t)H * H;
+    pr->off[4] = pr->off[3] + H;
+    pr->off[5] = pr->off[4] + (int64_t)Cp * H;
+    pr->nparam = pr->off[5] + Cp;
+    std::vector<float> P0(pr->nparam, 0.f);
+    std::mt19937_64 g(seed);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (int h = 0; h < H; ++h)
+        for (int k = 0; k < D; ++k) P0[pr->off[0] + (int64_t)h * D0 + k] = (float)(nd(g) * std::sqrt(2.0 / D));
+    for (int h = 0; h < H; ++h)
+        for (int k = 0; k < H; ++k) P0[pr->off[2] + (int64_t)h * H + k] = (float)(nd(g) * std::sqrt(2.0 / H));
+    for (int c = 0; c < C; ++c)
+        for (int k = 0; k < H; ++k) P0[pr->off[4] + (int64_t)c * H + k] = (float)(nd(g) * std::sqrt(1.0 / H));
+    // padded cells: large negative bias so that they never win
+    for (int c = C; c < Cp; ++c) P0[pr->off[5] + c] = -1e4f;
+    up(P0.data(), sizeof(float) * pr->nparam, (void**)&pr->P);
+    std::vector<float> zeros(pr->nparam, 0.f);
+    up(zeros.data(), sizeof(float) * pr->nparam, (void**)&pr->Mm);
+    up(zeros.data(), sizeof(float) * pr->nparam, (void**)&pr->Vv);
+    const size_t wsz[3] = {(size_t)H * D0, (size_t)H * H, (size_t)Cp * H};
+    for (int l = 0; l < 3; ++l) {
+        SP_HIP(hipMalloc((void**)&pr->Wh[l], wsz[l] * sizeof(_Float16)));
+        SP_HIP(hipMalloc((void**)&pr->Wt[l], wsz[l] * sizeof(_Float16)));
+    }
+    SP_HIP(hipMalloc((void**)&pr->d_count, 4 * sizeof(int)));
+    cast_weights(pr, nullptr);
+    SP_HIP(hipDeviceSynchronize());
+}
+
+float proposal_train_step(svdphat_proposal* pr, const float2* X, int64_t F, float lr, hipStream_t s) {
+    svdphat_plan* p = pr->plan;
+    PW o = carve(pr, F, s);
+    // labels: the cell of the method's own argmax (FP16, rescored, hi/lo)
+    launch_locate(p, X, F, P_FP16, SVDPHAT_RESCORE | SVDPHAT_HILO, o.doa, o.pw, nullptr, nullptr, nullptr, s);
+    k_labels<<<dim3((unsigned)((F + 255) / 256)), 256, 0, s>>>(o.doa, pr->d_cell_of_dir, F, o.lab);
+    front_fp16(p, X, F, o.zpart, o.z32, o.zfrag, o.zsc, o.zn, s);
+    k_features<<<dim3((unsigned)((F * p->Rp + 255) / 256)), 256, 0, s>>>(o.z32, o.zn, F, p->Rp, o.feat);
+    forward(pr, o, F, s);
+    k_xent<<<dim3((unsigned)((F + 3) / 4)), 256, 0, s>>>(o.logits, pr->Cp, pr->C, o.lab, F, o.dlog, o.loss);
+    SP_HIP(hipGetLastError());
+    backward(pr, o, F, s);
+    adam(pr, o, F, lr, s);
+    std::vector<float> loss(F);
+    SP_HIP(hipMemcpyAsync(loss.data(), o.loss, sizeof(float) * F, hipMemcpyDeviceToHost, s));
+    SP_HIP(hipStreamSynchronize(s));
+    double sum = 0.0;
+    for (float v : loss) sum += v;
+    return (float)(sum / (double)F);
+}
+
+void proposal_locate(svdphat_proposal* pr, const float2* X, int64_t F, int topk, float conf_min, int32_t* doa,
+                     float* power, uint8_t* fell, hipStream_t s) {
+    svdphat_plan* p = pr->plan;
+    PW o = carve(pr, F, s);
+    KernelTimer kt(s);
+    kt.begin("prop_front");
+    front_fp16(p, X, F, o.zpart, o.z32, o.zfrag, o.zsc, o.zn, s);
+    kt.end();
+    kt.begin("prop_mlp");
+    k_features<<<dim3((unsigned)((F * p->Rp + 255) / 256)), 256, 0, s>>>(o.z32, o.zn, F, p->Rp, o.feat);
+    forward(pr, o, F, s);
+    kt.end();
+    SP_HIP(hipMemsetAsync(pr->d_count, 0, sizeof(int), s));
+    kt.begin("prop_rescore");
+    if (p->M <= 8)
+        k_propose<8><<<dim3((unsigned)((F + 3) / 4)), 256, 0, s>>>(
+            o.logits, pr->Cp, pr->C, topk, conf_min, o.z32, p->Rp, pr->d_U32R, pr->d_cell_start, pr->d_cell_rows,
+            p->d_rows, X, p->M, p->P, p->B, p->d_tauN_all, F, doa, power, fell, o.flist, pr->d_count);
+    else
+        k_propose<16><<<dim3((unsigned)((F + 3) / 4)), 256, 0, s>>>(
+            o.logits, pr->Cp, pr->C, topk, conf_min, o.z32, p->Rp, pr->d_U32R, pr->d_cell_start, pr->d_cell_rows,
+            p->d_rows, X, p->M, p->P, p->B, p->d_tauN_all, F, doa, power, fell, o.flist, pr->d_count);
+    SP_HIP(hipGetLastError());
+    kt.end();
+    // low-confidence frames: the full search on the listed frames only
+    kt.begin("prop_fallback");
+    k_gather_z<<<dim3((unsigned)(o.Fc / 4)), 256, 0, s>>>(o.flist, pr->d_count, o.z32, p->Rp, o.zg32, o.zgfrag,
+                                                          o.zgsc);
+    SP_HIP(hipGetLastError());
+    back_list_fp16(p, X, F, o.flist, pr->d_count, o.zgfrag, o.zgsc, o.zg32, o.zn, o.pmax, o.Fc, doa, power, nullptr,
+                   s);
+    kt.end();
+    kt.flush();
+}
+
+// host parameters in the layout W1 [H][D], b1 [H], W2 [H][H], b2 [H],
+// W3 [C][H], b3 [C] (no padding)
+int64_t proposal_nparams(const svdphat_proposal* pr) {
+    const int64_t H = pr->H, D = pr->D, C = pr->C;
+    return H * D + H + H * H + H + C * H + C;
+}
+
+void proposal_params(svdphat_proposal* pr, float* host, bool set) {
+    const int H = pr->H, D = pr->D, D0 = pr->D0, C = pr->C;
+    std::vector<float> P(pr->nparam);
+    SP_HIP(hipMemcpy(P.data(), pr->P, sizeof(float) * pr->nparam, hipMemcpyDeviceToHost));
+    int64_t h = 0;
+    auto xfer = [&](int64_t dst, int rows, int cols, int ld) {
+        for (int r = 0; r < rows; ++r)
+            for (int c = 0; c < cols; ++c, ++h) {
+                if (set) P[dst + (int64_t)r * ld + c] = host[h];
+                else host[h] = P[dst + (int64_t)r * ld + c];
+            }
+    };
+    xfer(pr->off[0], H, D, D0);
+    xfer(pr->off[1], 1, H, H);
+    xfer(pr->off[2], H, H, H);
+    xfer(pr->off[3], 1, H, H);
+    xfer(pr->off[4], C, H, H);
+    xfer(pr->off[5], 1, C, C);
+    if (set) {
+        SP_HIP(hipMemcpy(pr->P, P.data(), sizeof(float) * pr->nparam, hipMemcpyHostToDevice));
+        cast_weights(pr, nullptr);
+        SP_HIP(hipDeviceSynchronize());
+    }
+}
+
+// gradient of the mean cross-entropy for host features [F][D] and labels,
+// in the host parameter layout (testing aid)
+float proposal_grad(svdphat_proposal* pr, const float* feat, const int32_t* lab, int64_t F, float* grad) {
+    const int H = pr->H, D = pr->D, D0 = pr->D0, C = pr->C, Cp = pr->Cp;
+    hipStream_t s = nullptr;
+    PW o = carve(pr, F, s);
+    std::vector<_Float16> fh((size_t)F * D0, (_Float16)0.f);
+    for (int64_t f = 0; f < F; ++f)
+        for (int k = 0; k < D; ++k) fh[(size_t)f * D0 + k] = (_Float16)feat[(size_t)f * D + k];
+    SP_HIP(hipMemcpy(o.feat, fh.data(), sizeof(_Float16) * fh.size(), hipMemcpyHostToDevice));
+    SP_HIP(hipMemcpy(o.lab, lab, sizeof(int32_t) * F, hipMemcpyHostToDevice));
+    forward(pr, o, F, s);
+    k_xent<<<dim3((unsigned)((F + 3) / 4)), 256, 0, s>>>(o.logits, Cp, C, o.lab, F, o.dlog, o.loss);
+    backward(pr, o, F, s);
+    SP_HIP(hipDeviceSynchronize());
+    const int ks = std::max(1, std::min(WSPLIT, (int)((F + 255) / 256)));
+    // partials are [parts][prow][ld]; the first rows x cols are returned
+    auto fetch = [&](const float* g, int rows, int cols, int prow, int ld, int parts, int64_t& h) {
+        std::vector<float> t((size_t)parts * prow * ld);
+        SP_HIP(hipMemcpy(t.data(), g, sizeof(float) * t.size(), hipMemcpyDeviceToHost));
+        for (int r = 0; r < rows; ++r)
+            for (int c = 0; c < cols; ++c, ++h) {
+                double v = 0.0;
+                for (int q = 0; q < parts; ++q) v += t[(size_t)q * prow * ld + (size_t)r * ld + c];
+                grad[h] = (float)(v / (double)F);
+            }
+    };
+    int64_t h = 0;
+    fetch(o.g[0], H, D, H, D0, ks, h);
+    fetch(o.g[1], 1, H, 1, H, 1, h);
+    fetch(o.g[2], H, H, H, H, ks, h);
+    fetch(o.g[3], 1, H, 1, H, 1, h);
+    fetch(o.g[4], C, H, Cp, H, ks, h);
+    fetch(o.g[5], 1, C, 1, Cp, 1, h);
+    std::vector<float> loss(F);
+    SP_HIP(hipMemcpy(loss.data(), o.loss, sizeof(float) * F, hipMemcpyDeviceToHost));
+    double sum = 0.0;
+    for (float v : loss) sum += v;
+    return (float)(sum / (double)F);
+}
+
+void proposal_free(svdphat_proposal* pr) {
+    if (!pr) return;
+    void* bufs[] = {pr->d_cell_of_dir, pr->d_cell_start, pr->d_cell_rows, pr->d_U32R, pr->P, pr->Mm, pr->Vv,
+                    pr->ws, pr->d_count, pr->Wh[0], pr->Wh[1], pr->Wh[2], pr->Wt[0], pr->Wt[1], pr->Wt[2]};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    delete pr;
+}
+
+}  // namespace svdphat

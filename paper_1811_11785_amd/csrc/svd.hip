@@ -297,7 +297,9 @@ template <typename T, int KSN, bool UREG>
 __device__ __forceinline__ void gemm2_body(int bx, int by, const T* __restrict__ U, int KSn,
                                            const T* __restrict__ zfrag, int64_t nfr, int fch, int ncls, int ntile,
                                            const float* __restrict__ zscale, float uinv, float* __restrict__ pmax,
-                                           int64_t pstride, float* __restrict__ ycls, int64_t yld) {
+                                           int64_t pstride, float* __restrict__ ycls, int64_t yld,
+                                           const int* __restrict__ fmap = nullptr,
+                                           const int* __restrict__ fcount = nullptr) {
     constexpr int EPL = Mf<T>::EPL;
     typedef typename Vec<T>::t VT;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -305,7 +307,8 @@ __device__ __forceinline__ void gemm2_body(int bx, int by, const T* __restrict__
     if (tile >= ntile) return;
     const int rb0 = tile * 4;
     const int64_t fbeg = (int64_t)by * fch;
-    const int64_t fend = min<int64_t>(nfr, fbeg + fch);
+    const int64_t fend = min<int64_t>(fcount ? (int64_t)*fcount : nfr, fbeg + fch);
+    if (fbeg >= fend) return;
     VT a[4][UREG ? KSN : 1];
     if (UREG) {
 #pragma unroll
@@ -365,7 +368,7 @@ __device__ __forceinline__ void gemm2_body(int bx, int by, const T* __restrict__
                 if (rowok[i][e]) m = fmaxf(m, acc[i][e]);
         m = fmaxf(m, __shfl_xor(m, 16));
         m = fmaxf(m, __shfl_xor(m, 32));
-        if (lane < 16 && live) pmax[(int64_t)tile * pstride + f] = m * inv;
+        if (lane < 16 && live) pmax[(int64_t)tile * pstride + (fmap ? (int64_t)fmap[f] : f)] = m * inv;
         if (ycls && live) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
@@ -386,6 +389,18 @@ __global__ __launch_bounds__(256) void k_gemm2(const T* __restrict__ U, int KSn,
                                                int64_t yld) {
     gemm2_body<T, KSN, UREG>(blockIdx.x, blockIdx.y, U, KSn, zfrag, nfr, fch, ncls, ntile, zscale, uinv, pmax,
                              pstride, ycls, yld);
+}
+
+// GEMM2 over a list of frames: position f of zfrag holds frame fmap[f];
+// the count is read on the device.
+template <int KSN, bool UREG>
+__global__ __launch_bounds__(256) void k_gemm2_list(const _Float16* __restrict__ U, int KSn,
+                                                    const _Float16* __restrict__ zfrag, int64_t nmax, int fch,
+                                                    int ncls, int ntile, const float* __restrict__ zscale, float uinv,
+                                                    float* __restrict__ pmax, int64_t pstride,
+                                                    const int* __restrict__ fmap, const int* __restrict__ fcount) {
+    gemm2_body<_Float16, KSN, UREG>(blockIdx.x, blockIdx.y, U, KSn, zfrag, nmax, fch, ncls, ntile, zscale, uinv,
+                                    pmax, pstride, nullptr, 0, fmap, fcount);
 }
 
 // ------------------------------------------------------------------ final
@@ -576,77 +591,8 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
         redo = (y1 - yr) < a.hilo_k * a.u * sqrtf(d2);
     }
 
-    // Algorithm 1 online step 4: power of the chosen direction from its row
-    // of W, Y = Re sum_{p,k} exp(2 pi i k tau_p / N) x_{p,k}
-    const float* tq = a.tauN + (int64_t)cls * a.P;
-    const float2* xf = a.X + f * a.M * a.B;
-    float acc = 0.f;
-    if (MAXM <= 8) {
-        // each lane takes bins b0 + lane + 64 j, j < NJ; the phase of bin
-        // b + 64 follows from that of bin b by one complex multiplication
-        constexpr int NJ = 5;
-        for (int b0 = 0; b0 < a.B; b0 += 64 * NJ) {
-            float nr[NJ][MAXM], ni[NJ][MAXM];
-#pragma unroll
-            for (int j = 0; j < NJ; ++j)
-#pragma unroll
-                for (int m = 0; m < MAXM; ++m) {
-                    const int bin = b0 + lane + 64 * j;
-                    float2 v = (bin < a.B && m < a.M) ? xf[(int64_t)m * a.B + bin] : float2{0.f, 0.f};
-                    nr[j][m] = v.x;
-                    ni[j][m] = v.y;
-                    unit(nr[j][m], ni[j][m]);
-                }
-            int p = 0;
-#pragma unroll
-            for (int i = 0; i < MAXM; ++i)
-#pragma unroll
-                for (int k = i + 1; k < MAXM; ++k)
-                    if (k < a.M) {
-                        const float tn = tq[p];
-                        float t0 = (float)(b0 + lane) * tn;
-                        t0 -= rintf(t0);
-                        float t1 = 64.f * tn;
-                        t1 -= rintf(t1);
-                        float wr = __builtin_amdgcn_cosf(t0), wi = __builtin_amdgcn_sinf(t0);
-                        const float sr = __builtin_amdgcn_cosf(t1), si = __builtin_amdgcn_sinf(t1);
-#pragma unroll
-                        for (int j = 0; j < NJ; ++j) {
-                            const float xr = nr[j][i] * nr[j][k] + ni[j][i] * ni[j][k];
-                            const float xi = ni[j][i] * nr[j][k] - nr[j][i] * ni[j][k];
-                            acc = fmaf(wr, xr, fmaf(-wi, xi, acc));
-                            const float nwr = wr * sr - wi * si;
-                            wi = wr * si + wi * sr;
-                            wr = nwr;
-                        }
-                        ++p;
-                    }
-        }
-    } else {
-        for (int bin = lane; bin < a.B; bin += 64) {
-            float re[MAXM], im[MAXM];
-#pragma unroll
-            for (int m = 0; m < MAXM; ++m) {
-                const float2 v = m < a.M ? xf[(int64_t)m * a.B + bin] : float2{0.f, 0.f};
-                re[m] = v.x;
-                im[m] = v.y;
-                unit(re[m], im[m]);
-            }
-            int p = 0;
-#pragma unroll
-            for (int i = 0; i < MAXM; ++i)
-#pragma unroll
-                for (int k = i + 1; k < MAXM; ++k)
-                    if (k < a.M) {
-                        const float xr = re[i] * re[k] + im[i] * im[k];
-                        const float xi = im[i] * re[k] - re[i] * im[k];
-                        float t = (float)bin * tq[p];
-                        t -= rintf(t);
-                        acc = fmaf(__builtin_amdgcn_cosf(t), xr, fmaf(-__builtin_amdgcn_sinf(t), xi, acc));
-                        ++p;
-                    }
-        }
-    }
+    // Algorithm 1 online step 4: power of the chosen direction from its row of W
+    float acc = direction_power<MAXM>(a.X + f * a.M * a.B, a.M, a.B, a.tauN + (int64_t)cls * a.P, lane);
     acc = wave_sum(acc);
     if (lane == 0) {
         a.doa[f] = cls;
@@ -962,6 +908,79 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
 
 }  // namespace
 
+
+
+// GEMM1 + Z prep in FP16 into caller buffers (zpart holds zpart_floats()).
+int64_t front_zpart_floats(const svdphat_plan* p, int64_t F) {
+    int nsplit, cps;
+    g1_split_layout(p->g1[P_FP16], p->Rp, F, 0, &nsplit, &cps);
+    return (int64_t)nsplit * round_up64(F, 64) * p->Rp;
+}
+
+void front_fp16(svdphat_plan* p, const float2* X, int64_t F, float* zpart, float* z32, _Float16* zfrag, float* zsc,
+                float* zn, hipStream_t s) {
+    const G1Layout& g = p->g1[P_FP16];
+    const int64_t Fc = round_up64(F, 64);
+    int nsplit, cps;
+    g1_split_layout(g, p->Rp, F, 0, &nsplit, &cps);
+    launch_g1<_Float16, 64, false>((int)(Fc / 64), nsplit, s, X, F, p, P_FP16, g, cps, zpart, Fc * p->Rp, nullptr,
+                                   nullptr);
+    SP_HIP(hipGetLastError());
+    k_zprep<_Float16><<<dim3((unsigned)(Fc / 4)), 256, 0, s>>>(zpart, nsplit, Fc * p->Rp, F, nullptr, p->Rp, z32,
+                                                               zfrag, zsc, zn, 1);
+    SP_HIP(hipGetLastError());
+}
+
+// GEMM2 (FP16) over the frames listed in flist (positions of zfrag hold
+// those frames) and the FP32-rescored search for them (pmax frame-indexed,
+// z32 position-indexed, znorm frame-indexed).
+void back_list_fp16(svdphat_plan* p, const float2* X, int64_t Fmax, const int* flist, const int* fcount,
+                    const _Float16* zfrag, const float* zsc, const float* z32pos, const float* zn_frame,
+                    float* pmax, int64_t pstride, int32_t* doa, float* power, float* margin, hipStream_t s) {
+    const int KSn = p->Rp / Mf<_Float16>::KSTEP;
+    const int ntile = p->ncls_pad / QTILE;
+    const int fch = 256;
+    dim3 grid(cdiv(ntile, 4), (unsigned)((Fmax + fch - 1) / fch));
+    const float uinv = 1.f / p->uscale[P_FP16];
+    if (KSn <= 6)
+        k_gemm2_list<6, true><<<grid, 256, 0, s>>>((const _Float16*)p->Ufr[P_FP16], KSn, zfrag, Fmax, fch, p->ncls,
+                                                   ntile, zsc, uinv, pmax, pstride, flist, fcount);
+    else
+        k_gemm2_list<1, false><<<grid, 256, 0, s>>>((const _Float16*)p->Ufr[P_FP16], KSn, zfrag, Fmax, fch, p->ncls,
+                                                    ntile, zsc, uinv, pmax, pstride, flist, fcount);
+    SP_HIP(hipGetLastError());
+    FinalArgs fa{};
+    fa.X = X;
+    fa.M = p->M;
+    fa.P = p->P;
+    fa.B = p->B;
+    fa.pmax = pmax;
+    fa.pstride = pstride;
+    fa.ntile = ntile;
+    fa.ncls = p->ncls;
+    fa.z32 = z32pos;
+    fa.znorm1 = zn_frame;
+    fa.Rp = p->Rp;
+    const double u = std::ldexp(1.0, -11);
+    fa.ecoef = (float)((2.0 * u + u * u + 2.0 * p->Rp * std::ldexp(1.0, -24)) * 1.01);
+    fa.rescore = 1;
+    fa.U32T = p->U32T;
+    fa.tkappa = p->d_tkappa;
+    fa.sig = p->d_sig;
+    fa.rows = p->d_rows;
+    fa.rep = p->d_rep;
+    fa.tauN = p->d_tauN_all;
+    fa.nfr = Fmax;
+    fa.flist = flist;
+    fa.fcount = fcount;
+    fa.doa = doa;
+    fa.power = power;
+    fa.margin = margin;
+    fa.hilo_k = 4.f;
+    fa.u = (float)u;
+    launch_final(fa, p->M, !(p->flags & SVDPHAT_NO_DEDUP), Fmax, s);
+    SP_HIP(hipGetLastError());
+}
 
 int g1_nrb_class(int nRB) {
     const int w = nRB <= 12 ? nRB : 12;
