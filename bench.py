@@ -81,7 +81,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--workload", default="planar_q10242",
-                    help="planar_q10242 (default, the headline line) or ragged256")
+                    help="planar_q10242 (default, the headline line), ragged256 or proposal_q40962")
+    ap.add_argument("--train-frames", type=int, default=2_000_000, help="training pairs of the proposal")
     ap.add_argument("--arrays", type=int, default=256, help="arrays of the ragged workload")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MB (a known-size reference "
@@ -101,6 +102,8 @@ def main():
     amd.lib()
     if args.workload == "ragged256":
         return bench_ragged(args, torch, amd, synth)
+    if args.workload == "proposal_q40962":
+        return bench_proposal(args, torch, amd, synth)
     if args.calib_copy_mb:
         n = args.calib_copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -296,6 +299,65 @@ def bench_ragged(args, torch, amd, synth):
         "single_call_fps": single_fps, "speedup_vs_single_calls": fps / single_fps,
         "doa_agreement_with_single_calls": agree, "tuned_shapes": tuned, "cached_shapes": cached,
         "plan_build_s": plan_s, "ragged_build_s": tune_s,
+    }
+    print(json.dumps(out))
+
+
+def bench_proposal(args, torch, amd, synth):
+    """Learned proposal on the planar array at Q = 40962 (icosphere level 6)
+    with 642 coarse cells (level 3): trained on the method's own labels, then
+    timed against the full search on fresh frames."""
+    mics = synth.geometry("2d")
+    fine, coarse = synth.icosphere(6), synth.icosphere(3)
+    t0 = time.perf_counter()
+    plan = amd.Plan(mics, fine, 16000.0, 343.0, 512, 1e-5)
+    plan_s = time.perf_counter() - t0
+    prop = amd.Proposal(plan, coarse, hidden=256, seed=1)
+    log(f"plan {plan_s:.1f} s, K={plan.info['K']}, classes={plan.info['n_classes']}")
+    batch = 8192
+    nsteps = max(1, args.train_frames // batch)
+    t0 = time.perf_counter()
+    losses = []
+    for step in range(nsteps):
+        X = synth.plane_wave_fd_torch(mics, batch // 64, 64, 512, 16000.0, 343.0, seed=5_000_000 + step)
+        lr = 2e-3 if step < int(0.7 * nsteps) else 5e-4
+        losses.append(prop.train_step(X, lr=lr))
+        if step % 50 == 0:
+            log(f"train step {step}/{nsteps} loss {losses[-1]:.3f}")
+    train_s = time.perf_counter() - t0
+    # evaluation: 20000 fresh frames, SNR U[-5, 20] dB, 100-frame segments
+    X = synth.plane_wave_fd_torch(mics, 200, 100, 512, 16000.0, 343.0, seed=9_999_999)
+    F = X.shape[0]
+    dev = X.device
+    doa = torch.empty(F, dtype=torch.int32, device=dev)
+    power = torch.empty(F, dtype=torch.float32, device=dev)
+    fell = torch.empty(F, dtype=torch.uint8, device=dev)
+    yhat = torch.empty(F, dtype=torch.float32, device=dev)
+    margin = torch.empty(F, dtype=torch.float32, device=dev)
+    fdoa = torch.empty(F, dtype=torch.int32, device=dev)
+    h = plan.handle
+    prop_step = lambda: amd.lib().svdphat_proposal_locate(prop._h, amd._ptr(X), F, 8, 0.5, amd._ptr(doa),
+                                                          amd._ptr(power), amd._ptr(fell), amd._stream(None))
+    full_step = lambda: amd.svdphat_locate(h, X, amd.FP16, amd.RESCORE | amd.HILO, fdoa, power, yhat, margin)
+    _timed(prop_step, args.warmup, torch)
+    dtp = _timed(prop_step, args.steps, torch)
+    pdoa, pfell = doa.cpu().numpy(), fell.cpu().numpy().astype(bool)
+    _timed(full_step, args.warmup, torch)
+    dtf = _timed(full_step, args.steps, torch)
+    full = fdoa.cpu().numpy()
+    out = {
+        "metric": "frames/s, learned proposal vs full search (planar, Q=40962)",
+        "value": F * args.steps / dtp, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dtp / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp16", "data": "synthetic",
+        "config": {"workload": "proposal_q40962", "Q": 40962, "cells": 642, "hidden": 256,
+                   "K": plan.info["K"], "frames_per_step": F, "train_pairs": nsteps * batch,
+                   "topk": 8, "conf_min": 0.5},
+        "full_search_fps": F * args.steps / dtf, "speedup_vs_full_search": dtf / dtp,
+        "miss_rate_vs_full_search": float(np.mean(pdoa != full)),
+        "fallback_rate": float(pfell.mean()),
+        "miss_rate_confident_frames": float(np.mean(pdoa[~pfell] != full[~pfell])) if (~pfell).any() else 0.0,
+        "final_loss": float(np.mean(losses[-10:])), "train_s": train_s, "plan_build_s": plan_s,
     }
     print(json.dumps(out))
 

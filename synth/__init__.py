@@ -286,3 +286,33 @@ def ragged_workload(n_arrays: int = 256, seed_offset: int = 0, frames_range=(64,
                           snr_db=rng.uniform(0.0, 20.0)).astype(np.complex64)
         out.append(dict(mics=mics, level=level, delta=delta, X=np.ascontiguousarray(X)))
     return out
+
+
+def plane_wave_fd_torch(mics, n_seg: int, seg_frames: int, N: int, fs: float, c: float, seed: int,
+                        snr_range=(-5.0, 20.0), device="cuda"):
+    """Frequency-domain plane waves generated directly on a torch device:
+    ``n_seg`` segments of ``seg_frames`` frames, each segment with its own
+    uniformly random direction and SNR (dB, uniform in ``snr_range``);
+    X_m[k] = S[k] exp(+2 pi i k a_m / N) + n_m[k], a_m = fs r_m . u / c,
+    S and n complex Gaussian.  Returns complex64 [n_seg * seg_frames, M, N/2+1]."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    M = mics.shape[0]
+    B = N // 2 + 1
+    F = n_seg * seg_frames
+    u = torch.randn(n_seg, 3, generator=g, device=device, dtype=torch.float64)
+    u = u / u.norm(dim=1, keepdim=True)
+    snr = torch.rand(n_seg, generator=g, device=device, dtype=torch.float64) * (snr_range[1] - snr_range[0]) + snr_range[0]
+    r = torch.as_tensor(np.asarray(mics, dtype=np.float64), device=device)
+    adv = fs * (u @ r.T) / c                                   # [n_seg, M]
+    k = torch.arange(B, device=device, dtype=torch.float64)
+    ph = torch.exp(2j * np.pi * adv[:, :, None] * k[None, None, :] / N)   # [n_seg, M, B]
+    ph = ph.repeat_interleave(seg_frames, dim=0)
+    S = torch.complex(torch.randn(F, B, generator=g, device=device),
+                      torch.randn(F, B, generator=g, device=device)) / np.sqrt(2.0)
+    sd = torch.sqrt(10.0 ** (-snr / 10.0) / 2.0).repeat_interleave(seg_frames).to(torch.float32)
+    noise = torch.complex(torch.randn(F, M, B, generator=g, device=device),
+                          torch.randn(F, M, B, generator=g, device=device)) * sd[:, None, None]
+    X = S[:, None, :] * ph.to(torch.complex64) + noise
+    return X.contiguous()
