@@ -163,4 +163,72 @@ __device__ __forceinline__ float direction_power(const float2* __restrict__ xf, 
     return acc;
 }
 
+
+// The STFT values one lane needs for direction_power, loaded early (before
+// the direction is known) so that their latency overlaps other work; used
+// when the frame has at most 5 x 64 bins and at most 8 microphones.
+template <int MAXM>
+struct PowerPrefetch {
+    static constexpr bool kRegs = MAXM <= 8;
+    static constexpr int NJ = 5;
+    float2 v[kRegs ? NJ : 1][kRegs ? MAXM : 1];
+    bool ok = false;
+    __device__ __forceinline__ void load(const float2* __restrict__ xf, int M, int B, int lane) {
+        if constexpr (kRegs) {
+            ok = B <= 64 * NJ;
+            if (!ok) return;
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                for (int m = 0; m < MAXM; ++m) {
+                    const int bin = lane + 64 * j;
+                    v[j][m] = (bin < B && m < M) ? xf[(int64_t)m * B + bin] : float2{0.f, 0.f};
+                }
+        }
+    }
+    __device__ __forceinline__ float power(const float2* __restrict__ xf, int M, int B,
+                                           const float* __restrict__ tq, int lane) {
+        if constexpr (kRegs) {
+            if (ok) {
+                float nr[NJ][MAXM], ni[NJ][MAXM];
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                    for (int m = 0; m < MAXM; ++m) {
+                        nr[j][m] = v[j][m].x;
+                        ni[j][m] = v[j][m].y;
+                        unit(nr[j][m], ni[j][m]);
+                    }
+                float acc = 0.f;
+                int p = 0;
+#pragma unroll
+                for (int i = 0; i < MAXM; ++i)
+#pragma unroll
+                    for (int k = i + 1; k < MAXM; ++k)
+                        if (k < M) {
+                            const float tn = tq[p];
+                            float t0 = (float)lane * tn;
+                            t0 -= rintf(t0);
+                            float t1 = 64.f * tn;
+                            t1 -= rintf(t1);
+                            float wr = __builtin_amdgcn_cosf(t0), wi = __builtin_amdgcn_sinf(t0);
+                            const float sr = __builtin_amdgcn_cosf(t1), si = __builtin_amdgcn_sinf(t1);
+#pragma unroll
+                            for (int j = 0; j < NJ; ++j) {
+                                const float xr = nr[j][i] * nr[j][k] + ni[j][i] * ni[j][k];
+                                const float xi = ni[j][i] * nr[j][k] - nr[j][i] * ni[j][k];
+                                acc = fmaf(wr, xr, fmaf(-wi, xi, acc));
+                                const float nwr = wr * sr - wi * si;
+                                wi = wr * si + wi * sr;
+                                wr = nwr;
+                            }
+                            ++p;
+                        }
+                return acc;
+            }
+        }
+        return direction_power<MAXM>(xf, M, B, tq, lane);
+    }
+};
+
 }  // namespace svdphat

@@ -81,7 +81,7 @@ struct G1Layout {
 struct FinalArgs {
     const float2* X;
     int M, P, B;
-    const float* pmax;      // [ntile][pstride]
+    const float* pmax;      // [frame][pstride] tile maxima
     int64_t pstride;
     int ntile, ncls;
     const float* z32;       // [pos][Rp] z used for rescoring
@@ -164,7 +164,7 @@ void front_fp16(svdphat_plan* p, const float2* X, int64_t F, float* zpart, float
                 float* zn, hipStream_t s);
 void back_list_fp16(svdphat_plan* p, const float2* X, int64_t Fmax, const int* flist, const int* fcount,
                     const _Float16* zfrag, const float* zsc, const float* z32pos, const float* zn_frame,
-                    float* pmax, int64_t pstride, int32_t* doa, float* power, float* margin, hipStream_t s);
+                    float* pmax, int32_t* doa, float* power, float* margin, hipStream_t s);
 void tune_time(svdphat_plan* p, int64_t F, int nsplit, int fch, double* us_g1, double* us_g2, hipStream_t s);
 
 struct Workspace {
@@ -241,6 +241,8 @@ struct svdphat_proposal {
 };
 
 namespace svdphat {
+// Row stride (floats) of the frame-major tile maxima: tiles padded to 32.
+inline int pmax_stride(const svdphat_plan* p) { return round_up(p->ncls_pad / QTILE, 32); }
 // launchers
 void launch_locate(svdphat_plan* p, const void* X, int64_t F, int prec, uint32_t mode,
                    int32_t* doa, float* power, float* yhat, float* margin, float* y_opt,

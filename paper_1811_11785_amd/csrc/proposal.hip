@@ -385,7 +385,7 @@ PW carve(svdphat_proposal* pr, int64_t F, hipStream_t s) {
     const size_t o_g0 = take(sizeof(float) * WSPLIT * H * D0), o_g1 = take(sizeof(float) * H);
     const size_t o_g2 = take(sizeof(float) * WSPLIT * H * H), o_g3 = take(sizeof(float) * H);
     const size_t o_g4 = take(sizeof(float) * WSPLIT * Cp * H), o_g5 = take(sizeof(float) * Cp);
-    const size_t o_pm = take(sizeof(float) * ntile * Fc), o_zg = take(sizeof(float) * Fc * Rp);
+    const size_t o_pm = take(sizeof(float) * pmax_stride(p) * Fc), o_zg = take(sizeof(float) * Fc * Rp);
     const size_t o_zgf = take(sizeof(_Float16) * Fc * Rp), o_zgs = take(sizeof(float) * Fc);
     if (pr->ws_bytes < off) {
         if (pr->ws) {
@@ -649,8 +649,7 @@ void proposal_locate(svdphat_proposal* pr, const float2* X, int64_t F, int topk,
     k_gather_z<<<dim3((unsigned)(o.Fc / 4)), 256, 0, s>>>(o.flist, pr->d_count, o.z32, p->Rp, o.zg32, o.zgfrag,
                                                           o.zgsc);
     SP_HIP(hipGetLastError());
-    back_list_fp16(p, X, F, o.flist, pr->d_count, o.zgfrag, o.zgsc, o.zg32, o.zn, o.pmax, o.Fc, doa, power, nullptr,
-                   s);
+    back_list_fp16(p, X, F, o.flist, pr->d_count, o.zgfrag, o.zgsc, o.zg32, o.zn, o.pmax, doa, power, nullptr, s);
     kt.end();
     kt.flush();
 }

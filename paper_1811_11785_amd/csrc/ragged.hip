@@ -164,7 +164,7 @@ void ragged_build(svdphat_ragged* r, uint32_t flags, const char* cache_path) {
         of[i].zf = take(sizeof(_Float16) * Fc * p->Rp);
         of[i].sc = take(sizeof(float) * Fc);
         of[i].zn = take(sizeof(float) * Fc);
-        of[i].pm = take(sizeof(float) * ntile * Fc);
+        of[i].pm = take(sizeof(float) * pmax_stride(p) * Fc);
     }
     if (hipMalloc(&r->ws, std::max<size_t>(total, 256)) != hipSuccess) {
         r->ws = nullptr;
@@ -204,13 +204,13 @@ void ragged_build(svdphat_ragged* r, uint32_t flags, const char* cache_path) {
         d.fch = r->fch[i];
         d.uinv = 1.f / p->uscale[P_FP16];
         d.pmax = (float*)(w + of[i].pm);
-        d.pstride = Fc;
+        d.pstride = pmax_stride(p);
         FinalArgs& fa = d.fin;
         fa.M = p->M;
         fa.P = p->P;
         fa.B = p->B;
         fa.pmax = d.pmax;
-        fa.pstride = Fc;
+        fa.pstride = d.pstride;
         fa.ntile = d.ntile;
         fa.ncls = p->ncls;
         fa.z32 = d.z32;

@@ -224,6 +224,21 @@ __device__ __forceinline__ void gemm1_body(int bx, int by, int bz, const float2*
     }
 }
 
+// the same over a device-counted frame list, grid-stride over (frame tile,
+// split) items
+template <typename T, int NF, int NRB, int MAXM, int IPT, bool HILO>
+__global__ __launch_bounds__(256) void k_gemm1_list(const float2* __restrict__ X, int M, int P, int B,
+                                                    const T* __restrict__ A, const T* __restrict__ Alo, int nRB,
+                                                    int BB, int CW, int nch, int cps, int nsplit,
+                                                    float* __restrict__ zpart, int64_t zstride, int Rp,
+                                                    const int* __restrict__ flist, const int* __restrict__ fcount) {
+    const int64_t n = *fcount;
+    const int64_t items = (n + NF - 1) / NF * nsplit;
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x)
+        gemm1_body<T, NF, NRB, MAXM, IPT, HILO>((int)(it / nsplit), (int)(it % nsplit), blockIdx.z, X, n, M, P, B, A,
+                                                Alo, nRB, BB, CW, nch, cps, zpart, zstride, Rp, flist, fcount);
+}
+
 template <typename T, int NF, int NRB, int MAXM, int IPT, bool HILO>
 __global__ __launch_bounds__(256) void k_gemm1(const float2* __restrict__ X, int64_t nfr, int M, int P, int B,
                                                const T* __restrict__ A, const T* __restrict__ Alo, int nRB, int BB,
@@ -249,8 +264,16 @@ __device__ __forceinline__ void zprep_body(int bx, const float* __restrict__ zpa
     if (f >= n) return;
     float mx = 0.f, ss = 0.f;
     for (int r = lane; r < Rp; r += 64) {
+        // the split partials are loaded eight at a time, all in flight together
         float v = 0.f;
-        for (int s = 0; s < nsplit; ++s) v += zpart[(int64_t)s * zstride + f * Rp + r];
+        for (int s0 = 0; s0 < nsplit; s0 += 8) {
+            float part[8];
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+                part[s] = s0 + s < nsplit ? zpart[(int64_t)(s0 + s) * zstride + f * Rp + r] : 0.f;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) v += part[s];
+        }
         z32[f * Rp + r] = v;
         mx = fmaxf(mx, fabsf(v));
         ss += v * v;
@@ -280,6 +303,15 @@ __device__ __forceinline__ void zprep_body(int bx, const float* __restrict__ zpa
 }
 
 template <typename T>
+__global__ __launch_bounds__(256) void k_zprep_list(const float* __restrict__ zpart, int nsplit, int64_t zstride,
+                                                    const int* __restrict__ fcount, int Rp, float* __restrict__ z32,
+                                                    float* __restrict__ znorm) {
+    const int64_t n = *fcount;
+    for (int64_t bx = blockIdx.x; bx * 4 < n; bx += gridDim.x)
+        zprep_body<T>((int)bx, zpart, nsplit, zstride, n, nullptr, Rp, z32, nullptr, nullptr, znorm, 0);
+}
+
+template <typename T>
 __global__ __launch_bounds__(256) void k_zprep(const float* __restrict__ zpart, int nsplit, int64_t zstride,
                                                int64_t nfr, const int* __restrict__ fcount, int Rp,
                                                float* __restrict__ z32, T* __restrict__ zfrag,
@@ -292,7 +324,7 @@ __global__ __launch_bounds__(256) void k_zprep(const float* __restrict__ zpart, 
 // FCH frames.  With UREG the wave keeps the tile's U fragments (KSN k-steps)
 // in registers and streams the frames 16 at a time (the next frames' Z
 // fragments are loaded during the current MFMAs); the epilogue writes one
-// maximum per (frame, tile), tile-major: pmax[tile * pstride + f].
+// maximum per (frame, tile), frame-major: pmax[f * pstride + tile].
 template <typename T, int KSN, bool UREG>
 __device__ __forceinline__ void gemm2_body(int bx, int by, const T* __restrict__ U, int KSn,
                                            const T* __restrict__ zfrag, int64_t nfr, int fch, int ncls, int ntile,
@@ -324,23 +356,38 @@ __device__ __forceinline__ void gemm2_body(int bx, int by, const T* __restrict__
 #pragma unroll
         for (int e = 0; e < 4; ++e) rowok[i][e] = (rb0 + i) * 16 + 4 * (lane >> 4) + e < ncls;
 
-    VT bn[UREG ? KSN : 1];
-    auto loadB = [&](int64_t fb) {
+    // Z fragments of the next two frame blocks are in flight while the
+    // current block's MFMAs run (ring of two register sets)
+    VT bq0[UREG ? KSN : 1], bq1[UREG ? KSN : 1];
+    float sq0 = 1.f, sq1 = 1.f;  // per-frame scale of the lane's frame
+    auto loadB = [&](VT* dst, float& sc, int64_t fb) {
         const T* zb = zfrag + (fb * KSn * 64 + lane) * EPL;
 #pragma unroll
         for (int ks = 0; ks < (UREG ? KSN : 1); ++ks)
-            if (ks < KSn) bn[ks] = *reinterpret_cast<const VT*>(zb + (int64_t)ks * 64 * EPL);
+            if (ks < KSn) dst[ks] = *reinterpret_cast<const VT*>(zb + (int64_t)ks * 64 * EPL);
+        const int64_t f = fb * 16 + (lane & 15);
+        sc = f < fend ? zscale[f] : 1.f;
     };
-    if (UREG && fbeg < fend) loadB(fbeg >> 4);
-    for (int64_t fb = fbeg >> 4; fb * 16 < fend; ++fb) {
+    const int64_t fb0 = fbeg >> 4;
+    if (UREG) {
+        loadB(bq0, sq0, fb0);
+        if ((fb0 + 1) * 16 < fend) loadB(bq1, sq1, fb0 + 1);
+    }
+    for (int64_t fb = fb0; fb * 16 < fend; ++fb) {
         f4 acc[4];
+        float zsc_cur = 1.f;
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
         if (UREG) {
             VT b[KSN];
+            const bool even = ((fb - fb0) & 1) == 0;
 #pragma unroll
-            for (int ks = 0; ks < KSN; ++ks) b[ks] = bn[ks];
-            if ((fb + 1) * 16 < fend) loadB(fb + 1);
+            for (int ks = 0; ks < KSN; ++ks) b[ks] = even ? bq0[ks] : bq1[ks];
+            zsc_cur = even ? sq0 : sq1;
+            if ((fb + 2) * 16 < fend) {
+                if (even) loadB(bq0, sq0, fb + 2);
+                else loadB(bq1, sq1, fb + 2);
+            }
 #pragma unroll
             for (int ks = 0; ks < KSN; ++ks)
                 if (ks < KSn)
@@ -359,7 +406,7 @@ __device__ __forceinline__ void gemm2_body(int bx, int by, const T* __restrict__
         }
         const int64_t f = fb * 16 + (lane & 15);
         const bool live = f < fend;
-        const float inv = live ? uinv / zscale[f] : 0.f;
+        const float inv = live ? uinv / (UREG ? zsc_cur : zscale[f]) : 0.f;
         float m = -INFINITY;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -368,7 +415,7 @@ __device__ __forceinline__ void gemm2_body(int bx, int by, const T* __restrict__
                 if (rowok[i][e]) m = fmaxf(m, acc[i][e]);
         m = fmaxf(m, __shfl_xor(m, 16));
         m = fmaxf(m, __shfl_xor(m, 32));
-        if (lane < 16 && live) pmax[(int64_t)tile * pstride + (fmap ? (int64_t)fmap[f] : f)] = m * inv;
+        if (lane < 16 && live) pmax[(fmap ? (int64_t)fmap[f] : f) * pstride + tile] = m * inv;
         if (ycls && live) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
@@ -406,6 +453,22 @@ __global__ __launch_bounds__(256) void k_gemm2_list(const _Float16* __restrict__
 // ------------------------------------------------------------------ final
 
 
+
+// y = sum_r ut[r * QTILE] zw[r] (one lane's row of a tile in the transposed
+// FP32 rescoring copy; Rp is a multiple of 32).  The loads of a 32-row batch
+// are all issued before their FMAs so that many are in flight at once.
+__device__ __forceinline__ float row_dot(const float* __restrict__ ut, const float* zw, int Rp) {
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int r0 = 0; r0 < Rp; r0 += 32) {
+        float v[32];
+#pragma unroll
+        for (int i = 0; i < 32; ++i) v[i] = ut[(int64_t)(r0 + i) * QTILE];
+#pragma unroll
+        for (int i = 0; i < 32; ++i) acc[i & 3] = fmaf(v[i], zw[r0 + i], acc[i & 3]);
+    }
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
 // One wave per frame.
 template <int MAXM, bool DEDUP>
 __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
@@ -416,6 +479,9 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
     if (pos >= n) return;
     const int64_t f = a.flist ? (int64_t)a.flist[pos] : pos;
     const int Rp = a.Rp;
+    const float2* xf = a.X + f * a.M * a.B;
+    PowerPrefetch<MAXM> pp;
+    pp.load(xf, a.M, a.B, lane);
     const float* z = a.z32 + pos * Rp;
     float* zw = zs[wave];
     float dz2 = 0.f;
@@ -431,8 +497,8 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
     wave_sync();
 
     // frame maximum over tiles and the tile holding it
-    const float* pm = a.pmax + f;
-    const int64_t ps = a.pstride;
+    const float* pm = a.pmax + f * a.pstride;
+    const int64_t ps = 1;
     float ym = -INFINITY;
     int tm = 0x7fffffff;
     for (int t = lane; t < a.ntile; t += 64) {
@@ -470,16 +536,7 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
             mask &= mask - 1;
             const int row = tt * QTILE + lane;
             const float* ut = a.U32T + (int64_t)tt * Rp * QTILE + lane;
-            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-            int r = 0;
-            for (; r + 4 <= Rp; r += 4) {
-                s0 = fmaf(ut[(int64_t)(r + 0) * QTILE], zw[r + 0], s0);
-                s1 = fmaf(ut[(int64_t)(r + 1) * QTILE], zw[r + 1], s1);
-                s2 = fmaf(ut[(int64_t)(r + 2) * QTILE], zw[r + 2], s2);
-                s3 = fmaf(ut[(int64_t)(r + 3) * QTILE], zw[r + 3], s3);
-            }
-            for (; r < Rp; ++r) s0 = fmaf(ut[(int64_t)r * QTILE], zw[r], s0);
-            const float y = (s0 + s1) + (s2 + s3);
+            const float y = row_dot(ut, zw, Rp);
             if (row < a.ncls) {
                 const int q = a.rows[row];
                 if (better(y, q, y1, q1)) {
@@ -546,8 +603,7 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
                 const int row = tt * QTILE + lane;
                 if (row < a.ncls && a.rep[a.rows[row]] != cls) {
                     const float* ut = a.U32T + (int64_t)tt * Rp * QTILE + lane;
-                    float y = 0.f;
-                    for (int r = 0; r < Rp; ++r) y = fmaf(ut[(int64_t)r * QTILE], zw[r], y);
+                    const float y = row_dot(ut, zw, Rp);
                     if (y > sy) {
                         sy = y;
                         sr = row;
@@ -592,7 +648,7 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
     }
 
     // Algorithm 1 online step 4: power of the chosen direction from its row of W
-    float acc = direction_power<MAXM>(a.X + f * a.M * a.B, a.M, a.B, a.tauN + (int64_t)cls * a.P, lane);
+    float acc = pp.power(xf, a.M, a.B, a.tauN + (int64_t)cls * a.P, lane);
     acc = wave_sum(acc);
     if (lane == 0) {
         a.doa[f] = cls;
@@ -613,6 +669,13 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
 template <int MAXM, bool DEDUP>
 __global__ __launch_bounds__(256) void k_final(FinalArgs a) {
     final_body<MAXM, DEDUP>(blockIdx.x, a);
+}
+
+// the same over a device-counted frame list, grid-stride (few frames)
+template <int MAXM, bool DEDUP>
+__global__ __launch_bounds__(256) void k_final_list(FinalArgs a) {
+    const int64_t n = *a.fcount;
+    for (int64_t bx = blockIdx.x; bx * 4 < n; bx += gridDim.x) final_body<MAXM, DEDUP>((int)bx, a);
 }
 
 
@@ -759,6 +822,46 @@ void launch_final(const FinalArgs& fa, int M, bool dedup, int64_t nwaves, hipStr
     }
 }
 
+
+// hi/lo pass over the device-counted frame list (32 frames per workgroup)
+template <typename T>
+void launch_g1_list(hipStream_t s, const float2* X, svdphat_plan* p, int prec, const G1Layout& g, int nsplit, int cps,
+                    float* zpart, int64_t zstride, const int* fl, const int* fc) {
+    const int nRB = p->Rp / 16;
+    const int NRB = nRB <= 2 ? 2 : nRB <= 4 ? 4 : nRB <= 6 ? 6 : nRB <= 8 ? 8 : nRB <= 10 ? 10 : 12;
+    dim3 grid(2048, 1, cdiv(nRB, NRB));
+    const size_t xbytes = (size_t)2 * 32 * (g.CW + XPAD) * sizeof(T);
+    const size_t lds = std::max(xbytes, (size_t)NRB * 2 * 64 * sizeof(f4));
+    const T* A = (const T*)p->A[prec];
+    const T* Alo = (const T*)p->Alo[prec];
+    const int M = p->M;
+#define SP_G1L(N)                                                                                                   \
+    if (NRB == N) {                                                                                                 \
+        if (M <= 8)                                                                                                 \
+            k_gemm1_list<T, 32, N, 8, G1_IPT8, true><<<grid, 256, lds, s>>>(X, M, p->P, p->B, A, Alo, nRB, g.BB,    \
+                                                                            g.CW, g.nch, cps, nsplit, zpart,       \
+                                                                            zstride, p->Rp, fl, fc);               \
+        else                                                                                                        \
+            k_gemm1_list<T, 32, N, 16, G1_IPT16, true><<<grid, 256, lds, s>>>(X, M, p->P, p->B, A, Alo, nRB, g.BB,  \
+                                                                              g.CW, g.nch, cps, nsplit, zpart,     \
+                                                                              zstride, p->Rp, fl, fc);             \
+        return;                                                                                                     \
+    }
+    SP_G1L(2) SP_G1L(4) SP_G1L(6) SP_G1L(8) SP_G1L(10) SP_G1L(12)
+#undef SP_G1L
+}
+
+void launch_final_list(const FinalArgs& fa, int M, bool dedup, hipStream_t s) {
+    dim3 grid(512);
+    if (M <= 8) {
+        if (dedup) k_final_list<8, true><<<grid, 256, 0, s>>>(fa);
+        else k_final_list<8, false><<<grid, 256, 0, s>>>(fa);
+    } else {
+        if (dedup) k_final_list<16, true><<<grid, 256, 0, s>>>(fa);
+        else k_final_list<16, false><<<grid, 256, 0, s>>>(fa);
+    }
+}
+
 template <typename T>
 void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t mode, int32_t* doa, float* power,
                 float* yhat, float* margin, float* y_opt, hipStream_t s) {
@@ -787,7 +890,8 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     const size_t o_zsc = take(sizeof(float) * Fc);
     const size_t o_zn = take(sizeof(float) * Fc);
     const size_t o_znh = hilo ? take(sizeof(float) * Fc) : 0;
-    const size_t o_pmax = take(sizeof(float) * ntile * Fc);
+    const int ntp = pmax_stride(p);
+    const size_t o_pmax = take(sizeof(float) * ntp * Fc);
     const size_t o_hl = hilo ? take(sizeof(int) * Fc) : 0;
     const size_t o_hc = hilo ? take(sizeof(int) * 64) : 0;
     const size_t o_y = y_opt ? take(sizeof(float) * Fc * p->ncls_pad) : 0;
@@ -820,7 +924,7 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     SP_HIP(hipGetLastError());
     kt.end();
     kt.begin("gemm2");
-    launch_g2<T>(p, prec, zfrag, F, zsc, pmax, Fc, ycls, s);
+    launch_g2<T>(p, prec, zfrag, F, zsc, pmax, ntp, ycls, s);
     SP_HIP(hipGetLastError());
     kt.end();
     if (y_opt) {
@@ -842,7 +946,7 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     fa.P = p->P;
     fa.B = p->B;
     fa.pmax = pmax;
-    fa.pstride = Fc;
+    fa.pstride = ntp;
     fa.ntile = ntile;
     fa.ncls = p->ncls;
     fa.z32 = z32;
@@ -876,12 +980,11 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
         float* z32h = (float*)(w + o_z32h);
         float* znh = (float*)(w + o_znh);
         kt.begin("gemm1_hilo");
-        launch_g1<T, 32, true>((int)(Fc / 32), hsplit, s, X, F, p, prec, g, hcps, zpart, zstride, hl, hc);
+        launch_g1_list<T>(s, X, p, prec, g, hsplit, hcps, zpart, zstride, hl, hc);
         SP_HIP(hipGetLastError());
         kt.end();
         kt.begin("zprep_hilo");
-        k_zprep<T><<<dim3((unsigned)(Fc / 4)), 256, 0, s>>>(zpart, hsplit, zstride, F, hc, Rp, z32h, nullptr, nullptr,
-                                                            znh, 0);
+        k_zprep_list<T><<<dim3(512), 256, 0, s>>>(zpart, hsplit, zstride, hc, Rp, z32h, znh);
         SP_HIP(hipGetLastError());
         kt.end();
         FinalArgs fb = fa;
@@ -892,7 +995,7 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
         fb.hlist = nullptr;
         fb.stats = nullptr;
         kt.begin("final_hilo");
-        launch_final(fb, p->M, dedup, F, s);
+        launch_final_list(fb, p->M, dedup, s);
         SP_HIP(hipGetLastError());
         kt.end();
     }
@@ -936,7 +1039,8 @@ void front_fp16(svdphat_plan* p, const float2* X, int64_t F, float* zpart, float
 // z32 position-indexed, znorm frame-indexed).
 void back_list_fp16(svdphat_plan* p, const float2* X, int64_t Fmax, const int* flist, const int* fcount,
                     const _Float16* zfrag, const float* zsc, const float* z32pos, const float* zn_frame,
-                    float* pmax, int64_t pstride, int32_t* doa, float* power, float* margin, hipStream_t s) {
+                    float* pmax, int32_t* doa, float* power, float* margin, hipStream_t s) {
+    const int64_t pstride = pmax_stride(p);
     const int KSn = p->Rp / Mf<_Float16>::KSTEP;
     const int ntile = p->ncls_pad / QTILE;
     const int fch = 256;
@@ -1043,7 +1147,7 @@ void tune_time(svdphat_plan* p, int64_t F, int nsplit_want, int fch, double* us_
     const size_t o_zf = take(sizeof(_Float16) * Fc * Rp);
     const size_t o_sc = take(sizeof(float) * Fc);
     const size_t o_zn = take(sizeof(float) * Fc);
-    const size_t o_pm = take(sizeof(float) * ntile * Fc);
+    const size_t o_pm = take(sizeof(float) * pmax_stride(p) * Fc);
     char* w = (char*)ws_get(p, s, off);
     float2* X = (float2*)(w + o_x);
     k_fill_synth<<<dim3((unsigned)((nx + 255) / 256)), 256, 0, s>>>(X, (int64_t)nx);
@@ -1066,12 +1170,12 @@ void tune_time(svdphat_plan* p, int64_t F, int nsplit_want, int fch, double* us_
         if (KSn <= 6)
             k_gemm2<_Float16, 6, true><<<grid, 256, 0, s>>>((const _Float16*)p->Ufr[P_FP16], KSn,
                                                             (const _Float16*)(w + o_zf), F, fch, p->ncls, ntile,
-                                                            (const float*)(w + o_sc), 1.f, (float*)(w + o_pm), Fc,
+                                                            (const float*)(w + o_sc), 1.f, (float*)(w + o_pm), pmax_stride(p),
                                                             nullptr, 0);
         else
             k_gemm2<_Float16, 1, false><<<grid, 256, 0, s>>>((const _Float16*)p->Ufr[P_FP16], KSn,
                                                              (const _Float16*)(w + o_zf), F, fch, p->ncls, ntile,
-                                                             (const float*)(w + o_sc), 1.f, (float*)(w + o_pm), Fc,
+                                                             (const float*)(w + o_sc), 1.f, (float*)(w + o_pm), pmax_stride(p),
                                                              nullptr, 0);
     }
     SP_HIP(hipEventRecord(e[2], s));
