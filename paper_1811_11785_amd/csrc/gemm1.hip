@@ -1,0 +1,351 @@
+// GEMM1, streamed form: Z = S V^H x (eq. (12) with S folded into V^H) with
+// the PHAT cross-spectra (eq. (3)) formed on chip, for 16-bit operands, 6 to
+// 8 microphones and all row blocks of Z in one workgroup.
+//
+// Work units are (frame tile of 64 frames, chunk of 8 bins) pairs in tile-
+// major order; a persistent grid of G workgroups (one per CU) takes equal
+// contiguous ranges of units, so every workgroup streams its STFT values
+// without a break from its first unit to its last.  A workgroup has 8
+// waves in two roles, one of each on every SIMD:
+//   producers (waves 4-7) load the STFT values of the units ahead into a
+//     register ring of XD units (each thread one frame and a pair of bins,
+//     one 16-byte load per microphone) and form each unit's PHAT tile
+//     (per-mic unit normalisation, then X_i conj(X_j) for pairs i < j in
+//     order, rounded to T, stored as (Re, Im)) in one of two LDS buffers;
+//   consumers (waves 0-3) take KSC/4 of the unit's KSC k-steps, load their A
+//     fragments and run the MFMAs, each accumulating every (row block, frame
+//     block) of the tile's Z; at the end of a frame tile (or of the range)
+//     each consumer writes its partial sum to its own slot: slot
+//     4 (w - w0) + wave, w0 the first workgroup whose range meets the tile.
+// One barrier per unit hands a PHAT tile from the producers to the
+// consumers.  The Z preparation sums the 4 (w1 - w0 + 1) slots of a frame.
+//
+// Memory order.  Vector-memory loads complete in issue order for a wave's
+// wait counter, so a wave that waits for one load also waits for every load
+// it issued earlier.  Splitting the roles keeps the two streams apart: the
+// producers' STFT loads run XD units ahead without the consumers' A loads
+// queueing behind them, and each consumer issues the A fragments of unit
+// u+1 as soon as the MFMAs of unit u that read those registers are issued.
+// Loop-carried registers are first filled outside the loop; an empty asm
+// statement on those first values keeps the compiler from merging the two
+// load sites into one load at the top of the loop (which would turn every
+// prefetch into a load right before its use).  Loads sit outside every
+// branch so that the wait counts stay exact.
+//
+// Cache footprint.  A unit reads a short run of bins from each (frame,
+// microphone) row of the STFT, so every row keeps one partly used cache
+// line in L2 until its next unit; with one workgroup per CU (the LDS request
+// guarantees it) the lines in flight on an XCD stay well inside its L2.
+#include "device.h"
+
+namespace svdphat {
+
+namespace {
+
+constexpr int G1S_NF = 64;
+constexpr int G1S_BB = 8;   // bins per chunk (64 frames x 4 bin pairs = 256 producer threads)
+constexpr int G1S_PAD = 8;  // LDS row padding (elements)
+constexpr int G1S_XD = 4;   // chunks of STFT values in flight (even)
+
+// k-steps per chunk for MM microphones (8 bins x MM (MM - 1) stacked values,
+// rounded up to a multiple of four k-steps of 32)
+constexpr int g1s_ksc(int MM) { return (G1S_BB * MM * (MM - 1) + 127) / 128 * 4; }
+
+// four floats read with one 16-byte load from an 8-byte aligned address
+struct __attribute__((aligned(8))) f4u {
+    float x, y, z, w;
+};
+
+// unit-modulus normalisation (the per-microphone factor of eq. (3)) of one
+// STFT value, rounded to a half pair; values whose |X|^2 is not a finite
+// normal float are silent and give 0
+__device__ __forceinline__ h2 unit_h2(float re, float im) {
+    const float m2 = re * re + im * im;
+    const float s = __builtin_amdgcn_rsqf(m2);
+    const h2 u = h2{(_Float16)(re * s), (_Float16)(im * s)};
+    return __builtin_amdgcn_classf(m2, 0x100) ? u : h2{(_Float16)0.f, (_Float16)0.f};
+}
+
+// workgroup whose unit range holds unit u (ranges [w U / G, (w+1) U / G))
+__host__ __device__ inline int g1s_owner(int64_t u, int G, int64_t U) { return (int)(((u + 1) * G - 1) / U); }
+
+template <typename T, int MM, int NRB, int XD>
+__global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, int64_t nfr, int B,
+                                                const T* __restrict__ A, int nch, int64_t U,
+                                                float* __restrict__ zpart, int64_t zstride, int Rp) {
+    constexpr int KS = Mf<T>::KSTEP, EPL = Mf<T>::EPL, NF = G1S_NF, FB = NF / 16;
+    constexpr int P = MM * (MM - 1) / 2, TWOP = 2 * P;
+    constexpr int BB = G1S_BB, BP = BB / 2;
+    constexpr int KSC = g1s_ksc(MM), KPW = KSC / 4;
+    constexpr int CW = KSC * KS;      // stacked values per chunk (BB * TWOP used)
+    constexpr int LDX = CW + G1S_PAD;
+    constexpr int PADC = CW - BB * TWOP;
+    static_assert(NF * BP == 256 && KSC % 4 == 0 && XD % 2 == 0, "chunk layout");
+    typedef typename Vec<T>::t VT;
+    typedef typename Vec<T>::pair VP;
+    extern __shared__ __align__(16) char smem[];
+    T* xsb = reinterpret_cast<T*>(smem);  // two tiles of NF x LDX
+
+    const int G = gridDim.x, w = blockIdx.x;
+    const int64_t ub = (int64_t)w * U / G, ue = (int64_t)(w + 1) * U / G;  // this workgroup's units
+    if (ub >= ue) return;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+
+    // padding columns of both tiles are zero (the PHAT phase never writes them)
+    if (PADC > 0)
+        for (int i = tid; i < 2 * NF * PADC; i += 512) xsb[(i / PADC) * LDX + BB * TWOP + i % PADC] = cvt<T>(0.f);
+
+    f4 acc[NRB][FB];
+#pragma unroll
+    for (int r = 0; r < NRB; ++r)
+#pragma unroll
+        for (int j = 0; j < FB; ++j) acc[r][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+    if (wave >= 4) {
+        // ---------------------------------------------------------- producer
+        // thread ptid: frame ptid / BP, bins 2 (ptid % BP) and 2 (ptid % BP) + 1
+        const int ptid = tid - 256;
+        const int fl = ptid / BP, b0 = 2 * (ptid % BP);
+        // Ring slot d holds the units ub + d (mod XD).  Loads are
+        // unconditional: a pair whose second bin is past the last one reads
+        // the pair one bin earlier, and a pair outside the data reads frame 0,
+        // bins 0-1; the values are selected (or zeroed) where consumed.
+        f4u xv[XD][MM];
+        int xmode[XD];  // 2: both bins, 1: first bin only (shifted load), 0: none
+        auto fetch = [&](int d, int64_t u) {
+            const int64_t t = u / nch;
+            const int c = (int)(u - t * nch);
+            const int64_t f = t * NF + fl;
+            const int s0 = c * BB + b0;
+            const int mode = f >= nfr ? 0 : s0 + 1 < B ? 2 : s0 < B ? 1 : 0;
+            xmode[d] = mode;
+            const int64_t off = mode == 2 ? f * MM * B + s0 : mode == 1 ? f * MM * B + s0 - 1 : 0;
+#pragma unroll
+            for (int m = 0; m < MM; ++m) xv[d][m] = *reinterpret_cast<const f4u*>(X + off + (int64_t)m * B);
+        };
+        // PHAT tile of one chunk from ring slot d; FULL: every pair of the
+        // chunk lies inside the data (no per-value selection)
+        auto phat_impl = [&](auto full_tag, int d, T* xs) {
+            constexpr bool FULL = decltype(full_tag)::value;
+            const int mode = xmode[d];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                VP* dst = reinterpret_cast<VP*>(xs + fl * LDX + (b0 + q) * TWOP);
+                float re[MM], im[MM];
+#pragma unroll
+                for (int m = 0; m < MM; ++m) {
+                    const f4u v = xv[d][m];
+                    if (FULL) {
+                        re[m] = q == 0 ? v.x : v.z;
+                        im[m] = q == 0 ? v.y : v.w;
+                    } else if (q == 0) {
+                        re[m] = mode == 2 ? v.x : mode == 1 ? v.z : 0.f;
+                        im[m] = mode == 2 ? v.y : mode == 1 ? v.w : 0.f;
+                    } else {
+                        re[m] = mode == 2 ? v.z : 0.f;
+                        im[m] = mode == 2 ? v.w : 0.f;
+                    }
+                }
+                if constexpr (std::is_same<T, _Float16>::value) {
+                    h2 u[MM];
+#pragma unroll
+                    for (int m = 0; m < MM; ++m) u[m] = unit_h2(re[m], im[m]);
+                    // (Re, Im) of X_i conj(X_j) = (a c + b d, b c - a d) for
+                    // X_i = a + ib, X_j = c + id
+                    int p = 0;
+#pragma unroll
+                    for (int i = 0; i < MM; ++i) {
+                        const h2 sw = __builtin_shufflevector(u[i], u[i], 1, 0);
+#pragma unroll
+                        for (int j = i + 1; j < MM; ++j) {
+                            const h2 cc = h2{u[j].x, u[j].x}, dd = h2{u[j].y, -u[j].y};
+                            dst[p] = u[i] * cc + sw * dd;
+                            ++p;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int m = 0; m < MM; ++m) unit(re[m], im[m]);
+                    int p = 0;
+#pragma unroll
+                    for (int i = 0; i < MM; ++i)
+#pragma unroll
+                        for (int j = i + 1; j < MM; ++j) {
+                            dst[p] = mkpair<T>(cvt<T>(re[i] * re[j] + im[i] * im[j]),
+                                               cvt<T>(im[i] * re[j] - re[i] * im[j]));
+                            ++p;
+                        }
+                }
+            }
+        };
+        auto phat = [&](int d, int64_t u, T* xs) {
+            const int64_t t = u / nch;
+            const int c = (int)(u - t * nch);
+            if ((t + 1) * NF <= nfr && (c + 1) * BB <= B) phat_impl(std::true_type{}, d, xs);
+            else phat_impl(std::false_type{}, d, xs);
+        };
+#pragma unroll
+        for (int d = 0; d < XD; ++d) fetch(d, min(ub + d, ue - 1));
+#pragma unroll
+        for (int d = 0; d < XD; ++d)
+#pragma unroll
+            for (int m = 0; m < MM; ++m)
+                asm volatile("" : "+v"(xv[d][m].x), "+v"(xv[d][m].y), "+v"(xv[d][m].z), "+v"(xv[d][m].w));
+        phat(0, ub, xsb);
+        fetch(0, min(ub + XD, ue - 1));
+        for (int64_t u0 = ub; u0 < ue; u0 += XD) {
+#pragma unroll
+            for (int d = 0; d < XD; ++d) {
+                const int64_t u = u0 + d;
+                if (u < ue) __syncthreads();  // tile of unit u complete; tile of u+1 free
+                if (u + 1 < ue) phat((d + 1) % XD, u + 1, xsb + ((d + 1) & 1) * NF * LDX);
+                fetch((d + 1) % XD, min(u + 1 + XD, ue - 1));
+            }
+        }
+    } else {
+        // ---------------------------------------------------------- consumer
+        VT a[KPW][NRB];
+        auto loadA = [&](int64_t u, int kk) {
+            const int c = (int)(u % nch);
+            const T* base = A + (((int64_t)c * KSC + wave + 4 * kk) * NRB * 64 + lane) * EPL;
+#pragma unroll
+            for (int r = 0; r < NRB; ++r) a[kk][r] = *reinterpret_cast<const VT*>(base + r * 64 * EPL);
+        };
+#pragma unroll
+        for (int kk = 0; kk < KPW; ++kk) loadA(ub, kk);
+#pragma unroll
+        for (int kk = 0; kk < KPW; ++kk)
+#pragma unroll
+            for (int r = 0; r < NRB; ++r) asm volatile("" : "+v"(a[kk][r]));
+        for (int64_t u = ub; u < ue; ++u) {
+            __syncthreads();  // tile of unit u complete
+            const T* xs = xsb + ((u - ub) & 1) * NF * LDX;
+            const int64_t un = min(u + 1, ue - 1);
+#pragma unroll
+            for (int kk = 0; kk < KPW; ++kk) {
+                const T* bp = xs + (lane & 15) * LDX + (wave + 4 * kk) * KS + EPL * (lane >> 4);
+                VT b[FB];
+#pragma unroll
+                for (int j = 0; j < FB; ++j) b[j] = *reinterpret_cast<const VT*>(bp + j * 16 * LDX);
+#pragma unroll
+                for (int r = 0; r < NRB; ++r)
+#pragma unroll
+                    for (int j = 0; j < FB; ++j) acc[r][j] = mfma(a[kk][r], b[j], acc[r][j]);
+                loadA(un, kk);
+            }
+            const int64_t t = u / nch;
+            if (u - t * nch == nch - 1 || u == ue - 1) {
+                // end of this workgroup's part of frame tile t: partial sum to
+                // slot 4 (w - w0) + wave.  D layout: lane holds rows
+                // 4 (lane / 16) + e of column lane % 16.
+                const int slot = 4 * (w - g1s_owner(t * nch, G, U)) + wave;
+#pragma unroll
+                for (int j = 0; j < FB; ++j) {
+                    const int64_t fpos = t * NF + j * 16 + (lane & 15);
+                    float* zp = zpart + (int64_t)slot * zstride + fpos * Rp;
+                    if (fpos < nfr)
+#pragma unroll
+                        for (int r = 0; r < NRB; ++r)
+                            *reinterpret_cast<f4*>(zp + r * 16 + 4 * (lane >> 4)) = acc[r][j];
+#pragma unroll
+                    for (int r = 0; r < NRB; ++r) acc[r][j] = f4{0.f, 0.f, 0.f, 0.f};
+                }
+            }
+        }
+    }
+}
+// whether the streamed form covers (microphones, row blocks): the consumer
+// keeps NRB x KSC/4 A fragments in registers
+constexpr bool g1s_ok(int M, int nRB) {
+    return M >= 6 && M <= 8 && (nRB == 2 || nRB == 4 || nRB == 6 || nRB == 8) && nRB * g1s_ksc(M) / 4 <= 18;
+}
+
+// LDS of the streamed kernel: two PHAT tiles, and at least 81 KiB so that
+// one workgroup runs per CU
+template <typename T, int MM>
+constexpr size_t g1s_lds() {
+    constexpr size_t tiles = 2 * G1S_NF * (g1s_ksc(MM) * Mf<T>::KSTEP + G1S_PAD) * sizeof(T);
+    return tiles > 81 * 1024 ? tiles : 81 * 1024;
+}
+
+template <typename T, int MM>
+void launch_mm(int nRB, int G, hipStream_t s, const float2* X, int64_t F, int B, const void* A, int nch, int64_t U,
+               float* zpart, int64_t zstride, int Rp) {
+    const T* a = (const T*)A;
+    switch (nRB) {
+#define G1S_CASE(NRB_)                                                                                         \
+    case NRB_:                                                                                                 \
+        if constexpr (g1s_ok(MM, NRB_))                                                                        \
+            k_gemm1s<T, MM, NRB_, G1S_XD><<<G, 512, g1s_lds<T, MM>(), s>>>(X, F, B, a, nch, U, zpart, zstride, \
+                                                                           Rp);                               \
+        return;
+        G1S_CASE(2)
+        G1S_CASE(4)
+        G1S_CASE(6)
+        G1S_CASE(8)
+#undef G1S_CASE
+    }
+}
+
+int cu_count(int device) {
+    static int cached[64] = {0};
+    if (device < 0 || device >= 64) return 256;
+    if (!cached[device]) {
+        int n = 0;
+        SP_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device));
+        cached[device] = n > 0 ? n : 256;
+    }
+    return cached[device];
+}
+
+}  // namespace
+
+bool g1s_layout(int M, int nRB, int kstep, int* CW, int* BB) {
+    if (kstep != 32 || !g1s_ok(M, nRB)) return false;
+    *CW = g1s_ksc(M) * kstep;
+    *BB = G1S_BB;
+    return true;
+}
+
+bool g1s_sched(int prec, const svdphat_plan* p, int64_t F, G1Sched* out) {
+    const int nRB = p->Rp / 16;
+    int cw = 0, bb = 0;
+    const G1Layout& g = p->g1[prec];
+    if (prec == P_FP32 || p->B < 2 || F < 1 || !g1s_layout(p->M, nRB, 32, &cw, &bb) || g.CW != cw || g.BB != bb)
+        return false;
+    G1Sched sc;
+    const int64_t ftiles = (F + G1S_NF - 1) / G1S_NF;
+    sc.nch = g.nch;
+    sc.U = ftiles * g.nch;
+    // one workgroup per CU, at least 8 units each
+    sc.G = (int)std::max<int64_t>(1, std::min<int64_t>(cu_count(p->device), sc.U / 8));
+    int runs = 1;
+    for (int64_t t = 0; t < ftiles; ++t)
+        runs = std::max(runs, g1s_owner((t + 1) * sc.nch - 1, sc.G, sc.U) - g1s_owner(t * sc.nch, sc.G, sc.U) + 1);
+    sc.slots = 4 * runs;
+    *out = sc;
+    return true;
+}
+
+void launch_g1_streamed(int prec, const svdphat_plan* p, const G1Sched& sc, const float2* X, int64_t F, float* zpart,
+                        int64_t zstride, hipStream_t s) {
+    const int nRB = p->Rp / 16;
+    const void* A = p->A[prec];
+    const int B = p->B, Rp = p->Rp;
+    if (prec == P_FP16) {
+        switch (p->M) {
+            case 6: launch_mm<_Float16, 6>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp); return;
+            case 7: launch_mm<_Float16, 7>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp); return;
+            case 8: launch_mm<_Float16, 8>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp); return;
+        }
+    } else {
+        switch (p->M) {
+            case 6: launch_mm<__bf16, 6>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp); return;
+            case 7: launch_mm<__bf16, 7>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp); return;
+            case 8: launch_mm<__bf16, 8>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp); return;
+        }
+    }
+    fail(SVDPHAT_E_UNSUPPORTED, "streamed GEMM1 launched for an unsupported plan");
+}
+
+}  // namespace svdphat

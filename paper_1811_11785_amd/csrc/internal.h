@@ -149,6 +149,21 @@ void launch_grouped(const GroupLaunch& g, const RDesc* d, hipStream_t s);
 int g1_nrb_class(int nRB);
 size_t g1_lds_bytes(int NRB, int CW);
 void g1_split(const svdphat_plan* p, int64_t F, int want, int* nsplit, int* cps);
+// streamed GEMM1 (16-bit operands, 6 to 8 microphones, up to 8 row blocks):
+// the chunk it needs (false = not available); its schedule over F frames
+// (false = not applicable to this plan and precision): G persistent
+// workgroups over U = frame tiles x chunks units, `slots` partial sums per
+// frame; and its launcher
+bool g1s_layout(int M, int nRB, int kstep, int* CW, int* BB);
+struct G1Sched {
+    int G = 0;
+    int64_t U = 0;
+    int nch = 0;
+    int slots = 0;
+};
+bool g1s_sched(int prec, const svdphat_plan* p, int64_t F, G1Sched* out);
+void launch_g1_streamed(int prec, const svdphat_plan* p, const G1Sched& sc, const float2* X, int64_t F, float* zpart,
+                        int64_t zstride, hipStream_t s);
 // times one GEMM1 + Z prep (nsplit) and one GEMM2 (fch) of plan p on F
 // synthetic frames in FP16; returns microseconds
 void proposal_build(svdphat_proposal* pr, const double* coarse, int C, int H, uint64_t seed);

@@ -78,6 +78,16 @@ float from_t(T v) { return (float)v; }
 // counts that fit, prefer little padding, then bigger chunks.
 G1Layout make_layout(int P, int B, int M, int esize, int kstep, int nRB, int epl) {
     G1Layout g;
+    int cws = 0, bbs = 0;
+    if (esize == 2 && B >= 2 && g1s_layout(M, nRB, kstep, &cws, &bbs)) {
+        // the chunk of the streamed GEMM1 kernel
+        g.CW = cws;
+        g.BB = bbs;
+        g.nch = cdiv(B, g.BB);
+        g.ks_chunk = g.CW / kstep;
+        g.elems = (int64_t)g.nch * g.ks_chunk * nRB * 64 * epl;
+        return g;
+    }
     const int budget = 65536 / (64 * esize) - 8;  // CW + pad per frame row
     const int max_bb = (M <= 8 ? G1_MAX_ITEMS8 : G1_MAX_ITEMS16) / 64;
     double best = -1.0;

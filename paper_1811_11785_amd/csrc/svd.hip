@@ -252,16 +252,29 @@ __global__ __launch_bounds__(256) void k_gemm1(const float2* __restrict__ X, int
 // One wave per frame: z = sum of the split partials (FP32), ||z||, and the
 // GEMM2 operand copy in T (FP16: scaled by 2^e so that max |z| lies in
 // [2^13, 2^14)), in B-operand fragment order [frame/16][k-step][lane][EPL].
+// Partial sums of GEMM1 to add for frame f: nsplit, or with the streamed
+// GEMM1 (sG > 0 workgroups over sU units of snch chunks per 64-frame tile)
+// four per workgroup whose unit range meets the frame's tile.
+__device__ __forceinline__ int zpart_count(int64_t f, int nsplit, int sG, int64_t sU, int snch) {
+    if (sG <= 0) return nsplit;
+    const int64_t t = f >> 6;
+    const int64_t u0 = t * snch, u1 = u0 + snch - 1;
+    const int w0 = (int)(((u0 + 1) * sG - 1) / sU), w1 = (int)(((u1 + 1) * sG - 1) / sU);
+    return 4 * (w1 - w0 + 1);
+}
+
 template <typename T>
-__device__ __forceinline__ void zprep_body(int bx, const float* __restrict__ zpart, int nsplit, int64_t zstride,
+__device__ __forceinline__ void zprep_body(int bx, const float* __restrict__ zpart, int nsplit0, int64_t zstride,
                                            int64_t nfr, const int* __restrict__ fcount, int Rp,
                                            float* __restrict__ z32, T* __restrict__ zfrag,
-                                           float* __restrict__ zscale, float* __restrict__ znorm, int scale16) {
+                                           float* __restrict__ zscale, float* __restrict__ znorm, int scale16,
+                                           int sG = 0, int64_t sU = 0, int snch = 0) {
     constexpr int KS = Mf<T>::KSTEP, EPL = Mf<T>::EPL;
     const int64_t n = fcount ? (int64_t)*fcount : nfr;
     const int64_t f = (int64_t)bx * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (f >= n) return;
+    const int nsplit = zpart_count(f, nsplit0, sG, sU, snch);
     float mx = 0.f, ss = 0.f;
     for (int r = lane; r < Rp; r += 64) {
         // the split partials are loaded eight at a time, all in flight together
@@ -315,8 +328,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_zprep(const float* __restrict__ zpart, int nsplit, int64_t zstride,
                                                int64_t nfr, const int* __restrict__ fcount, int Rp,
                                                float* __restrict__ z32, T* __restrict__ zfrag,
-                                               float* __restrict__ zscale, float* __restrict__ znorm, int scale16) {
-    zprep_body<T>(blockIdx.x, zpart, nsplit, zstride, nfr, fcount, Rp, z32, zfrag, zscale, znorm, scale16);
+                                               float* __restrict__ zscale, float* __restrict__ znorm, int scale16,
+                                               int sG, int64_t sU, int snch) {
+    zprep_body<T>(blockIdx.x, zpart, nsplit, zstride, nfr, fcount, Rp, z32, zfrag, zscale, znorm, scale16, sG, sU,
+                  snch);
 }
 
 // ------------------------------------------------------------------ GEMM2
@@ -872,6 +887,9 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     const int ftiles = (int)(Fc / 64);
     int nsplit, cps;
     g1_split_layout(g, Rp, F, 0, &nsplit, &cps);
+    G1Sched sc;
+    const bool streamed = g1s_sched(prec, p, F, &sc);
+    const int zslots = streamed ? sc.slots : nsplit;
     const bool hilo = (mode & SVDPHAT_HILO) && prec != P_FP32;
     // the hi/lo pass covers few frames: more splits keep the grid busy
     int hsplit = g.nch, hcps = 1;
@@ -882,7 +900,7 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
         off += round_up64((int64_t)bytes, 256);
         return o;
     };
-    const int maxsplit = std::max(nsplit, hilo ? hsplit : 1);
+    const int maxsplit = std::max(zslots, hilo ? hsplit : 1);
     const size_t o_zpart = take(sizeof(float) * maxsplit * Fc * Rp);
     const size_t o_z32 = take(sizeof(float) * Fc * Rp);
     const size_t o_z32h = hilo ? take(sizeof(float) * Fc * Rp) : 0;
@@ -915,12 +933,13 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     const int64_t zstride = Fc * Rp;
     KernelTimer kt(s);
     kt.begin("gemm1");
-    launch_g1<T, 64, false>(ftiles, nsplit, s, X, F, p, prec, g, cps, zpart, zstride, nullptr, nullptr);
+    if (streamed) launch_g1_streamed(prec, p, sc, X, F, zpart, zstride, s);
+    else launch_g1<T, 64, false>(ftiles, nsplit, s, X, F, p, prec, g, cps, zpart, zstride, nullptr, nullptr);
     SP_HIP(hipGetLastError());
     kt.end();
     kt.begin("zprep");
-    k_zprep<T><<<dim3((unsigned)(Fc / 4)), 256, 0, s>>>(zpart, nsplit, zstride, F, nullptr, Rp, z32, zfrag, zsc, zn,
-                                                        prec == P_FP16 ? 1 : 0);
+    k_zprep<T><<<dim3((unsigned)(Fc / 4)), 256, 0, s>>>(zpart, zslots, zstride, F, nullptr, Rp, z32, zfrag, zsc, zn,
+                                                        prec == P_FP16 ? 1 : 0, streamed ? sc.G : 0, sc.U, sc.nch);
     SP_HIP(hipGetLastError());
     kt.end();
     kt.begin("gemm2");
@@ -1017,6 +1036,8 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
 int64_t front_zpart_floats(const svdphat_plan* p, int64_t F) {
     int nsplit, cps;
     g1_split_layout(p->g1[P_FP16], p->Rp, F, 0, &nsplit, &cps);
+    G1Sched sc;
+    if (g1s_sched(P_FP16, p, F, &sc)) nsplit = sc.slots;
     return (int64_t)nsplit * round_up64(F, 64) * p->Rp;
 }
 
@@ -1026,11 +1047,15 @@ void front_fp16(svdphat_plan* p, const float2* X, int64_t F, float* zpart, float
     const int64_t Fc = round_up64(F, 64);
     int nsplit, cps;
     g1_split_layout(g, p->Rp, F, 0, &nsplit, &cps);
-    launch_g1<_Float16, 64, false>((int)(Fc / 64), nsplit, s, X, F, p, P_FP16, g, cps, zpart, Fc * p->Rp, nullptr,
-                                   nullptr);
+    G1Sched sc;
+    const bool streamed = g1s_sched(P_FP16, p, F, &sc);
+    if (streamed) launch_g1_streamed(P_FP16, p, sc, X, F, zpart, Fc * p->Rp, s);
+    else launch_g1<_Float16, 64, false>((int)(Fc / 64), nsplit, s, X, F, p, P_FP16, g, cps, zpart, Fc * p->Rp,
+                                        nullptr, nullptr);
     SP_HIP(hipGetLastError());
-    k_zprep<_Float16><<<dim3((unsigned)(Fc / 4)), 256, 0, s>>>(zpart, nsplit, Fc * p->Rp, F, nullptr, p->Rp, z32,
-                                                               zfrag, zsc, zn, 1);
+    k_zprep<_Float16><<<dim3((unsigned)(Fc / 4)), 256, 0, s>>>(zpart, streamed ? sc.slots : nsplit, Fc * p->Rp, F,
+                                                               nullptr, p->Rp, z32, zfrag, zsc, zn, 1,
+                                                               streamed ? sc.G : 0, sc.U, sc.nch);
     SP_HIP(hipGetLastError());
 }
 
@@ -1161,7 +1186,8 @@ void tune_time(svdphat_plan* p, int64_t F, int nsplit_want, int fch, double* us_
                                        nullptr);
         k_zprep<_Float16><<<dim3((unsigned)(Fc / 4)), 256, 0, s>>>(zpart, nsplit, Fc * Rp, F, nullptr, Rp,
                                                                    (float*)(w + o_z), (_Float16*)(w + o_zf),
-                                                                   (float*)(w + o_sc), (float*)(w + o_zn), 1);
+                                                                   (float*)(w + o_sc), (float*)(w + o_zn), 1, 0, 0,
+                                                                   0);
     }
     SP_HIP(hipEventRecord(e[1], s));
     const int KSn = Rp / Mf<_Float16>::KSTEP;
