@@ -86,149 +86,69 @@ __device__ __forceinline__ bool better(float a, int ia, float b, int ib) {
 }
 
 
-// Algorithm 1, online step 4: the power of one direction from its row of W,
-// Y = Re sum_{p,k} exp(2 pi i k tau_p / N) x_{p,k}, for one frame (xf =
-// [M][B] STFT values, tq = tau_p / N of the direction's pairs).  One wave;
-// returns this lane's partial sum (the caller reduces over the wave).
+// Algorithm 1, online step 4: the power of direction q from its row of W,
+// Y_q = Re sum_{p,k} exp(2 pi i k tau_p / N) x_{p,k}, for one frame.  With
+// far-field delays (eq. (2)) the delay of pair p = (i, j) is tau_j - tau_i,
+// so each term is Re(V_i conj(V_j)) with V_m = exp(-2 pi i k tau_m / N)
+// X_m / |X_m| (0 for a silent bin: |X_m|^2 not a finite normal float), and
+// the sum over the pairs i < j at a bin is (|sum_m V_m|^2 - sum_m |V_m|^2)
+// / 2 (the delay-and-sum form of the same sum).  One wave: xf = [M][B] STFT
+// values, tm = tau_m / N; each lane takes bins b0 + lane + 64 j and returns
+// its partial sum (the caller reduces over the wave).  All STFT loads of a
+// block of NJ x 64 bins are issued before any is used.
 template <int MAXM>
-__device__ __forceinline__ float direction_power(const float2* __restrict__ xf, int M, int B,
-                                                 const float* __restrict__ tq, int lane) {
+__device__ __forceinline__ float power_ds(const float2* __restrict__ xf, int M, int B,
+                                          const float* __restrict__ tm, int lane) {
+    constexpr int NJ = MAXM <= 8 ? 5 : 1;
+    float t[MAXM];
+#pragma unroll
+    for (int m = 0; m < MAXM; ++m) t[m] = m < M ? tm[m] : 0.f;
     float acc = 0.f;
-    if (MAXM <= 8) {
-        // each lane takes bins b0 + lane + 64 j, j < NJ; the phase of bin
-        // b + 64 follows from that of bin b by one complex multiplication
-        constexpr int NJ = 5;
-        for (int b0 = 0; b0 < B; b0 += 64 * NJ) {
-            float nr[NJ][MAXM], ni[NJ][MAXM];
+    for (int b0 = 0; b0 < B; b0 += 64 * NJ) {
+        float2 v[NJ][MAXM];
 #pragma unroll
-            for (int j = 0; j < NJ; ++j)
-#pragma unroll
-                for (int m = 0; m < MAXM; ++m) {
-                    const int bin = b0 + lane + 64 * j;
-                    float2 v = (bin < B && m < M) ? xf[(int64_t)m * B + bin] : float2{0.f, 0.f};
-                    nr[j][m] = v.x;
-                    ni[j][m] = v.y;
-                    unit(nr[j][m], ni[j][m]);
-                }
-            int p = 0;
-#pragma unroll
-            for (int i = 0; i < MAXM; ++i)
-#pragma unroll
-                for (int k = i + 1; k < MAXM; ++k)
-                    if (k < M) {
-                        const float tn = tq[p];
-                        float t0 = (float)(b0 + lane) * tn;
-                        t0 -= rintf(t0);
-                        float t1 = 64.f * tn;
-                        t1 -= rintf(t1);
-                        float wr = __builtin_amdgcn_cosf(t0), wi = __builtin_amdgcn_sinf(t0);
-                        const float sr = __builtin_amdgcn_cosf(t1), si = __builtin_amdgcn_sinf(t1);
-#pragma unroll
-                        for (int j = 0; j < NJ; ++j) {
-                            const float xr = nr[j][i] * nr[j][k] + ni[j][i] * ni[j][k];
-                            const float xi = ni[j][i] * nr[j][k] - nr[j][i] * ni[j][k];
-                            acc = fmaf(wr, xr, fmaf(-wi, xi, acc));
-                            const float nwr = wr * sr - wi * si;
-                            wi = wr * si + wi * sr;
-                            wr = nwr;
-                        }
-                        ++p;
-                    }
-        }
-    } else {
-        for (int bin = lane; bin < B; bin += 64) {
-            float re[MAXM], im[MAXM];
+        for (int j = 0; j < NJ; ++j)
 #pragma unroll
             for (int m = 0; m < MAXM; ++m) {
-                const float2 v = m < M ? xf[(int64_t)m * B + bin] : float2{0.f, 0.f};
-                re[m] = v.x;
-                im[m] = v.y;
-                unit(re[m], im[m]);
+                const int bin = b0 + lane + 64 * j;
+                v[j][m] = xf[(bin < B && m < M) ? (int64_t)m * B + bin : 0];
             }
-            int p = 0;
+        // phase of the lane's first bin and its step over 64 bins, per mic
+        float cr[MAXM], ci[MAXM], sr[MAXM], si[MAXM];
 #pragma unroll
-            for (int i = 0; i < MAXM; ++i)
+        for (int m = 0; m < MAXM; ++m) {
+            float p0 = (float)(b0 + lane) * t[m];
+            p0 -= rintf(p0);
+            float p1 = 64.f * t[m];
+            p1 -= rintf(p1);
+            cr[m] = __builtin_amdgcn_cosf(p0);  // argument in revolutions
+            ci[m] = -__builtin_amdgcn_sinf(p0);
+            sr[m] = __builtin_amdgcn_cosf(p1);
+            si[m] = -__builtin_amdgcn_sinf(p1);
+        }
 #pragma unroll
-                for (int k = i + 1; k < MAXM; ++k)
-                    if (k < M) {
-                        const float xr = re[i] * re[k] + im[i] * im[k];
-                        const float xi = im[i] * re[k] - re[i] * im[k];
-                        float t = (float)bin * tq[p];
-                        t -= rintf(t);
-                        acc = fmaf(__builtin_amdgcn_cosf(t), xr, fmaf(-__builtin_amdgcn_sinf(t), xi, acc));
-                        ++p;
-                    }
+        for (int j = 0; j < NJ; ++j) {
+            const bool live = b0 + lane + 64 * j < B;
+            float sre = 0.f, sim = 0.f, cnt = 0.f;
+#pragma unroll
+            for (int m = 0; m < MAXM; ++m)
+                if (m < M) {
+                    const float2 x = v[j][m];
+                    const float m2 = x.x * x.x + x.y * x.y;
+                    const bool ok = live && __builtin_amdgcn_classf(m2, 0x100);
+                    const float s = __builtin_amdgcn_rsqf(m2);
+                    const float ur = ok ? x.x * s : 0.f, ui = ok ? x.y * s : 0.f;
+                    sre = fmaf(ur, cr[m], fmaf(-ui, ci[m], sre));
+                    sim = fmaf(ur, ci[m], fmaf(ui, cr[m], sim));
+                    cnt += ok ? 1.f : 0.f;
+                    const float nr = cr[m] * sr[m] - ci[m] * si[m];
+                    ci[m] = cr[m] * si[m] + ci[m] * sr[m];
+                    cr[m] = nr;
+                }
+            acc += 0.5f * (fmaf(sre, sre, sim * sim) - cnt);
         }
     }
     return acc;
 }
-
-
-// The STFT values one lane needs for direction_power, loaded early (before
-// the direction is known) so that their latency overlaps other work; used
-// when the frame has at most 5 x 64 bins and at most 8 microphones.
-template <int MAXM>
-struct PowerPrefetch {
-    static constexpr bool kRegs = MAXM <= 8;
-    static constexpr int NJ = 5;
-    float2 v[kRegs ? NJ : 1][kRegs ? MAXM : 1];
-    bool ok = false;
-    __device__ __forceinline__ void load(const float2* __restrict__ xf, int M, int B, int lane) {
-        if constexpr (kRegs) {
-            ok = B <= 64 * NJ;
-            if (!ok) return;
-#pragma unroll
-            for (int j = 0; j < NJ; ++j)
-#pragma unroll
-                for (int m = 0; m < MAXM; ++m) {
-                    const int bin = lane + 64 * j;
-                    v[j][m] = (bin < B && m < M) ? xf[(int64_t)m * B + bin] : float2{0.f, 0.f};
-                }
-        }
-    }
-    __device__ __forceinline__ float power(const float2* __restrict__ xf, int M, int B,
-                                           const float* __restrict__ tq, int lane) {
-        if constexpr (kRegs) {
-            if (ok) {
-                float nr[NJ][MAXM], ni[NJ][MAXM];
-#pragma unroll
-                for (int j = 0; j < NJ; ++j)
-#pragma unroll
-                    for (int m = 0; m < MAXM; ++m) {
-                        nr[j][m] = v[j][m].x;
-                        ni[j][m] = v[j][m].y;
-                        unit(nr[j][m], ni[j][m]);
-                    }
-                float acc = 0.f;
-                int p = 0;
-#pragma unroll
-                for (int i = 0; i < MAXM; ++i)
-#pragma unroll
-                    for (int k = i + 1; k < MAXM; ++k)
-                        if (k < M) {
-                            const float tn = tq[p];
-                            float t0 = (float)lane * tn;
-                            t0 -= rintf(t0);
-                            float t1 = 64.f * tn;
-                            t1 -= rintf(t1);
-                            float wr = __builtin_amdgcn_cosf(t0), wi = __builtin_amdgcn_sinf(t0);
-                            const float sr = __builtin_amdgcn_cosf(t1), si = __builtin_amdgcn_sinf(t1);
-#pragma unroll
-                            for (int j = 0; j < NJ; ++j) {
-                                const float xr = nr[j][i] * nr[j][k] + ni[j][i] * ni[j][k];
-                                const float xi = ni[j][i] * nr[j][k] - nr[j][i] * ni[j][k];
-                                acc = fmaf(wr, xr, fmaf(-wi, xi, acc));
-                                const float nwr = wr * sr - wi * si;
-                                wi = wr * si + wi * sr;
-                                wr = nwr;
-                            }
-                            ++p;
-                        }
-                return acc;
-            }
-        }
-        return direction_power<MAXM>(xf, M, B, tq, lane);
-    }
-};
 
 }  // namespace svdphat

@@ -96,6 +96,9 @@ struct FinalArgs {
     const int32_t* rows;    // [ncls] direction of each scored row
     const int32_t* rep;     // [Q] class representative
     const float* tauN;      // [Q][P] tau / N
+    const float* tauM;      // [Q][M] per-microphone tau / N
+    const int32_t* rowcls;  // [ncls_pad] class of each scored row
+    float usig_max;         // max ||U_q sigma|| (cheap bound of the hi/lo test)
     int64_t nfr;
     const int* flist;       // second pass: frames to redo
     const int* fcount;
@@ -197,6 +200,7 @@ struct svdphat_plan {
     uint32_t flags = 0;
     double residual = 0, fro2 = 0, kappa = 0;  // kappa = max_q ||U_q||
     std::vector<double> tau;     // [Q][P] delays in samples, eq. (2)
+    std::vector<double> tauM;    // [Q][M] per-microphone delays in samples
     std::vector<double> grid;    // [Q][3] unit directions
     std::vector<int32_t> rep;    // [Q] class representative
     std::vector<int32_t> rows;   // [ncls] direction index of each scored row
@@ -222,6 +226,9 @@ struct svdphat_plan {
     int32_t* d_rowof = nullptr;                  // [Q] scored row holding each direction's class
     float* d_tauN = nullptr;                     // [ncls][P] tau / N (rows of the search)
     float* d_tauN_all = nullptr;                 // [Q][P] tau / N
+    float* d_tauM_all = nullptr;                 // [Q][M] per-microphone tau / N
+    int32_t* d_rowcls = nullptr;                 // [ncls_pad] class of each scored row
+    float usig_max = 0.f;                        // max ||U_q sigma|| over scored rows
     int8_t* d_pi = nullptr;                      // [P] first mic of pair
     int8_t* d_pj = nullptr;                      // [P] second mic of pair
     float* Wfr = nullptr;                        // plain form operand (KEEP_W)

@@ -240,6 +240,17 @@ void build_plan(svdphat_plan* p, const double* mics, const double* grid) {
             p->tau[(size_t)q * P + k] = p->fs / p->c * d / n;
         }
     }
+    // per-microphone delays tau_m = fs/c r_m . s_q / ||s_q|| (tau of pair
+    // (i, j) is tau_j - tau_i); used by the power of the chosen direction
+    p->tauM.resize((size_t)Q * M);
+    for (int q = 0; q < Q; ++q) {
+        const double* s = grid + 3 * q;
+        const double n = std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+        for (int m = 0; m < M; ++m) {
+            const double* r = mics + 3 * m;
+            p->tauM[(size_t)q * M + m] = p->fs / p->c * (r[0] * s[0] + r[1] * s[1] + r[2] * s[2]) / n;
+        }
+    }
 
     // ---- classes of identical delay rows
     direction_classes(p->tau, Q, P, 1e-9, p->rep);
@@ -482,6 +493,17 @@ void build_plan(svdphat_plan* p, const double* mics, const double* grid) {
         for (int k = 0; k < K; ++k) sg[k] = sg[K + k] = (float)p->sigma[k];
         upload(sg, &d, bytes);
         p->d_sig = (float*)d;
+        // largest ||U_q sigma|| over the scored rows (bound of the hi/lo test)
+        double us = 0.0;
+        for (int r = 0; r < p->ncls; ++r) {
+            double nrm = 0.0;
+            for (int k = 0; k < p->Rp; ++k) {
+                const double v = (double)Ust[(size_t)r * p->Rp + k] * sg[k];
+                nrm += v * v;
+            }
+            us = std::max(us, std::sqrt(nrm));
+        }
+        p->usig_max = (float)(us * (1.0 + 1e-6));
     }
     {
         std::vector<int32_t> rows(p->rows);
@@ -499,6 +521,15 @@ void build_plan(svdphat_plan* p, const double* mics, const double* grid) {
         for (size_t i = 0; i < tn.size(); ++i) tn[i] = (float)(p->tau[i] / N);
         upload(tn, &d, bytes);
         p->d_tauN_all = (float*)d;
+        std::vector<float> tm(p->tauM.size());
+        for (size_t i = 0; i < tm.size(); ++i) tm[i] = (float)(p->tauM[i] / N);
+        upload(tm, &d, bytes);
+        p->d_tauM_all = (float*)d;
+        // class of each scored row (padding rows: class 0)
+        std::vector<int32_t> rc(p->ncls_pad, 0);
+        for (int r = 0; r < p->ncls; ++r) rc[r] = p->rep[p->rows[r]];
+        upload(rc, &d, bytes);
+        p->d_rowcls = (int32_t*)d;
         upload(pi, &d, bytes);
         p->d_pi = (int8_t*)d;
         upload(pj, &d, bytes);

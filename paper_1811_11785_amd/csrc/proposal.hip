@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void k_propose(const float* __restrict__ logit
                                                  const float* __restrict__ U32R, const int32_t* __restrict__ cstart,
                                                  const int32_t* __restrict__ crows, const int32_t* __restrict__ rows,
                                                  const float2* __restrict__ X, int M, int P, int B,
-                                                 const float* __restrict__ tauN, int64_t F, int32_t* __restrict__ doa,
+                                                 const float* __restrict__ tauM, int64_t F, int32_t* __restrict__ doa,
                                                  float* __restrict__ power, uint8_t* __restrict__ fell,
                                                  int* __restrict__ flist, int* __restrict__ fcount) {
     __shared__ float zs[4][1024];
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(256) void k_propose(const float* __restrict__ logit
         }
     }
     if (bq < 0 || bq == 0x7fffffff) bq = rows[0];
-    float acc = direction_power<MAXM>(X + f * M * B, M, B, tauN + (int64_t)bq * P, lane);
+    float acc = power_ds<MAXM>(X + f * M * B, M, B, tauM + (int64_t)bq * M, lane);
     acc = wave_sum(acc);
     if (lane == 0) {
         doa[f] = bq;
@@ -637,11 +637,11 @@ void proposal_locate(svdphat_proposal* pr, const float2* X, int64_t F, int topk,
     if (p->M <= 8)
         k_propose<8><<<dim3((unsigned)((F + 3) / 4)), 256, 0, s>>>(
             o.logits, pr->Cp, pr->C, topk, conf_min, o.z32, p->Rp, pr->d_U32R, pr->d_cell_start, pr->d_cell_rows,
-            p->d_rows, X, p->M, p->P, p->B, p->d_tauN_all, F, doa, power, fell, o.flist, pr->d_count);
+            p->d_rows, X, p->M, p->P, p->B, p->d_tauM_all, F, doa, power, fell, o.flist, pr->d_count);
     else
         k_propose<16><<<dim3((unsigned)((F + 3) / 4)), 256, 0, s>>>(
             o.logits, pr->Cp, pr->C, topk, conf_min, o.z32, p->Rp, pr->d_U32R, pr->d_cell_start, pr->d_cell_rows,
-            p->d_rows, X, p->M, p->P, p->B, p->d_tauN_all, F, doa, power, fell, o.flist, pr->d_count);
+            p->d_rows, X, p->M, p->P, p->B, p->d_tauM_all, F, doa, power, fell, o.flist, pr->d_count);
     SP_HIP(hipGetLastError());
     kt.end();
     // low-confidence frames: the full search on the listed frames only

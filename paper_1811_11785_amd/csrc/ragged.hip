@@ -225,6 +225,9 @@ void ragged_build(svdphat_ragged* r, uint32_t flags, const char* cache_path) {
         fa.rows = p->d_rows;
         fa.rep = p->d_rep;
         fa.tauN = p->d_tauN_all;
+        fa.tauM = p->d_tauM_all;
+        fa.rowcls = p->d_rowcls;
+        fa.usig_max = p->usig_max;
         fa.hilo_k = 4.f;
         fa.u = (float)u;
         r->h_desc[i] = d;
@@ -248,7 +251,8 @@ void ragged_build(svdphat_ragged* r, uint32_t flags, const char* cache_path) {
         lds[k1] = std::max(lds[k1], g1_lds_bytes(NRB, g.CW));
         for (int64_t bx = 0; bx < Fc / 4; ++bx) lists[{1, 0}].push_back(int4{i, (int)bx, 0, 0});
         const int ntile = p->ncls_pad / QTILE;
-        const int ureg = p->Rp / Mf<_Float16>::KSTEP <= 6 ? 1 : 0;
+        const int ksn = p->Rp / Mf<_Float16>::KSTEP;
+        const int ureg = ksn <= 6 ? ksn : 0;  // exact k-step class, 0: general form
         for (int bx = 0; bx < cdiv(ntile, 4); ++bx)
             for (int64_t by = 0; by < (F + r->fch[i] - 1) / r->fch[i]; ++by)
                 lists[{2, ureg}].push_back(int4{i, bx, (int)by, 0});

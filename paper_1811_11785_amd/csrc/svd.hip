@@ -335,12 +335,27 @@ __global__ __launch_bounds__(256) void k_zprep(const float* __restrict__ zpart, 
 }
 
 // ------------------------------------------------------------------ GEMM2
-// Wave = one tile of 64 scored directions; workgroup = 4 tiles x a range of
-// FCH frames.  With UREG the wave keeps the tile's U fragments (KSN k-steps)
-// in registers and streams the frames 16 at a time (the next frames' Z
-// fragments are loaded during the current MFMAs); the epilogue writes one
-// maximum per (frame, tile), frame-major: pmax[f * pstride + tile].
-template <typename T, int KSN, bool UREG>
+// Wave = one tile of 64 scored directions (4 row blocks); workgroup = 4 tiles
+// x a range of FCH frames, streamed 16 at a time.  With KSN > 0 (exactly
+// KSn k-steps) the wave keeps the tile's U fragments in registers and a
+// ring of two Z-fragment sets in flight (the loads of block b+2 are issued
+// after the MFMAs of block b, outside every branch, so the wait counts stay
+// exact; the ring's first values pass through an empty asm statement so the
+// compiler cannot merge the two load sites).  KSN = 0 is the general form
+// (U fragments read per k-step).  The epilogue keeps one maximum per (frame,
+// tile), frame-major: pmax[f * pstride + tile], scaled back by the power-of-
+// two scales of U and of the frame's Z.
+
+// maximum over lanes l, l ^ 16, l ^ 32, l ^ 48 (the four row groups of a
+// 16 x 16 MFMA result)
+__device__ __forceinline__ float max_rowgroups(float m) {
+    const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(m), __float_as_uint(m), false, false);
+    m = fmaxf(__uint_as_float(a[0]), __uint_as_float(a[1]));
+    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(m), __float_as_uint(m), false, false);
+    return fmaxf(__uint_as_float(b[0]), __uint_as_float(b[1]));
+}
+
+template <typename T, int KSN>
 __device__ __forceinline__ void gemm2_body(int bx, int by, const T* __restrict__ U, int KSn,
                                            const T* __restrict__ zfrag, int64_t nfr, int fch, int ncls, int ntile,
                                            const float* __restrict__ zscale, float uinv, float* __restrict__ pmax,
@@ -348,6 +363,7 @@ __device__ __forceinline__ void gemm2_body(int bx, int by, const T* __restrict__
                                            const int* __restrict__ fmap = nullptr,
                                            const int* __restrict__ fcount = nullptr) {
     constexpr int EPL = Mf<T>::EPL;
+    constexpr int NK = KSN > 0 ? KSN : 1;
     typedef typename Vec<T>::t VT;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int tile = bx * 4 + wave;
@@ -356,113 +372,118 @@ __device__ __forceinline__ void gemm2_body(int bx, int by, const T* __restrict__
     const int64_t fbeg = (int64_t)by * fch;
     const int64_t fend = min<int64_t>(fcount ? (int64_t)*fcount : nfr, fbeg + fch);
     if (fbeg >= fend) return;
-    VT a[4][UREG ? KSN : 1];
-    if (UREG) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int ks = 0; ks < KSN; ++ks)
-                if (ks < KSn)
-                    a[i][ks] = *reinterpret_cast<const VT*>(U + (((int64_t)(rb0 + i) * KSn + ks) * 64 + lane) * EPL);
-    }
-    bool rowok[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) rowok[i][e] = (rb0 + i) * 16 + 4 * (lane >> 4) + e < ncls;
+    const int64_t fb0 = fbeg >> 4, fbl = (fend - 1) >> 4;  // first and last frame block
+    const int nb = (int)(fbl - fb0 + 1);
+    // the last tile may hold padding rows, which must not take part
+    const bool masked = (tile + 1) * QTILE > ncls;
 
-    // Z fragments of the next two frame blocks are in flight while the
-    // current block's MFMAs run (ring of two register sets)
-    VT bq0[UREG ? KSN : 1], bq1[UREG ? KSN : 1];
-    float sq0 = 1.f, sq1 = 1.f;  // per-frame scale of the lane's frame
-    auto loadB = [&](VT* dst, float& sc, int64_t fb) {
-        const T* zb = zfrag + (fb * KSn * 64 + lane) * EPL;
-#pragma unroll
-        for (int ks = 0; ks < (UREG ? KSN : 1); ++ks)
-            if (ks < KSn) dst[ks] = *reinterpret_cast<const VT*>(zb + (int64_t)ks * 64 * EPL);
-        const int64_t f = fb * 16 + (lane & 15);
-        sc = f < fend ? zscale[f] : 1.f;
-    };
-    const int64_t fb0 = fbeg >> 4;
-    if (UREG) {
-        loadB(bq0, sq0, fb0);
-        if ((fb0 + 1) * 16 < fend) loadB(bq1, sq1, fb0 + 1);
-    }
-    for (int64_t fb = fb0; fb * 16 < fend; ++fb) {
-        f4 acc[4];
-        float zsc_cur = 1.f;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
-        if (UREG) {
-            VT b[KSN];
-            const bool even = ((fb - fb0) & 1) == 0;
-#pragma unroll
-            for (int ks = 0; ks < KSN; ++ks) b[ks] = even ? bq0[ks] : bq1[ks];
-            zsc_cur = even ? sq0 : sq1;
-            if ((fb + 2) * 16 < fend) {
-                if (even) loadB(bq0, sq0, fb + 2);
-                else loadB(bq1, sq1, fb + 2);
-            }
-#pragma unroll
-            for (int ks = 0; ks < KSN; ++ks)
-                if (ks < KSn)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) acc[i] = mfma(a[i][ks], b[ks], acc[i]);
-        } else {
-            const T* zb = zfrag + (fb * KSn * 64 + lane) * EPL;
-            for (int ks = 0; ks < KSn; ++ks) {
-                const VT b = *reinterpret_cast<const VT*>(zb + (int64_t)ks * 64 * EPL);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const VT ai = *reinterpret_cast<const VT*>(U + (((int64_t)(rb0 + i) * KSn + ks) * 64 + lane) * EPL);
-                    acc[i] = mfma(ai, b, acc[i]);
-                }
-            }
-        }
-        const int64_t f = fb * 16 + (lane & 15);
-        const bool live = f < fend;
-        const float inv = live ? uinv / (UREG ? zsc_cur : zscale[f]) : 0.f;
-        float m = -INFINITY;
+    VT a[4][NK];
+    if constexpr (KSN > 0) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (rowok[i][e]) m = fmaxf(m, acc[i][e]);
-        m = fmaxf(m, __shfl_xor(m, 16));
-        m = fmaxf(m, __shfl_xor(m, 32));
-        if (lane < 16 && live) pmax[(fmap ? (int64_t)fmap[f] : f) * pstride + tile] = m * inv;
-        if (ycls && live) {
+            for (int ks = 0; ks < KSN; ++ks)
+                a[i][ks] = *reinterpret_cast<const VT*>(U + (((int64_t)(rb0 + i) * KSN + ks) * 64 + lane) * EPL);
+    }
+    VT bz[2][NK];
+    float sc[2];
+    auto loadB = [&](int slot, int64_t fb) {
+        if constexpr (KSN > 0) {
+            const T* zb = zfrag + (fb * KSN * 64 + lane) * EPL;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int ks = 0; ks < KSN; ++ks) bz[slot][ks] = *reinterpret_cast<const VT*>(zb + (int64_t)ks * 64 * EPL);
+        }
+        sc[slot] = zscale[min(fb * 16 + (lane & 15), fend - 1)];
+    };
+    loadB(0, fb0);
+    loadB(1, min(fb0 + 1, fbl));
+    if constexpr (KSN > 0) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int row = (rb0 + i) * 16 + 4 * (lane >> 4) + e;
-                    if (row < ncls) ycls[f * yld + row] = acc[i][e] * inv;
+        for (int sl = 0; sl < 2; ++sl)
+#pragma unroll
+            for (int ks = 0; ks < KSN; ++ks) asm volatile("" : "+v"(bz[sl][ks]));
+    }
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) asm volatile("" : "+v"(sc[sl]));
+
+    for (int i0 = 0; i0 < nb; i0 += 2) {
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+            const int64_t fb = fb0 + i0 + sl;
+            if (i0 + sl < nb) {
+                f4 acc[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
+                if constexpr (KSN > 0) {
+#pragma unroll
+                    for (int ks = 0; ks < KSN; ++ks)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) acc[i] = mfma(a[i][ks], bz[sl][ks], acc[i]);
+                } else {
+                    const T* zb = zfrag + (fb * KSn * 64 + lane) * EPL;
+                    for (int ks = 0; ks < KSn; ++ks) {
+                        const VT b = *reinterpret_cast<const VT*>(zb + (int64_t)ks * 64 * EPL);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const VT ai =
+                                *reinterpret_cast<const VT*>(U + (((int64_t)(rb0 + i) * KSn + ks) * 64 + lane) * EPL);
+                            acc[i] = mfma(ai, b, acc[i]);
+                        }
+                    }
                 }
+                // D layout: lane holds rows 4 (lane / 16) + e of column (frame) lane % 16
+                const int64_t f = fb * 16 + (lane & 15);
+                const float inv = uinv * __builtin_amdgcn_rcpf(sc[sl]);  // both powers of two: exact
+                float m = -INFINITY;
+                if (!masked) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) m = fmaxf(m, acc[i][e]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if ((rb0 + i) * 16 + 4 * (lane >> 4) + e < ncls) m = fmaxf(m, acc[i][e]);
+                }
+                m = max_rowgroups(m);
+                if (lane < 16 && f < fend) pmax[(fmap ? (int64_t)fmap[f] : f) * pstride + tile] = m * inv;
+                if (ycls && f < fend) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int row = (rb0 + i) * 16 + 4 * (lane >> 4) + e;
+                            if (row < ncls) ycls[f * yld + row] = acc[i][e] * inv;
+                        }
+                }
+            }
+            loadB(sl, min(fb + 2, fbl));
         }
     }
 }
 
-template <typename T, int KSN, bool UREG>
+template <typename T, int KSN>
 __global__ __launch_bounds__(256) void k_gemm2(const T* __restrict__ U, int KSn, const T* __restrict__ zfrag,
                                                int64_t nfr, int fch, int ncls, int ntile,
                                                const float* __restrict__ zscale, float uinv,
                                                float* __restrict__ pmax, int64_t pstride, float* __restrict__ ycls,
                                                int64_t yld) {
-    gemm2_body<T, KSN, UREG>(blockIdx.x, blockIdx.y, U, KSn, zfrag, nfr, fch, ncls, ntile, zscale, uinv, pmax,
-                             pstride, ycls, yld);
+    gemm2_body<T, KSN>(blockIdx.x, blockIdx.y, U, KSn, zfrag, nfr, fch, ncls, ntile, zscale, uinv, pmax, pstride,
+                       ycls, yld);
 }
 
 // GEMM2 over a list of frames: position f of zfrag holds frame fmap[f];
 // the count is read on the device.
-template <int KSN, bool UREG>
+template <int KSN>
 __global__ __launch_bounds__(256) void k_gemm2_list(const _Float16* __restrict__ U, int KSn,
                                                     const _Float16* __restrict__ zfrag, int64_t nmax, int fch,
                                                     int ncls, int ntile, const float* __restrict__ zscale, float uinv,
                                                     float* __restrict__ pmax, int64_t pstride,
                                                     const int* __restrict__ fmap, const int* __restrict__ fcount) {
-    gemm2_body<_Float16, KSN, UREG>(blockIdx.x, blockIdx.y, U, KSn, zfrag, nmax, fch, ncls, ntile, zscale, uinv,
-                                    pmax, pstride, nullptr, 0, fmap, fcount);
+    gemm2_body<_Float16, KSN>(blockIdx.x, blockIdx.y, U, KSn, zfrag, nmax, fch, ncls, ntile, zscale, uinv, pmax,
+                              pstride, nullptr, 0, fmap, fcount);
 }
 
 // ------------------------------------------------------------------ final
@@ -484,7 +505,11 @@ __device__ __forceinline__ float row_dot(const float* __restrict__ ut, const flo
     return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
-// One wave per frame.
+// One wave per frame.  The memory traffic comes in three dependent rounds:
+// (1) the frame's tile maxima with their bounds, z and ||z||; (2) for each
+// candidate tile, its rows of the FP32 copy of U with their directions and
+// classes; (3) the per-microphone delays of the chosen class and the
+// frame's STFT values (the power).  Each round's loads are issued together.
 template <int MAXM, bool DEDUP>
 __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
     __shared__ float zs[4][1024];
@@ -493,10 +518,31 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
     const int64_t pos = (int64_t)bx * 4 + wave;
     if (pos >= n) return;
     const int64_t f = a.flist ? (int64_t)a.flist[pos] : pos;
-    const int Rp = a.Rp;
-    const float2* xf = a.X + f * a.M * a.B;
-    PowerPrefetch<MAXM> pp;
-    pp.load(xf, a.M, a.B, lane);
+    const int Rp = a.Rp, T = a.ntile;
+    const float* pm = a.pmax + f * a.pstride;
+
+    // ---- round 1: frame maximum over tiles, the tile holding it and that
+    // tile's bound (carried through the reduction), z into LDS
+    float ym = -INFINITY, km = 0.f;
+    int tm = 0x7fffffff;
+    for (int t0 = 0; t0 < T; t0 += 256) {
+        float pv[4], kv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int t = t0 + lane + 64 * j;
+            pv[j] = pm[t < T ? t : 0];
+            kv[j] = a.tkappa[t < T ? t : 0];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int t = t0 + lane + 64 * j;
+            if (t < T && better(pv[j], t, ym, tm)) {
+                ym = pv[j];
+                tm = t;
+                km = kv[j];
+            }
+        }
+    }
     const float* z = a.z32 + pos * Rp;
     float* zw = zs[wave];
     float dz2 = 0.f;
@@ -509,39 +555,27 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
         }
     }
     const float ef = a.ecoef * a.znorm1[f] + (a.z32_first ? 1.01f * sqrtf(wave_sum(dz2)) : 0.f);
-    wave_sync();
-
-    // frame maximum over tiles and the tile holding it
-    const float* pm = a.pmax + f * a.pstride;
-    const int64_t ps = 1;
-    float ym = -INFINITY;
-    int tm = 0x7fffffff;
-    for (int t = lane; t < a.ntile; t += 64) {
-        const float v = pm[t * ps];
-        if (better(v, t, ym, tm)) {
-            ym = v;
-            tm = t;
-        }
-    }
     for (int o = 32; o > 0; o >>= 1) {
-        const float oy = __shfl_xor(ym, o);
+        const float oy = __shfl_xor(ym, o), ok = __shfl_xor(km, o);
         const int ot = __shfl_xor(tm, o);
         if (better(oy, ot, ym, tm)) {
             ym = oy;
             tm = ot;
+            km = ok;
         }
     }
-    if (tm < 0 || tm >= a.ntile) tm = 0;
-    const float thr = a.rescore ? ym - a.tkappa[tm] * ef : ym;
+    wave_sync();
+    const float thr = a.rescore ? ym - km * ef : ym;
 
-    // rescore the candidate tiles in FP32: best (y1, q1, r1) and runner-up
+    // ---- round 2: rescore the candidate tiles in FP32: best (y1, q1, r1,
+    // class c1) and runner-up (y2, q2, r2)
     float y1 = -INFINITY, y2 = -INFINITY, ncmax = -INFINITY;
-    int q1 = 0x7fffffff, q2 = 0x7fffffff, r1 = -1, r2 = -1;
+    int q1 = 0x7fffffff, q2 = 0x7fffffff, r1 = -1, r2 = -1, c1 = 0;
     int ncand = 0;
-    for (int t0 = 0; t0 < a.ntile; t0 += 64) {
+    for (int t0 = 0; t0 < T; t0 += 64) {
         const int t = t0 + lane;
-        const float et = t < a.ntile ? (a.rescore ? a.tkappa[t] * ef : 0.f) : 0.f;
-        const float pv = t < a.ntile ? pm[t * ps] : -INFINITY;
+        const float et = t < T ? (a.rescore ? a.tkappa[t] * ef : 0.f) : 0.f;
+        const float pv = t < T ? pm[t] : -INFINITY;
         const bool cand = pv + et >= thr;
         if (!cand) ncmax = fmaxf(ncmax, pv + et);
         uint64_t mask = __ballot(cand);
@@ -550,10 +584,10 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
             const int tt = t0 + __ffsll((unsigned long long)mask) - 1;
             mask &= mask - 1;
             const int row = tt * QTILE + lane;
-            const float* ut = a.U32T + (int64_t)tt * Rp * QTILE + lane;
-            const float y = row_dot(ut, zw, Rp);
+            const int q = a.rows[row < a.ncls ? row : 0];
+            const int c = a.rowcls[row];
+            const float y = row_dot(a.U32T + (int64_t)tt * Rp * QTILE + lane, zw, Rp);
             if (row < a.ncls) {
-                const int q = a.rows[row];
                 if (better(y, q, y1, q1)) {
                     if (DEDUP) {
                         y2 = y1;
@@ -563,6 +597,7 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
                     y1 = y;
                     q1 = q;
                     r1 = row;
+                    c1 = c;
                 } else if (DEDUP && better(y, q, y2, q2)) {
                     y2 = y;
                     q2 = q;
@@ -576,6 +611,7 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
         const float oy1 = __shfl_xor(y1, o), oy2 = __shfl_xor(y2, o);
         const int oq1 = __shfl_xor(q1, o), oq2 = __shfl_xor(q2, o);
         const int or1 = __shfl_xor(r1, o), or2 = __shfl_xor(r2, o);
+        const int oc1 = __shfl_xor(c1, o);
         if (better(oy1, oq1, y1, q1)) {
             // new best is the other lane's; runner-up is the better of mine-best and other's second
             if (DEDUP) {
@@ -592,6 +628,7 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
             y1 = oy1;
             q1 = oq1;
             r1 = or1;
+            c1 = oc1;
         } else if (DEDUP && better(oy1, oq1, y2, q2)) {
             y2 = oy1;
             q2 = oq1;
@@ -601,24 +638,24 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
     if (q1 < 0 || q1 == 0x7fffffff) {  // no finite candidate
         q1 = a.rows[0];
         r1 = 0;
+        c1 = a.rowcls[0];
     }
-    const int cls = a.rep[q1];
+    const int cls = c1;
     if (!DEDUP) {
         // runner-up over directions of other classes among the candidates
         float sy = -INFINITY;
         int sr = -1;
-        for (int t0 = 0; t0 < a.ntile; t0 += 64) {
+        for (int t0 = 0; t0 < T; t0 += 64) {
             const int t = t0 + lane;
-            const float et = t < a.ntile ? (a.rescore ? a.tkappa[t] * ef : 0.f) : 0.f;
-            const float pv = t < a.ntile ? pm[t * ps] : -INFINITY;
+            const float et = t < T ? (a.rescore ? a.tkappa[t] * ef : 0.f) : 0.f;
+            const float pv = t < T ? pm[t] : -INFINITY;
             uint64_t mask = __ballot(pv + et >= thr);
             while (mask) {
                 const int tt = t0 + __ffsll((unsigned long long)mask) - 1;
                 mask &= mask - 1;
                 const int row = tt * QTILE + lane;
-                if (row < a.ncls && a.rep[a.rows[row]] != cls) {
-                    const float* ut = a.U32T + (int64_t)tt * Rp * QTILE + lane;
-                    const float y = row_dot(ut, zw, Rp);
+                if (row < a.ncls && a.rowcls[row] != cls) {
+                    const float y = row_dot(a.U32T + (int64_t)tt * Rp * QTILE + lane, zw, Rp);
                     if (y > sy) {
                         sy = y;
                         sr = row;
@@ -643,9 +680,11 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
 
     // hi/lo trigger (first pass): GEMM1 rounding perturbs z_r by about u
     // sigma_r (random signs), so y1 - y2 moves by about u ||(U_q1 - U_q2)
-    // sigma||; frames whose rescored gap is within hilo_k times that are redone
+    // sigma||; frames whose rescored gap is within hilo_k times that are
+    // redone.  ||(U_q1 - U_q2) sigma|| <= 2 max_q ||U_q sigma|| decides most
+    // frames without loading the two rows.
     bool redo = false;
-    if (a.hlist && !a.flist) {
+    if (a.hlist && !a.flist && (y1 - yr) < a.hilo_k * a.u * 2.f * a.usig_max) {
         float d2 = 0.f;
         if (r2 >= 0 && y2 >= ncmax) {
             const float* u1 = a.U32T + (int64_t)(r1 / QTILE) * Rp * QTILE + r1 % QTILE;
@@ -657,13 +696,14 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
             d2 = wave_sum(d2);
         } else {
             // runner-up not rescored: bound with the largest row difference
-            d2 = 4.f * a.sig[0] * a.sig[0];
+            d2 = 4.f * a.usig_max * a.usig_max;
         }
         redo = (y1 - yr) < a.hilo_k * a.u * sqrtf(d2);
     }
 
-    // Algorithm 1 online step 4: power of the chosen direction from its row of W
-    float acc = pp.power(xf, a.M, a.B, a.tauN + (int64_t)cls * a.P, lane);
+    // ---- round 3: Algorithm 1 online step 4, the power of the chosen
+    // direction from its row of W (delay-and-sum form)
+    float acc = power_ds<MAXM>(a.X + f * a.M * a.B, a.M, a.B, a.tauM + (int64_t)cls * a.M, lane);
     acc = wave_sum(acc);
     if (lane == 0) {
         a.doa[f] = cls;
@@ -714,11 +754,11 @@ __global__ __launch_bounds__(256) void k_zprep_grouped(const RDesc* __restrict__
                          a.zn, 1);
 }
 
-template <int KSN, bool UREG>
+template <int KSN>
 __global__ __launch_bounds__(256) void k_gemm2_grouped(const RDesc* __restrict__ d, const int4* __restrict__ work) {
     const int4 w = work[blockIdx.x];
     const RDesc& a = d[w.x];
-    gemm2_body<_Float16, KSN, UREG>(w.y, w.z, (const _Float16*)a.U, a.KSn, (const _Float16*)a.zfrag, a.F, a.fch,
+    gemm2_body<_Float16, KSN>(w.y, w.z, (const _Float16*)a.U, a.KSn, (const _Float16*)a.zfrag, a.F, a.fch,
                                     a.ncls, a.ntile, a.zsc, a.uinv, a.pmax, a.pstride, nullptr, 0);
 }
 
@@ -806,24 +846,45 @@ int launch_g1(int ftiles, int nsplit, hipStream_t s, const float2* X, int64_t F,
     return NRB;
 }
 
+// frames per GEMM2 workgroup: about one wave per 4096 (tile, 16-frame
+// block) pairs, so the grid is about one round of four waves per SIMD
+int g2_frames(int ntile, int64_t F) {
+    const int64_t blocks = (int64_t)ntile * ((F + 15) / 16);
+    const int64_t per = std::max<int64_t>(1, (blocks + 4095) / 4096);
+    return (int)std::min<int64_t>(16 * per, 4096);
+}
+
 template <typename T>
 void launch_g2(svdphat_plan* p, int prec, const T* zfrag, int64_t F, const float* zsc, float* pmax,
                int64_t pstride, float* ycls, hipStream_t s) {
     constexpr int KS = Mf<T>::KSTEP;
     const int KSn = p->Rp / KS;
     const int ntile = p->ncls_pad / QTILE;
-    const int fch = 256;
+    const int fch = g2_frames(ntile, F);
     dim3 grid(cdiv(ntile, 4), (unsigned)((F + fch - 1) / fch));
     const float uinv = 1.f / p->uscale[prec];
     const T* U = (const T*)p->Ufr[prec];
+#define SP_G2(N) k_gemm2<T, N><<<grid, 256, 0, s>>>(U, KSn, zfrag, F, fch, p->ncls, ntile, zsc, uinv, pmax, pstride, \
+                                                    ycls, p->ncls_pad)
     // U fragments of the tile stay in registers when they fit (<= 96 VGPRs)
-    constexpr int KREG = sizeof(T) == 4 ? 24 : 6;
-    if (KSn <= KREG)
-        k_gemm2<T, KREG, true><<<grid, 256, 0, s>>>(U, KSn, zfrag, F, fch, p->ncls, ntile, zsc, uinv, pmax,
-                                                     pstride, ycls, p->ncls_pad);
-    else
-        k_gemm2<T, 1, false><<<grid, 256, 0, s>>>(U, KSn, zfrag, F, fch, p->ncls, ntile, zsc, uinv, pmax, pstride,
-                                                   ycls, p->ncls_pad);
+    if constexpr (sizeof(T) == 2) {
+        switch (KSn) {
+            case 1: SP_G2(1); return;
+            case 2: SP_G2(2); return;
+            case 3: SP_G2(3); return;
+            case 4: SP_G2(4); return;
+            case 5: SP_G2(5); return;
+            case 6: SP_G2(6); return;
+        }
+    } else {
+        switch (KSn) {
+            case 8: SP_G2(8); return;
+            case 16: SP_G2(16); return;
+            case 24: SP_G2(24); return;
+        }
+    }
+    SP_G2(0);
+#undef SP_G2
 }
 
 void launch_final(const FinalArgs& fa, int M, bool dedup, int64_t nwaves, hipStream_t s) {
@@ -980,6 +1041,9 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     fa.rows = p->d_rows;
     fa.rep = p->d_rep;
     fa.tauN = p->d_tauN_all;
+    fa.tauM = p->d_tauM_all;
+    fa.rowcls = p->d_rowcls;
+    fa.usig_max = p->usig_max;
     fa.nfr = F;
     fa.doa = doa;
     fa.power = power;
@@ -1071,12 +1135,19 @@ void back_list_fp16(svdphat_plan* p, const float2* X, int64_t Fmax, const int* f
     const int fch = 256;
     dim3 grid(cdiv(ntile, 4), (unsigned)((Fmax + fch - 1) / fch));
     const float uinv = 1.f / p->uscale[P_FP16];
-    if (KSn <= 6)
-        k_gemm2_list<6, true><<<grid, 256, 0, s>>>((const _Float16*)p->Ufr[P_FP16], KSn, zfrag, Fmax, fch, p->ncls,
-                                                   ntile, zsc, uinv, pmax, pstride, flist, fcount);
-    else
-        k_gemm2_list<1, false><<<grid, 256, 0, s>>>((const _Float16*)p->Ufr[P_FP16], KSn, zfrag, Fmax, fch, p->ncls,
-                                                    ntile, zsc, uinv, pmax, pstride, flist, fcount);
+#define SP_G2L(N)                                                                                             \
+    k_gemm2_list<N><<<grid, 256, 0, s>>>((const _Float16*)p->Ufr[P_FP16], KSn, zfrag, Fmax, fch, p->ncls, ntile, zsc, \
+                                         uinv, pmax, pstride, flist, fcount)
+    switch (KSn) {
+        case 1: SP_G2L(1); break;
+        case 2: SP_G2L(2); break;
+        case 3: SP_G2L(3); break;
+        case 4: SP_G2L(4); break;
+        case 5: SP_G2L(5); break;
+        case 6: SP_G2L(6); break;
+        default: SP_G2L(0); break;
+    }
+#undef SP_G2L
     SP_HIP(hipGetLastError());
     FinalArgs fa{};
     fa.X = X;
@@ -1099,6 +1170,9 @@ void back_list_fp16(svdphat_plan* p, const float2* X, int64_t Fmax, const int* f
     fa.rows = p->d_rows;
     fa.rep = p->d_rep;
     fa.tauN = p->d_tauN_all;
+    fa.tauM = p->d_tauM_all;
+    fa.rowcls = p->d_rowcls;
+    fa.usig_max = p->usig_max;
     fa.nfr = Fmax;
     fa.flist = flist;
     fa.fcount = fcount;
@@ -1125,7 +1199,8 @@ void g1_split(const svdphat_plan* p, int64_t F, int want, int* nsplit, int* cps)
 }
 
 // Grouped launch classes: GEMM1 cls = NRB class * 2 + (M > 8); GEMM2 cls =
-// 1 if the tile's U fragments stay in registers; search cls = (M > 8).
+// the k-step count when the tile's U fragments stay in registers (1-6), else
+// 0; search cls = (M > 8).
 void launch_grouped(const GroupLaunch& g, const RDesc* d, hipStream_t s) {
     if (g.nwork <= 0) return;
     dim3 grid((unsigned)g.nwork);
@@ -1144,8 +1219,15 @@ void launch_grouped(const GroupLaunch& g, const RDesc* d, hipStream_t s) {
     } else if (g.stage == 1) {
         k_zprep_grouped<<<grid, 256, 0, s>>>(d, g.work);
     } else if (g.stage == 2) {
-        if (g.cls) k_gemm2_grouped<6, true><<<grid, 256, 0, s>>>(d, g.work);
-        else k_gemm2_grouped<1, false><<<grid, 256, 0, s>>>(d, g.work);
+        switch (g.cls) {
+            case 1: k_gemm2_grouped<1><<<grid, 256, 0, s>>>(d, g.work); break;
+            case 2: k_gemm2_grouped<2><<<grid, 256, 0, s>>>(d, g.work); break;
+            case 3: k_gemm2_grouped<3><<<grid, 256, 0, s>>>(d, g.work); break;
+            case 4: k_gemm2_grouped<4><<<grid, 256, 0, s>>>(d, g.work); break;
+            case 5: k_gemm2_grouped<5><<<grid, 256, 0, s>>>(d, g.work); break;
+            case 6: k_gemm2_grouped<6><<<grid, 256, 0, s>>>(d, g.work); break;
+            default: k_gemm2_grouped<0><<<grid, 256, 0, s>>>(d, g.work); break;
+        }
     } else {
         if (g.cls) k_final_grouped<16><<<grid, 256, 0, s>>>(d, g.work);
         else k_final_grouped<8><<<grid, 256, 0, s>>>(d, g.work);
@@ -1193,16 +1275,20 @@ void tune_time(svdphat_plan* p, int64_t F, int nsplit_want, int fch, double* us_
     const int KSn = Rp / Mf<_Float16>::KSTEP;
     dim3 grid(cdiv(ntile, 4), (unsigned)((F + fch - 1) / fch));
     for (int it = 0; it < reps; ++it) {
-        if (KSn <= 6)
-            k_gemm2<_Float16, 6, true><<<grid, 256, 0, s>>>((const _Float16*)p->Ufr[P_FP16], KSn,
-                                                            (const _Float16*)(w + o_zf), F, fch, p->ncls, ntile,
-                                                            (const float*)(w + o_sc), 1.f, (float*)(w + o_pm), pmax_stride(p),
-                                                            nullptr, 0);
-        else
-            k_gemm2<_Float16, 1, false><<<grid, 256, 0, s>>>((const _Float16*)p->Ufr[P_FP16], KSn,
-                                                             (const _Float16*)(w + o_zf), F, fch, p->ncls, ntile,
-                                                             (const float*)(w + o_sc), 1.f, (float*)(w + o_pm), pmax_stride(p),
-                                                             nullptr, 0);
+#define SP_G2T(N)                                                                                            \
+    k_gemm2<_Float16, N><<<grid, 256, 0, s>>>((const _Float16*)p->Ufr[P_FP16], KSn, (const _Float16*)(w + o_zf), F, \
+                                              fch, p->ncls, ntile, (const float*)(w + o_sc), 1.f,                   \
+                                              (float*)(w + o_pm), pmax_stride(p), nullptr, 0)
+        switch (KSn) {
+            case 1: SP_G2T(1); break;
+            case 2: SP_G2T(2); break;
+            case 3: SP_G2T(3); break;
+            case 4: SP_G2T(4); break;
+            case 5: SP_G2T(5); break;
+            case 6: SP_G2T(6); break;
+            default: SP_G2T(0); break;
+        }
+#undef SP_G2T
     }
     SP_HIP(hipEventRecord(e[2], s));
     SP_HIP(hipGetLastError());
