@@ -108,17 +108,17 @@ void timing_count(const char* name, double count, int64_t calls) {
     e.second += calls;
 }
 
-void KernelTimer::begin(const char* name) {
+void KernelTimer::begin(const char* name, hipStream_t on) {
     if (!timing_on()) return;
-    Rec r{name, nullptr, nullptr};
+    Rec r{name, nullptr, nullptr, on ? on : s};
     SP_HIP(hipEventCreate(&r.a));
     SP_HIP(hipEventCreate(&r.b));
-    SP_HIP(hipEventRecord(r.a, s));
+    SP_HIP(hipEventRecord(r.a, r.s));
     recs.push_back(r);
 }
 void KernelTimer::end() {
     if (!timing_on() || recs.empty()) return;
-    SP_HIP(hipEventRecord(recs.back().b, s));
+    SP_HIP(hipEventRecord(recs.back().b, recs.back().s));
 }
 void KernelTimer::flush() {
     for (auto& r : recs) {

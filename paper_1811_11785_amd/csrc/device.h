@@ -93,25 +93,36 @@ __device__ __forceinline__ bool better(float a, int ia, float b, int ib) {
 // X_m / |X_m| (0 for a silent bin: |X_m|^2 not a finite normal float), and
 // the sum over the pairs i < j at a bin is (|sum_m V_m|^2 - sum_m |V_m|^2)
 // / 2 (the delay-and-sum form of the same sum).  One wave: xf = [M][B] STFT
-// values, tm = tau_m / N; each lane takes bins b0 + lane + 64 j and returns
-// its partial sum (the caller reduces over the wave).  All STFT loads of a
-// block of NJ x 64 bins are issued before any is used.
+// values, t[m] = tau_m / N; lanes take bins lane + 64 j of the first
+// Bmain = B - tail bins (all STFT loads of a block of 4 x 64 bins issued
+// before any is used), and the last `tail` bins (B mod 64 when tail x M <=
+// 64, typically the Nyquist bin) one (bin, microphone) per lane.  Returns
+// the wave's total.
+__device__ __forceinline__ float ds_term(float2 x, bool live, float cr, float ci, float& sre, float& sim) {
+    const float m2 = x.x * x.x + x.y * x.y;
+    const bool ok = live && __builtin_amdgcn_classf(m2, 0x100);
+    const float s = __builtin_amdgcn_rsqf(m2);
+    const float ur = ok ? x.x * s : 0.f, ui = ok ? x.y * s : 0.f;
+    sre = fmaf(ur, cr, fmaf(-ui, ci, sre));
+    sim = fmaf(ur, ci, fmaf(ui, cr, sim));
+    return ok ? 1.f : 0.f;
+}
+
 template <int MAXM>
-__device__ __forceinline__ float power_ds(const float2* __restrict__ xf, int M, int B,
-                                          const float* __restrict__ tm, int lane) {
-    constexpr int NJ = MAXM <= 8 ? 5 : 1;
-    float t[MAXM];
-#pragma unroll
-    for (int m = 0; m < MAXM; ++m) t[m] = m < M ? tm[m] : 0.f;
+__device__ __forceinline__ float power_ds(const float2* __restrict__ xf, int M, int B, const float (&t)[MAXM],
+                                          int lane) {
+    constexpr int NJ = MAXM <= 8 ? 4 : 1;
+    const int tail = ((B % 64) * M <= 64) ? B % 64 : 0;
+    const int Bm = B - tail;
     float acc = 0.f;
-    for (int b0 = 0; b0 < B; b0 += 64 * NJ) {
+    for (int b0 = 0; b0 < Bm; b0 += 64 * NJ) {
         float2 v[NJ][MAXM];
 #pragma unroll
         for (int j = 0; j < NJ; ++j)
 #pragma unroll
             for (int m = 0; m < MAXM; ++m) {
                 const int bin = b0 + lane + 64 * j;
-                v[j][m] = xf[(bin < B && m < M) ? (int64_t)m * B + bin : 0];
+                v[j][m] = xf[(bin < Bm && m < M) ? (int64_t)m * B + bin : 0];
             }
         // phase of the lane's first bin and its step over 64 bins, per mic
         float cr[MAXM], ci[MAXM], sr[MAXM], si[MAXM];
@@ -128,19 +139,12 @@ __device__ __forceinline__ float power_ds(const float2* __restrict__ xf, int M, 
         }
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-            const bool live = b0 + lane + 64 * j < B;
+            const bool live = b0 + lane + 64 * j < Bm;
             float sre = 0.f, sim = 0.f, cnt = 0.f;
 #pragma unroll
             for (int m = 0; m < MAXM; ++m)
                 if (m < M) {
-                    const float2 x = v[j][m];
-                    const float m2 = x.x * x.x + x.y * x.y;
-                    const bool ok = live && __builtin_amdgcn_classf(m2, 0x100);
-                    const float s = __builtin_amdgcn_rsqf(m2);
-                    const float ur = ok ? x.x * s : 0.f, ui = ok ? x.y * s : 0.f;
-                    sre = fmaf(ur, cr[m], fmaf(-ui, ci[m], sre));
-                    sim = fmaf(ur, ci[m], fmaf(ui, cr[m], sim));
-                    cnt += ok ? 1.f : 0.f;
+                    cnt += ds_term(v[j][m], live, cr[m], ci[m], sre, sim);
                     const float nr = cr[m] * sr[m] - ci[m] * si[m];
                     ci[m] = cr[m] * si[m] + ci[m] * sr[m];
                     cr[m] = nr;
@@ -148,7 +152,25 @@ __device__ __forceinline__ float power_ds(const float2* __restrict__ xf, int M, 
             acc += 0.5f * (fmaf(sre, sre, sim * sim) - cnt);
         }
     }
-    return acc;
+    float tot = wave_sum(acc);
+    // tail bins: lane = (bin - Bm) * M + m
+    for (int tb = 0; tb < tail; ++tb) {
+        const int bin = Bm + tb;
+        const bool mine = lane >= tb * M && lane < (tb + 1) * M;
+        const int m = lane - tb * M;
+        const float2 x = xf[mine ? (int64_t)m * B + bin : 0];
+        float tm = 0.f;
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k)
+            if (k == m) tm = t[k];
+        float p0 = (float)bin * tm;
+        p0 -= rintf(p0);
+        float sre = 0.f, sim = 0.f;
+        const float cnt = ds_term(x, mine, __builtin_amdgcn_cosf(p0), -__builtin_amdgcn_sinf(p0), sre, sim);
+        const float sr = wave_sum(sre), sm = wave_sum(sim), c = wave_sum(cnt);
+        tot += 0.5f * (fmaf(sr, sr, sm * sm) - c);
+    }
+    return tot;
 }
 
 }  // namespace svdphat

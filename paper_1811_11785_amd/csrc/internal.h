@@ -291,11 +291,14 @@ struct KernelTimer {
     struct Rec {
         const char* name;
         hipEvent_t a, b;
+        hipStream_t s;
     };
     hipStream_t s;
     std::vector<Rec> recs;
     explicit KernelTimer(hipStream_t st) : s(st) {}
-    void begin(const char* name);
+    // times the work enqueued on stream `on` (default: the timer's stream)
+    // between begin() and the next end()
+    void begin(const char* name, hipStream_t on = nullptr);
     void end();
     void flush();
     ~KernelTimer();

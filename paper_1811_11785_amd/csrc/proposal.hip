@@ -302,8 +302,10 @@ __global__ __launch_bounds__(256) void k_propose(const float* __restrict__ logit
         }
     }
     if (bq < 0 || bq == 0x7fffffff) bq = rows[0];
-    float acc = power_ds<MAXM>(X + f * M * B, M, B, tauM + (int64_t)bq * M, lane);
-    acc = wave_sum(acc);
+    float t[MAXM];
+#pragma unroll
+    for (int m = 0; m < MAXM; ++m) t[m] = m < M ? tauM[(int64_t)bq * M + m] : 0.f;
+    const float acc = power_ds<MAXM>(X + f * M * B, M, B, t, lane);
     if (lane == 0) {
         doa[f] = bq;
         power[f] = acc;

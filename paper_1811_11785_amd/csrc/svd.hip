@@ -701,13 +701,19 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
         redo = (y1 - yr) < a.hilo_k * a.u * sqrtf(d2);
     }
 
-    // ---- round 3: Algorithm 1 online step 4, the power of the chosen
-    // direction from its row of W (delay-and-sum form)
-    float acc = power_ds<MAXM>(a.X + f * a.M * a.B, a.M, a.B, a.tauM + (int64_t)cls * a.M, lane);
-    acc = wave_sum(acc);
+    // ---- round 3 (when the power is not left to k_power): Algorithm 1
+    // online step 4, the power of the chosen direction from its row of W
+    // (delay-and-sum form)
+    float acc = 0.f;
+    if (a.power) {
+        float t[MAXM];
+#pragma unroll
+        for (int m = 0; m < MAXM; ++m) t[m] = m < a.M ? a.tauM[(int64_t)cls * a.M + m] : 0.f;
+        acc = power_ds<MAXM>(a.X + f * a.M * a.B, a.M, a.B, t, lane);
+    }
     if (lane == 0) {
         a.doa[f] = cls;
-        a.power[f] = acc;
+        if (a.power) a.power[f] = acc;
         if (a.yhat) a.yhat[f] = y1;
         if (a.margin) a.margin[f] = mg;
         if (redo) {
@@ -733,6 +739,36 @@ __global__ __launch_bounds__(256) void k_final_list(FinalArgs a) {
     for (int64_t bx = blockIdx.x; bx * 4 < n; bx += gridDim.x) final_body<MAXM, DEDUP>((int)bx, a);
 }
 
+
+// Algorithm 1 online step 4 for every frame once the search is final: the
+// power of direction doa[f] from its row of W (delay-and-sum form).  One
+// wave per frame; the frame, its direction and the direction's delays are
+// wave-uniform (scalar loads), so the STFT loads are the only vector loads.
+// (With flist, the frames flist[0 .. *fcount), grid-stride.)
+template <int MAXM>
+__global__ __launch_bounds__(256) void k_power(const float2* __restrict__ X, int M, int B,
+                                               const int32_t* __restrict__ doa, const float* __restrict__ tauM,
+                                               int64_t nfr, float* __restrict__ power,
+                                               const int* __restrict__ flist, const int* __restrict__ fcount) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t n = fcount ? (int64_t)*fcount : nfr;
+    for (int64_t pos = (int64_t)blockIdx.x * 4 + wave; pos < n; pos += (int64_t)gridDim.x * 4) {
+        const int64_t f = flist ? (int64_t)__builtin_amdgcn_readfirstlane(flist[pos]) : pos;
+        const int q = __builtin_amdgcn_readfirstlane(doa[f]);
+        float t[MAXM];
+#pragma unroll
+        for (int m = 0; m < MAXM; ++m) t[m] = m < M ? tauM[(int64_t)q * M + m] : 0.f;
+        const float acc = power_ds<MAXM>(X + f * M * B, M, B, t, lane);
+        if (lane == 0) power[f] = acc;
+    }
+}
+
+void launch_power(const svdphat_plan* p, const float2* X, const int32_t* doa, int64_t F, float* power,
+                  const int* flist, const int* fcount, hipStream_t s) {
+    const dim3 grid(flist ? 512u : (unsigned)((F + 3) / 4));
+    if (p->M <= 8) k_power<8><<<grid, 256, 0, s>>>(X, p->M, p->B, doa, p->d_tauM_all, F, power, flist, fcount);
+    else k_power<16><<<grid, 256, 0, s>>>(X, p->M, p->B, doa, p->d_tauM_all, F, power, flist, fcount);
+}
 
 // ------------------------------------------------------------------ grouped
 // Ragged batches: one launch per stage and template class walks a device
@@ -1046,7 +1082,7 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     fa.usig_max = p->usig_max;
     fa.nfr = F;
     fa.doa = doa;
-    fa.power = power;
+    fa.power = nullptr;  // k_power below, after the hi/lo pass
     fa.yhat = yhat;
     fa.margin = margin;
     fa.hilo_k = 4.f;
@@ -1082,6 +1118,11 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
         SP_HIP(hipGetLastError());
         kt.end();
     }
+    // Algorithm 1 online step 4 for every frame, once the directions are final
+    kt.begin("power");
+    launch_power(p, X, doa, F, power, nullptr, nullptr, s);
+    SP_HIP(hipGetLastError());
+    kt.end();
     kt.flush();
     if (stats) {
         unsigned long long h[4] = {0, 0, 0, 0};
