@@ -2,7 +2,7 @@
 // the PHAT cross-spectra (eq. (3)) formed on chip, for 16-bit operands, 6 to
 // 8 microphones and all row blocks of Z in one workgroup.
 //
-// Work units are (frame tile of 64 frames, chunk of 8 bins) pairs in tile-
+// Work units are (frame tile of 64 frames, chunk of BB bins) pairs in tile-
 // major order; a persistent grid of G workgroups (one per CU) takes equal
 // contiguous ranges of units, so every workgroup streams its STFT values
 // without a break from its first unit to its last.  A workgroup has 8
@@ -12,9 +12,11 @@
 //     one 16-byte load per microphone) and form each unit's PHAT tile
 //     (per-mic unit normalisation, then X_i conj(X_j) for pairs i < j in
 //     order, rounded to T, stored as (Re, Im)) in one of two LDS buffers;
-//   consumers (waves 0-3) take KSC/4 of the unit's KSC k-steps, load their A
-//     fragments and run the MFMAs, each accumulating every (row block, frame
-//     block) of the tile's Z; at the end of a frame tile (or of the range)
+//   consumers (waves 0-3) take two of the unit's 8 k-steps (a chunk is the
+//     largest even number of bins whose stacked values fit 8 k-steps of 32),
+//     keep a ring of two units of A fragments in flight and run the MFMAs,
+//     each accumulating every (row block, frame block) of the tile's Z; at
+//     the end of a frame tile (or of the range)
 //     each consumer writes its partial sum to its own slot: slot
 //     4 (w - w0) + wave, w0 the first workgroup whose range meets the tile.
 // One barrier per unit hands a PHAT tile from the producers to the
@@ -25,7 +27,7 @@
 // it issued earlier.  Splitting the roles keeps the two streams apart: the
 // producers' STFT loads run XD units ahead without the consumers' A loads
 // queueing behind them, and each consumer issues the A fragments of unit
-// u+1 as soon as the MFMAs of unit u that read those registers are issued.
+// u+2 as soon as the MFMAs of unit u that read those registers are issued.
 // Loop-carried registers are first filled outside the loop; an empty asm
 // statement on those first values keeps the compiler from merging the two
 // load sites into one load at the top of the loop (which would turn every
@@ -43,13 +45,14 @@ namespace svdphat {
 namespace {
 
 constexpr int G1S_NF = 64;
-constexpr int G1S_BB = 8;   // bins per chunk (64 frames x 4 bin pairs = 256 producer threads)
+constexpr int G1S_KSC = 8;  // k-steps per chunk (two per consumer wave)
 constexpr int G1S_PAD = 8;  // LDS row padding (elements)
-constexpr int G1S_XD = 4;   // chunks of STFT values in flight (even)
+constexpr int G1S_XD = 4;   // units of STFT values in flight (even)
+constexpr int G1S_AD = 2;   // units of A fragments in flight
 
-// k-steps per chunk for MM microphones (8 bins x MM (MM - 1) stacked values,
-// rounded up to a multiple of four k-steps of 32)
-constexpr int g1s_ksc(int MM) { return (G1S_BB * MM * (MM - 1) + 127) / 128 * 4; }
+// bins per chunk for MM microphones: the largest even count whose stacked
+// values (MM (MM - 1) per bin) fit the chunk's 8 k-steps of 32
+constexpr int g1s_bb(int MM) { return (G1S_KSC * 32 / (MM * (MM - 1))) & ~1; }
 
 // four floats read with one 16-byte load from an 8-byte aligned address
 struct __attribute__((aligned(8))) f4u {
@@ -75,12 +78,13 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
                                                 float* __restrict__ zpart, int64_t zstride, int Rp) {
     constexpr int KS = Mf<T>::KSTEP, EPL = Mf<T>::EPL, NF = G1S_NF, FB = NF / 16;
     constexpr int P = MM * (MM - 1) / 2, TWOP = 2 * P;
-    constexpr int BB = G1S_BB, BP = BB / 2;
-    constexpr int KSC = g1s_ksc(MM), KPW = KSC / 4;
+    constexpr int BB = g1s_bb(MM), BP = BB / 2;
+    constexpr int KSC = G1S_KSC, KPW = KSC / 4, AD = G1S_AD;
     constexpr int CW = KSC * KS;      // stacked values per chunk (BB * TWOP used)
     constexpr int LDX = CW + G1S_PAD;
     constexpr int PADC = CW - BB * TWOP;
-    static_assert(NF * BP == 256 && KSC % 4 == 0 && XD % 2 == 0, "chunk layout");
+    constexpr int PL = NF * BP / 4;   // (frame, bin pair) items per producer wave
+    static_assert(BB >= 2 && PL <= 64 && (NF * BP) % 4 == 0 && XD % 2 == 0, "chunk layout");
     typedef typename Vec<T>::t VT;
     typedef typename Vec<T>::pair VP;
     extern __shared__ __align__(16) char smem[];
@@ -103,9 +107,12 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
 
     if (wave >= 4) {
         // ---------------------------------------------------------- producer
-        // thread ptid: frame ptid / BP, bins 2 (ptid % BP) and 2 (ptid % BP) + 1
-        const int ptid = tid - 256;
-        const int fl = ptid / BP, b0 = 2 * (ptid % BP);
+        // item (frame it / BP, bins 2 (it % BP) and 2 (it % BP) + 1), it =
+        // PL (wave - 4) + lane for the first PL lanes of each producer wave;
+        // the other lanes repeat items of their wave (same values to the
+        // same LDS words), so every lane runs the same code
+        const int it = PL * (wave - 4) + (lane < PL ? lane : lane - PL * (lane / PL));
+        const int fl = it / BP, b0 = 2 * (it % BP);
         // Ring slot d holds the units ub + d (mod XD).  Loads are
         // unconditional: a pair whose second bin is past the last one reads
         // the pair one bin earlier, and a pair outside the data reads frame 0,
@@ -204,67 +211,86 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
         }
     } else {
         // ---------------------------------------------------------- consumer
-        VT a[KPW][NRB];
-        auto loadA = [&](int64_t u, int kk) {
+        // ring of AD units of A fragments: slot sl holds the units ub + sl
+        // (mod AD); the fragments of unit u+AD are loaded into the registers
+        // of unit u right after the MFMAs of u that read them
+        VT a[AD][KPW][NRB];
+        auto loadA = [&](int sl, int64_t u, int kk) {
             const int c = (int)(u % nch);
             const T* base = A + (((int64_t)c * KSC + wave + 4 * kk) * NRB * 64 + lane) * EPL;
 #pragma unroll
-            for (int r = 0; r < NRB; ++r) a[kk][r] = *reinterpret_cast<const VT*>(base + r * 64 * EPL);
+            for (int r = 0; r < NRB; ++r) a[sl][kk][r] = *reinterpret_cast<const VT*>(base + r * 64 * EPL);
         };
 #pragma unroll
-        for (int kk = 0; kk < KPW; ++kk) loadA(ub, kk);
+        for (int sl = 0; sl < AD; ++sl)
 #pragma unroll
-        for (int kk = 0; kk < KPW; ++kk)
+            for (int kk = 0; kk < KPW; ++kk) loadA(sl, min(ub + sl, ue - 1), kk);
 #pragma unroll
-            for (int r = 0; r < NRB; ++r) asm volatile("" : "+v"(a[kk][r]));
-        for (int64_t u = ub; u < ue; ++u) {
-            __syncthreads();  // tile of unit u complete
-            const T* xs = xsb + ((u - ub) & 1) * NF * LDX;
-            const int64_t un = min(u + 1, ue - 1);
+        for (int sl = 0; sl < AD; ++sl)
 #pragma unroll
-            for (int kk = 0; kk < KPW; ++kk) {
-                const T* bp = xs + (lane & 15) * LDX + (wave + 4 * kk) * KS + EPL * (lane >> 4);
-                VT b[FB];
+            for (int kk = 0; kk < KPW; ++kk)
 #pragma unroll
-                for (int j = 0; j < FB; ++j) b[j] = *reinterpret_cast<const VT*>(bp + j * 16 * LDX);
+                for (int r = 0; r < NRB; ++r) asm volatile("" : "+v"(a[sl][kk][r]));
+        for (int64_t u0 = ub; u0 < ue; u0 += AD) {
 #pragma unroll
-                for (int r = 0; r < NRB; ++r)
+            for (int sl = 0; sl < AD; ++sl) {
+                const int64_t u = u0 + sl;
+                const int64_t un = min(u + AD, ue - 1);
+                if (u < ue) {
+                    __syncthreads();  // tile of unit u complete
+                    const T* xs = xsb + (sl & 1) * NF * LDX;
 #pragma unroll
-                    for (int j = 0; j < FB; ++j) acc[r][j] = mfma(a[kk][r], b[j], acc[r][j]);
-                loadA(un, kk);
-            }
-            const int64_t t = u / nch;
-            if (u - t * nch == nch - 1 || u == ue - 1) {
-                // end of this workgroup's part of frame tile t: partial sum to
-                // slot 4 (w - w0) + wave.  D layout: lane holds rows
-                // 4 (lane / 16) + e of column lane % 16.
-                const int slot = 4 * (w - g1s_owner(t * nch, G, U)) + wave;
+                    for (int kk = 0; kk < KPW; ++kk) {
+                        const T* bp = xs + (lane & 15) * LDX + (wave + 4 * kk) * KS + EPL * (lane >> 4);
+                        VT b[FB];
 #pragma unroll
-                for (int j = 0; j < FB; ++j) {
-                    const int64_t fpos = t * NF + j * 16 + (lane & 15);
-                    float* zp = zpart + (int64_t)slot * zstride + fpos * Rp;
-                    if (fpos < nfr)
+                        for (int j = 0; j < FB; ++j) b[j] = *reinterpret_cast<const VT*>(bp + j * 16 * LDX);
 #pragma unroll
                         for (int r = 0; r < NRB; ++r)
-                            *reinterpret_cast<f4*>(zp + r * 16 + 4 * (lane >> 4)) = acc[r][j];
 #pragma unroll
-                    for (int r = 0; r < NRB; ++r) acc[r][j] = f4{0.f, 0.f, 0.f, 0.f};
+                            for (int j = 0; j < FB; ++j) acc[r][j] = mfma(a[sl][kk][r], b[j], acc[r][j]);
+                        loadA(sl, un, kk);
+                    }
+                    const int64_t t = u / nch;
+                    if (u - t * nch == nch - 1 || u == ue - 1) {
+                        // end of this workgroup's part of frame tile t: partial sum
+                        // to slot 4 (w - w0) + wave.  D layout: lane holds rows
+                        // 4 (lane / 16) + e of column lane % 16.
+                        const int slot = 4 * (w - g1s_owner(t * nch, G, U)) + wave;
+#pragma unroll
+                        for (int j = 0; j < FB; ++j) {
+                            const int64_t fpos = t * NF + j * 16 + (lane & 15);
+                            float* zp = zpart + (int64_t)slot * zstride + fpos * Rp;
+                            if (fpos < nfr)
+#pragma unroll
+                                for (int r = 0; r < NRB; ++r)
+                                    *reinterpret_cast<f4*>(zp + r * 16 + 4 * (lane >> 4)) = acc[r][j];
+#pragma unroll
+                            for (int r = 0; r < NRB; ++r) acc[r][j] = f4{0.f, 0.f, 0.f, 0.f};
+                        }
+                        // once per tile: let every memory operation finish, so
+                        // that this path rejoins the loop with nothing pending
+                        // and the loop's wait counts need not allow for the
+                        // stores (vector stores count in vmcnt)
+                        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+                    }
+                } else {
+#pragma unroll
+                    for (int kk = 0; kk < KPW; ++kk) loadA(sl, un, kk);
                 }
             }
         }
     }
 }
-// whether the streamed form covers (microphones, row blocks): the consumer
-// keeps NRB x KSC/4 A fragments in registers
-constexpr bool g1s_ok(int M, int nRB) {
-    return M >= 6 && M <= 8 && (nRB == 2 || nRB == 4 || nRB == 6 || nRB == 8) && nRB * g1s_ksc(M) / 4 <= 18;
-}
+
+// whether the streamed form covers (microphones, row blocks)
+constexpr bool g1s_ok(int M, int nRB) { return M >= 6 && M <= 8 && (nRB == 2 || nRB == 4 || nRB == 6); }
 
 // LDS of the streamed kernel: two PHAT tiles, and at least 81 KiB so that
 // one workgroup runs per CU
 template <typename T, int MM>
 constexpr size_t g1s_lds() {
-    constexpr size_t tiles = 2 * G1S_NF * (g1s_ksc(MM) * Mf<T>::KSTEP + G1S_PAD) * sizeof(T);
+    constexpr size_t tiles = 2 * G1S_NF * (G1S_KSC * Mf<T>::KSTEP + G1S_PAD) * sizeof(T);
     return tiles > 81 * 1024 ? tiles : 81 * 1024;
 }
 
@@ -282,7 +308,6 @@ void launch_mm(int nRB, int G, hipStream_t s, const float2* X, int64_t F, int B,
         G1S_CASE(2)
         G1S_CASE(4)
         G1S_CASE(6)
-        G1S_CASE(8)
 #undef G1S_CASE
     }
 }
@@ -302,8 +327,8 @@ int cu_count(int device) {
 
 bool g1s_layout(int M, int nRB, int kstep, int* CW, int* BB) {
     if (kstep != 32 || !g1s_ok(M, nRB)) return false;
-    *CW = g1s_ksc(M) * kstep;
-    *BB = G1S_BB;
+    *CW = G1S_KSC * kstep;
+    *BB = g1s_bb(M);
     return true;
 }
 

@@ -315,6 +315,76 @@ __device__ __forceinline__ void zprep_body(int bx, const float* __restrict__ zpa
     }
 }
 
+// The same for 16-bit operands and Rp <= 128, sixteen lanes per frame: lane
+// j < Rp / 8 of a frame's group sums rows 8j .. 8j+7 over the partials
+// (16-byte loads, all in flight together), the group reduces max |z| and
+// ||z||^2 within its 16 lanes, and each lane writes its 8 rows of the GEMM2
+// operand as one 16-byte piece of the fragment.
+template <typename T>
+__global__ __launch_bounds__(256) void k_zprep16(const float* __restrict__ zpart, int nsplit0, int64_t zstride,
+                                                 int64_t nfr, int Rp, float* __restrict__ z32, T* __restrict__ zfrag,
+                                                 float* __restrict__ zscale, float* __restrict__ znorm, int scale16,
+                                                 int sG, int64_t sU, int snch) {
+    constexpr int KS = Mf<T>::KSTEP, EPL = Mf<T>::EPL;
+    static_assert(EPL == 8, "16-bit fragment layout");
+    typedef typename Vec<T>::t VT;
+    const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
+    const int64_t f = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 6) * 4 + g;
+    const bool fl = f < nfr;
+    const int64_t fc = fl ? f : 0;
+    const bool act = fl && j < Rp / 8;
+    const int ns = zpart_count(fc, nsplit0, sG, sU, snch);
+    float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const float* src = zpart + fc * Rp + 8 * (act ? j : 0);
+    for (int s0 = 0; s0 < ns; s0 += 4) {
+        float4 a[4][2];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const float* p = src + (int64_t)min(s0 + s, ns - 1) * zstride;
+            a[s][0] = *reinterpret_cast<const float4*>(p);
+            a[s][1] = *reinterpret_cast<const float4*>(p + 4);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            if (s0 + s < ns) {
+                v[0] += a[s][0].x; v[1] += a[s][0].y; v[2] += a[s][0].z; v[3] += a[s][0].w;
+                v[4] += a[s][1].x; v[5] += a[s][1].y; v[6] += a[s][1].z; v[7] += a[s][1].w;
+            }
+    }
+    float mx = 0.f, ss = 0.f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        if (!act) v[e] = 0.f;
+        mx = fmaxf(mx, fabsf(v[e]));
+        ss = fmaf(v[e], v[e], ss);
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+        mx = fmaxf(mx, __shfl_xor(mx, o));
+        ss += __shfl_xor(ss, o);
+    }
+    float sc = 1.f;
+    if (scale16 && mx > 0.f) {
+        int e;
+        frexpf(mx, &e);
+        sc = ldexpf(1.f, 14 - e);
+    }
+    if (!act) return;
+    *reinterpret_cast<float4*>(z32 + f * Rp + 8 * j) = float4{v[0], v[1], v[2], v[3]};
+    *reinterpret_cast<float4*>(z32 + f * Rp + 8 * j + 4) = float4{v[4], v[5], v[6], v[7]};
+    if (j == 0) {
+        zscale[f] = sc;
+        znorm[f] = sqrtf(ss);
+    }
+    // rows 8j .. 8j+7: k-step 8j / KS, lane (f & 15) + 16 ((8j % KS) / 8) of the fragment
+    const int KSn = Rp / KS;
+    const int64_t fb = f >> 4;
+    VT h;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) h[e] = cvt<T>(v[e] * sc);
+    *reinterpret_cast<VT*>(zfrag + ((fb * KSn + (8 * j) / KS) * 64 + (f & 15) + 16 * ((8 * j % KS) / 8)) * EPL) = h;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_zprep_list(const float* __restrict__ zpart, int nsplit, int64_t zstride,
                                                     const int* __restrict__ fcount, int Rp, float* __restrict__ z32,
@@ -355,7 +425,7 @@ __device__ __forceinline__ float max_rowgroups(float m) {
     return fmaxf(__uint_as_float(b[0]), __uint_as_float(b[1]));
 }
 
-template <typename T, int KSN>
+template <typename T, int KSN, bool YOUT = false>
 __device__ __forceinline__ void gemm2_body(int bx, int by, const T* __restrict__ U, int KSn,
                                            const T* __restrict__ zfrag, int64_t nfr, int fch, int ncls, int ntile,
                                            const float* __restrict__ zscale, float uinv, float* __restrict__ pmax,
@@ -402,6 +472,10 @@ __device__ __forceinline__ void gemm2_body(int bx, int by, const T* __restrict__
         for (int sl = 0; sl < 2; ++sl)
 #pragma unroll
             for (int ks = 0; ks < KSN; ++ks) asm volatile("" : "+v"(bz[sl][ks]));
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int ks = 0; ks < KSN; ++ks) asm volatile("" : "+v"(a[i][ks]));
     }
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) asm volatile("" : "+v"(sc[sl]));
@@ -449,7 +523,7 @@ __device__ __forceinline__ void gemm2_body(int bx, int by, const T* __restrict__
                 }
                 m = max_rowgroups(m);
                 if (lane < 16 && f < fend) pmax[(fmap ? (int64_t)fmap[f] : f) * pstride + tile] = m * inv;
-                if (ycls && f < fend) {
+                if (YOUT && f < fend) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -464,14 +538,14 @@ __device__ __forceinline__ void gemm2_body(int bx, int by, const T* __restrict__
     }
 }
 
-template <typename T, int KSN>
+template <typename T, int KSN, bool YOUT = false>
 __global__ __launch_bounds__(256) void k_gemm2(const T* __restrict__ U, int KSn, const T* __restrict__ zfrag,
                                                int64_t nfr, int fch, int ncls, int ntile,
                                                const float* __restrict__ zscale, float uinv,
                                                float* __restrict__ pmax, int64_t pstride, float* __restrict__ ycls,
                                                int64_t yld) {
-    gemm2_body<T, KSN>(blockIdx.x, blockIdx.y, U, KSn, zfrag, nfr, fch, ncls, ntile, zscale, uinv, pmax, pstride,
-                       ycls, yld);
+    gemm2_body<T, KSN, YOUT>(blockIdx.x, blockIdx.y, U, KSn, zfrag, nfr, fch, ncls, ntile, zscale, uinv, pmax,
+                             pstride, ycls, yld);
 }
 
 // GEMM2 over a list of frames: position f of zfrag holds frame fmap[f];
@@ -900,8 +974,14 @@ void launch_g2(svdphat_plan* p, int prec, const T* zfrag, int64_t F, const float
     dim3 grid(cdiv(ntile, 4), (unsigned)((F + fch - 1) / fch));
     const float uinv = 1.f / p->uscale[prec];
     const T* U = (const T*)p->Ufr[prec];
+    if (ycls) {
+        // every reduced power as well (debugging output): general form
+        k_gemm2<T, 0, true><<<grid, 256, 0, s>>>(U, KSn, zfrag, F, fch, p->ncls, ntile, zsc, uinv, pmax, pstride, ycls,
+                                                 p->ncls_pad);
+        return;
+    }
 #define SP_G2(N) k_gemm2<T, N><<<grid, 256, 0, s>>>(U, KSn, zfrag, F, fch, p->ncls, ntile, zsc, uinv, pmax, pstride, \
-                                                    ycls, p->ncls_pad)
+                                                    nullptr, p->ncls_pad)
     // U fragments of the tile stay in registers when they fit (<= 96 VGPRs)
     if constexpr (sizeof(T) == 2) {
         switch (KSn) {
@@ -1035,8 +1115,19 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     SP_HIP(hipGetLastError());
     kt.end();
     kt.begin("zprep");
-    k_zprep<T><<<dim3((unsigned)(Fc / 4)), 256, 0, s>>>(zpart, zslots, zstride, F, nullptr, Rp, z32, zfrag, zsc, zn,
-                                                        prec == P_FP16 ? 1 : 0, streamed ? sc.G : 0, sc.U, sc.nch);
+    if constexpr (sizeof(T) == 2) {
+        if (Rp <= 128)
+            k_zprep16<T><<<dim3((unsigned)((F + 15) / 16)), 256, 0, s>>>(zpart, zslots, zstride, F, Rp, z32, zfrag, zsc,
+                                                                    zn, prec == P_FP16 ? 1 : 0,
+                                                                    streamed ? sc.G : 0, sc.U, sc.nch);
+        else
+            k_zprep<T><<<dim3((unsigned)(Fc / 4)), 256, 0, s>>>(zpart, zslots, zstride, F, nullptr, Rp, z32, zfrag,
+                                                                zsc, zn, prec == P_FP16 ? 1 : 0,
+                                                                streamed ? sc.G : 0, sc.U, sc.nch);
+    } else {
+        k_zprep<T><<<dim3((unsigned)(Fc / 4)), 256, 0, s>>>(zpart, zslots, zstride, F, nullptr, Rp, z32, zfrag, zsc,
+                                                            zn, 0, streamed ? sc.G : 0, sc.U, sc.nch);
+    }
     SP_HIP(hipGetLastError());
     kt.end();
     kt.begin("gemm2");
