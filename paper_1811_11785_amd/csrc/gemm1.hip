@@ -9,16 +9,17 @@
 // waves in two roles, one of each on every SIMD:
 //   producers (waves 4-7) load the STFT values of the units ahead into a
 //     register ring of XD units (each thread one frame and a pair of bins,
-//     one 16-byte load per microphone) and form each unit's PHAT tile
-//     (per-mic unit normalisation, then X_i conj(X_j) for pairs i < j in
-//     order, rounded to T, stored as (Re, Im)) in one of two LDS buffers;
-//   consumers (waves 0-3) take two of the unit's 8 k-steps (a chunk is the
-//     largest even number of bins whose stacked values fit 8 k-steps of 32),
-//     keep a ring of two units of A fragments in flight and run the MFMAs,
-//     each accumulating every (row block, frame block) of the tile's Z; at
-//     the end of a frame tile (or of the range)
-//     each consumer writes its partial sum to its own slot: slot
-//     4 (w - w0) + wave, w0 the first workgroup whose range meets the tile.
+//     one 16-byte load per microphone; 64 frames x 4 pairs fill the 256
+//     threads) and form each unit's PHAT tile (per-mic unit normalisation,
+//     then X_i conj(X_j) for pairs i < j in order, rounded to T, stored as
+//     (Re, Im)) in one of two LDS buffers;
+//   consumers (waves 0-3) take the k-steps wave, wave + 4, ... of the
+//     unit's KSC = ceil(8 MM (MM - 1) / 32) k-steps, keep a ring of A
+//     fragments in flight and run the MFMAs, each accumulating every (row
+//     block, frame block) of the tile's Z; at the end of a frame tile (or
+//     of the range) each consumer writes its partial sum to its own slot:
+//     slot 4 (w - w0) + wave, w0 the first workgroup whose range meets the
+//     tile.
 // One barrier per unit hands a PHAT tile from the producers to the
 // consumers.  The Z preparation sums the 4 (w1 - w0 + 1) slots of a frame.
 //
@@ -38,6 +39,11 @@
 // microphone) row of the STFT, so every row keeps one partly used cache
 // line in L2 until its next unit; with one workgroup per CU (the LDS request
 // guarantees it) the lines in flight on an XCD stay well inside its L2.
+// The chunks of a frame tile are visited in a rotated order, so that the
+// first workgroup starting inside the tile starts at chunk 0: the
+// workgroups of an XCD then walk the chunks of A (the same for every frame
+// tile) nearly in step and share them in L2 instead of each fetching all
+// of A from memory.
 #include "device.h"
 
 namespace svdphat {
@@ -45,14 +51,13 @@ namespace svdphat {
 namespace {
 
 constexpr int G1S_NF = 64;
-constexpr int G1S_KSC = 8;  // k-steps per chunk (two per consumer wave)
+constexpr int G1S_BB = 8;   // bins per chunk
 constexpr int G1S_PAD = 8;  // LDS row padding (elements)
 constexpr int G1S_XD = 4;   // units of STFT values in flight (even)
-constexpr int G1S_AD = 2;   // units of A fragments in flight
 
-// bins per chunk for MM microphones: the largest even count whose stacked
-// values (MM (MM - 1) per bin) fit the chunk's 8 k-steps of 32
-constexpr int g1s_bb(int MM) { return (G1S_KSC * 32 / (MM * (MM - 1))) & ~1; }
+// k-steps of 32 per chunk for MM microphones (MM (MM - 1) stacked values
+// per bin)
+constexpr int g1s_ksc(int MM) { return (G1S_BB * MM * (MM - 1) + 31) / 32; }
 
 // four floats read with one 16-byte load from an 8-byte aligned address
 struct __attribute__((aligned(8))) f4u {
@@ -72,19 +77,31 @@ __device__ __forceinline__ h2 unit_h2(float re, float im) {
 // workgroup whose unit range holds unit u (ranges [w U / G, (w+1) U / G))
 __host__ __device__ inline int g1s_owner(int64_t u, int G, int64_t U) { return (int)(((u + 1) * G - 1) / U); }
 
+// rotation of frame tile t's chunk order: position j of the tile holds chunk
+// (j + phi) mod nch, phi chosen so that the first workgroup whose range
+// starts inside the tile starts at chunk 0 (0 when none does)
+__device__ inline int g1s_phi(int64_t t, int nch, int G, int64_t U) {
+    const int64_t t0 = t * nch;
+    const int wf = g1s_owner(t0, G, U);
+    if ((int64_t)wf * U / G == t0 || wf + 1 >= G) return 0;
+    const int64_t s2 = (int64_t)(wf + 1) * U / G;
+    return s2 < t0 + nch ? (int)(nch - (s2 - t0)) : 0;
+}
+
 template <typename T, int MM, int NRB, int XD>
 __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, int64_t nfr, int B,
                                                 const T* __restrict__ A, int nch, int64_t U,
                                                 float* __restrict__ zpart, int64_t zstride, int Rp) {
     constexpr int KS = Mf<T>::KSTEP, EPL = Mf<T>::EPL, NF = G1S_NF, FB = NF / 16;
     constexpr int P = MM * (MM - 1) / 2, TWOP = 2 * P;
-    constexpr int BB = g1s_bb(MM), BP = BB / 2;
-    constexpr int KSC = G1S_KSC, KPW = KSC / 4, AD = G1S_AD;
-    constexpr int CW = KSC * KS;      // stacked values per chunk (BB * TWOP used)
+    constexpr int BB = G1S_BB, BP = BB / 2;
+    constexpr int KSC = g1s_ksc(MM), KPW = (KSC + 3) / 4;
+    constexpr int AD = KPW <= 2 ? 2 : 1;  // units of A fragments in flight
+    constexpr int CW = KSC * KS;          // stacked values per chunk (BB * TWOP used)
     constexpr int LDX = CW + G1S_PAD;
     constexpr int PADC = CW - BB * TWOP;
-    constexpr int PL = NF * BP / 4;   // (frame, bin pair) items per producer wave
-    static_assert(BB >= 2 && PL <= 64 && (NF * BP) % 4 == 0 && XD % 2 == 0, "chunk layout");
+    constexpr int PL = NF * BP / 4;       // (frame, bin pair) items per producer wave
+    static_assert(KS == 32 && PL == 64 && XD % 2 == 0, "chunk layout");
     typedef typename Vec<T>::t VT;
     typedef typename Vec<T>::pair VP;
     extern __shared__ __align__(16) char smem[];
@@ -94,6 +111,14 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
     const int64_t ub = (int64_t)w * U / G, ue = (int64_t)(w + 1) * U / G;  // this workgroup's units
     if (ub >= ue) return;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    // chunk of unit u in frame tile t; only the first and the last tile of
+    // the range can have a rotation (no other workgroup starts in between)
+    const int64_t tf = ub / nch, tl = (ue - 1) / nch;
+    const int phf = g1s_phi(tf, nch, G, U), phl = g1s_phi(tl, nch, G, U);
+    auto chunk = [&](int64_t t, int64_t u) {
+        const int c = (int)(u - t * nch) + (t == tf ? phf : t == tl ? phl : 0);
+        return c >= nch ? c - nch : c;
+    };
 
     // padding columns of both tiles are zero (the PHAT phase never writes them)
     if (PADC > 0)
@@ -108,10 +133,8 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
     if (wave >= 4) {
         // ---------------------------------------------------------- producer
         // item (frame it / BP, bins 2 (it % BP) and 2 (it % BP) + 1), it =
-        // PL (wave - 4) + lane for the first PL lanes of each producer wave;
-        // the other lanes repeat items of their wave (same values to the
-        // same LDS words), so every lane runs the same code
-        const int it = PL * (wave - 4) + (lane < PL ? lane : lane - PL * (lane / PL));
+        // 64 (wave - 4) + lane
+        const int it = PL * (wave - 4) + lane;
         const int fl = it / BP, b0 = 2 * (it % BP);
         // Ring slot d holds the units ub + d (mod XD).  Loads are
         // unconditional: a pair whose second bin is past the last one reads
@@ -121,7 +144,7 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
         int xmode[XD];  // 2: both bins, 1: first bin only (shifted load), 0: none
         auto fetch = [&](int d, int64_t u) {
             const int64_t t = u / nch;
-            const int c = (int)(u - t * nch);
+            const int c = chunk(t, u);
             const int64_t f = t * NF + fl;
             const int s0 = c * BB + b0;
             const int mode = f >= nfr ? 0 : s0 + 1 < B ? 2 : s0 < B ? 1 : 0;
@@ -187,7 +210,7 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
         };
         auto phat = [&](int d, int64_t u, T* xs) {
             const int64_t t = u / nch;
-            const int c = (int)(u - t * nch);
+            const int c = chunk(t, u);
             if ((t + 1) * NF <= nfr && (c + 1) * BB <= B) phat_impl(std::true_type{}, d, xs);
             else phat_impl(std::false_type{}, d, xs);
         };
@@ -213,10 +236,13 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
         // ---------------------------------------------------------- consumer
         // ring of AD units of A fragments: slot sl holds the units ub + sl
         // (mod AD); the fragments of unit u+AD are loaded into the registers
-        // of unit u right after the MFMAs of u that read them
+        // of unit u right after the MFMAs of u that read them.  This wave
+        // takes k-steps wave + 4 kk, kk < nkk (the same for the whole wave).
+        const int nkk = (KSC - __builtin_amdgcn_readfirstlane(wave) + 3) / 4;
+        auto has = [&](int kk) { return KSC % 4 == 0 || kk < nkk; };
         VT a[AD][KPW][NRB];
         auto loadA = [&](int sl, int64_t u, int kk) {
-            const int c = (int)(u % nch);
+            const int c = chunk(u / nch, u);
             const T* base = A + (((int64_t)c * KSC + wave + 4 * kk) * NRB * 64 + lane) * EPL;
 #pragma unroll
             for (int r = 0; r < NRB; ++r) a[sl][kk][r] = *reinterpret_cast<const VT*>(base + r * 64 * EPL);
@@ -224,7 +250,8 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
 #pragma unroll
         for (int sl = 0; sl < AD; ++sl)
 #pragma unroll
-            for (int kk = 0; kk < KPW; ++kk) loadA(sl, min(ub + sl, ue - 1), kk);
+            for (int kk = 0; kk < KPW; ++kk)
+                if (has(kk)) loadA(sl, min(ub + sl, ue - 1), kk);
 #pragma unroll
         for (int sl = 0; sl < AD; ++sl)
 #pragma unroll
@@ -238,9 +265,10 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
                 const int64_t un = min(u + AD, ue - 1);
                 if (u < ue) {
                     __syncthreads();  // tile of unit u complete
-                    const T* xs = xsb + (sl & 1) * NF * LDX;
+                    const T* xs = xsb + ((u - ub) & 1) * NF * LDX;  // the producers' buffer of unit u
 #pragma unroll
                     for (int kk = 0; kk < KPW; ++kk) {
+                        if (!has(kk)) continue;
                         const T* bp = xs + (lane & 15) * LDX + (wave + 4 * kk) * KS + EPL * (lane >> 4);
                         VT b[FB];
 #pragma unroll
@@ -276,7 +304,8 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
                     }
                 } else {
 #pragma unroll
-                    for (int kk = 0; kk < KPW; ++kk) loadA(sl, un, kk);
+                    for (int kk = 0; kk < KPW; ++kk)
+                        if (has(kk)) loadA(sl, un, kk);
                 }
             }
         }
@@ -290,7 +319,7 @@ constexpr bool g1s_ok(int M, int nRB) { return M >= 6 && M <= 8 && (nRB == 2 || 
 // one workgroup runs per CU
 template <typename T, int MM>
 constexpr size_t g1s_lds() {
-    constexpr size_t tiles = 2 * G1S_NF * (G1S_KSC * Mf<T>::KSTEP + G1S_PAD) * sizeof(T);
+    constexpr size_t tiles = 2 * G1S_NF * (g1s_ksc(MM) * Mf<T>::KSTEP + G1S_PAD) * sizeof(T);
     return tiles > 81 * 1024 ? tiles : 81 * 1024;
 }
 
@@ -327,8 +356,8 @@ int cu_count(int device) {
 
 bool g1s_layout(int M, int nRB, int kstep, int* CW, int* BB) {
     if (kstep != 32 || !g1s_ok(M, nRB)) return false;
-    *CW = G1S_KSC * kstep;
-    *BB = g1s_bb(M);
+    *CW = g1s_ksc(M) * kstep;
+    *BB = G1S_BB;
     return true;
 }
 
