@@ -341,6 +341,8 @@ void launch_mm(int nRB, int G, hipStream_t s, const float2* X, int64_t F, int B,
     }
 }
 
+}  // namespace
+
 int cu_count(int device) {
     static int cached[64] = {0};
     if (device < 0 || device >= 64) return 256;
@@ -351,8 +353,6 @@ int cu_count(int device) {
     }
     return cached[device];
 }
-
-}  // namespace
 
 bool g1s_layout(int M, int nRB, int kstep, int* CW, int* BB) {
     if (kstep != 32 || !g1s_ok(M, nRB)) return false;

@@ -85,6 +85,9 @@ struct FinalArgs {
     int64_t pstride;
     int ntile, ncls;
     const float* z32;       // [pos][Rp] z used for rescoring
+    const float* zpart;     // or, when set: z = sum of zp_n partials zpart[s * zp_stride + pos * Rp]
+    int zp_n;
+    int64_t zp_stride;
     const float* z32_first; // [F][Rp] z of the first pass (second pass only)
     const float* znorm1;    // [F] ||z|| of the first pass
     int Rp;
@@ -158,6 +161,7 @@ void g1_split(const svdphat_plan* p, int64_t F, int want, int* nsplit, int* cps)
 // workgroups over U = frame tiles x chunks units, `slots` partial sums per
 // frame; and its launcher
 bool g1s_layout(int M, int nRB, int kstep, int* CW, int* BB);
+int cu_count(int device);  // compute units of a device (cached)
 struct G1Sched {
     int G = 0;
     int64_t U = 0;

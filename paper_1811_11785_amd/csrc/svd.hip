@@ -14,9 +14,12 @@
 //             streams frames; its epilogue keeps one maximum per (frame, tile).
 //   k_final   per frame: every tile whose maximum is within the rounding bound
 //             of the frame maximum is rescored in FP32; best class, runner-up
-//             and margin; the power of the chosen direction from its row of W
-//             (Algorithm 1, online step 4); frames whose margin is within the
-//             modelled GEMM1 rounding are queued for a hi/lo recomputation.
+//             and margin; frames whose margin is within the modelled GEMM1
+//             rounding are queued for a hi/lo recomputation, which
+//             k_gemm1_list and k_final_list (summing the list's partial Z
+//             itself) redo over the device-counted list.
+//   k_power   the power of the chosen direction from its row of W (Algorithm
+//             1, online step 4), once the directions are final.
 #include "device.h"
 
 #include <type_traits>
@@ -386,15 +389,6 @@ __global__ __launch_bounds__(256) void k_zprep16(const float* __restrict__ zpart
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_zprep_list(const float* __restrict__ zpart, int nsplit, int64_t zstride,
-                                                    const int* __restrict__ fcount, int Rp, float* __restrict__ z32,
-                                                    float* __restrict__ znorm) {
-    const int64_t n = *fcount;
-    for (int64_t bx = blockIdx.x; bx * 4 < n; bx += gridDim.x)
-        zprep_body<T>((int)bx, zpart, nsplit, zstride, n, nullptr, Rp, z32, nullptr, nullptr, znorm, 0);
-}
-
-template <typename T>
 __global__ __launch_bounds__(256) void k_zprep(const float* __restrict__ zpart, int nsplit, int64_t zstride,
                                                int64_t nfr, const int* __restrict__ fcount, int Rp,
                                                float* __restrict__ z32, T* __restrict__ zfrag,
@@ -621,7 +615,20 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
     float* zw = zs[wave];
     float dz2 = 0.f;
     for (int r = lane; r < Rp; r += 64) {
-        const float v = z[r];
+        float v = 0.f;
+        if (a.zpart) {
+            // the GEMM1 partial sums of this list position, eight in flight
+            for (int s0 = 0; s0 < a.zp_n; s0 += 8) {
+                float part[8];
+#pragma unroll
+                for (int s = 0; s < 8; ++s)
+                    part[s] = s0 + s < a.zp_n ? a.zpart[(int64_t)(s0 + s) * a.zp_stride + pos * Rp + r] : 0.f;
+#pragma unroll
+                for (int s = 0; s < 8; ++s) v += part[s];
+            }
+        } else {
+            v = z[r];
+        }
         zw[r] = v;
         if (a.z32_first) {
             const float d = v - a.z32_first[f * Rp + r];
@@ -1021,7 +1028,9 @@ void launch_g1_list(hipStream_t s, const float2* X, svdphat_plan* p, int prec, c
                     float* zpart, int64_t zstride, const int* fl, const int* fc) {
     const int nRB = p->Rp / 16;
     const int NRB = nRB <= 2 ? 2 : nRB <= 4 ? 4 : nRB <= 6 ? 6 : nRB <= 8 ? 8 : nRB <= 10 ? 10 : 12;
-    dim3 grid(2048, 1, cdiv(nRB, NRB));
+    // grid-stride over (frame tile, split) items of the short device-counted
+    // list: one workgroup per CU
+    dim3 grid(cu_count(p->device), 1, cdiv(nRB, NRB));
     const size_t xbytes = (size_t)2 * 32 * (g.CW + XPAD) * sizeof(T);
     const size_t lds = std::max(xbytes, (size_t)NRB * 2 * 64 * sizeof(f4));
     const T* A = (const T*)p->A[prec];
@@ -1044,7 +1053,8 @@ void launch_g1_list(hipStream_t s, const float2* X, svdphat_plan* p, int prec, c
 }
 
 void launch_final_list(const FinalArgs& fa, int M, bool dedup, hipStream_t s) {
-    dim3 grid(512);
+    // grid-stride over the device-counted list, which is short
+    dim3 grid(64);
     if (M <= 8) {
         if (dedup) k_final_list<8, true><<<grid, 256, 0, s>>>(fa);
         else k_final_list<8, false><<<grid, 256, 0, s>>>(fa);
@@ -1080,11 +1090,9 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     const int maxsplit = std::max(zslots, hilo ? hsplit : 1);
     const size_t o_zpart = take(sizeof(float) * maxsplit * Fc * Rp);
     const size_t o_z32 = take(sizeof(float) * Fc * Rp);
-    const size_t o_z32h = hilo ? take(sizeof(float) * Fc * Rp) : 0;
     const size_t o_zfrag = take(sizeof(T) * Fc * Rp);
     const size_t o_zsc = take(sizeof(float) * Fc);
     const size_t o_zn = take(sizeof(float) * Fc);
-    const size_t o_znh = hilo ? take(sizeof(float) * Fc) : 0;
     const int ntp = pmax_stride(p);
     const size_t o_pmax = take(sizeof(float) * ntp * Fc);
     const size_t o_hl = hilo ? take(sizeof(int) * Fc) : 0;
@@ -1187,18 +1195,15 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     SP_HIP(hipGetLastError());
     kt.end();
     if (hilo) {
-        float* z32h = (float*)(w + o_z32h);
-        float* znh = (float*)(w + o_znh);
         kt.begin("gemm1_hilo");
         launch_g1_list<T>(s, X, p, prec, g, hsplit, hcps, zpart, zstride, hl, hc);
         SP_HIP(hipGetLastError());
         kt.end();
-        kt.begin("zprep_hilo");
-        k_zprep_list<T><<<dim3(512), 256, 0, s>>>(zpart, hsplit, zstride, hc, Rp, z32h, znh);
-        SP_HIP(hipGetLastError());
-        kt.end();
         FinalArgs fb = fa;
-        fb.z32 = z32h;
+        fb.z32 = nullptr;
+        fb.zpart = zpart;  // z of the list positions summed in the rescoring kernel
+        fb.zp_n = hsplit;
+        fb.zp_stride = zstride;
         fb.z32_first = z32;
         fb.flist = hl;
         fb.fcount = hc;
