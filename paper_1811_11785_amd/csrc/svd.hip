@@ -593,6 +593,15 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
     // tile's bound (carried through the reduction), z into LDS
     float ym = -INFINITY, km = 0.f;
     int tm = 0x7fffffff;
+    // z of up to 128 rows is loaded with the tile maxima, so both arrive
+    // in one round trip
+    const float* z = a.z32 + pos * Rp;
+    const bool zfast = !a.zpart && Rp <= 128;
+    float zpre[2] = {0.f, 0.f};
+    if (zfast) {
+        zpre[0] = z[min(lane, Rp - 1)];
+        zpre[1] = z[min(lane + 64, Rp - 1)];
+    }
     for (int t0 = 0; t0 < T; t0 += 256) {
         float pv[4], kv[4];
 #pragma unroll
@@ -611,12 +620,13 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
             }
         }
     }
-    const float* z = a.z32 + pos * Rp;
     float* zw = zs[wave];
     float dz2 = 0.f;
     for (int r = lane; r < Rp; r += 64) {
         float v = 0.f;
-        if (a.zpart) {
+        if (zfast) {
+            v = r == lane ? zpre[0] : zpre[1];
+        } else if (a.zpart) {
             // the GEMM1 partial sums of this list position, eight in flight
             for (int s0 = 0; s0 < a.zp_n; s0 += 8) {
                 float part[8];
@@ -785,12 +795,16 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
     // ---- round 3 (when the power is not left to k_power): Algorithm 1
     // online step 4, the power of the chosen direction from its row of W
     // (delay-and-sum form)
+    // (MAXM = 0: no power here, which keeps the register count and so the
+    // number of frames in flight up)
     float acc = 0.f;
-    if (a.power) {
-        float t[MAXM];
+    if constexpr (MAXM > 0) {
+        if (a.power) {
+            float t[MAXM];
 #pragma unroll
-        for (int m = 0; m < MAXM; ++m) t[m] = m < a.M ? a.tauM[(int64_t)cls * a.M + m] : 0.f;
-        acc = power_ds<MAXM>(a.X + f * a.M * a.B, a.M, a.B, t, lane);
+            for (int m = 0; m < MAXM; ++m) t[m] = m < a.M ? a.tauM[(int64_t)cls * a.M + m] : 0.f;
+            acc = power_ds<MAXM>(a.X + f * a.M * a.B, a.M, a.B, t, lane);
+        }
     }
     if (lane == 0) {
         a.doa[f] = cls;
@@ -811,6 +825,14 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
 template <int MAXM, bool DEDUP>
 __global__ __launch_bounds__(256) void k_final(FinalArgs a) {
     final_body<MAXM, DEDUP>(blockIdx.x, a);
+}
+
+
+// the same without the power (k_power computes it afterwards): few enough
+// registers for five waves per SIMD, so more frames' dependent loads overlap
+template <bool DEDUP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_final_np(FinalArgs a) {
+    final_body<0, DEDUP>(blockIdx.x, a);
 }
 
 // the same over a device-counted frame list, grid-stride (few frames)
@@ -1012,7 +1034,10 @@ void launch_g2(svdphat_plan* p, int prec, const T* zfrag, int64_t F, const float
 
 void launch_final(const FinalArgs& fa, int M, bool dedup, int64_t nwaves, hipStream_t s) {
     dim3 grid((unsigned)((nwaves + 3) / 4));
-    if (M <= 8) {
+    if (!fa.power) {
+        if (dedup) k_final_np<true><<<grid, 256, 0, s>>>(fa);
+        else k_final_np<false><<<grid, 256, 0, s>>>(fa);
+    } else if (M <= 8) {
         if (dedup) k_final<8, true><<<grid, 256, 0, s>>>(fa);
         else k_final<8, false><<<grid, 256, 0, s>>>(fa);
     } else {
@@ -1055,7 +1080,10 @@ void launch_g1_list(hipStream_t s, const float2* X, svdphat_plan* p, int prec, c
 void launch_final_list(const FinalArgs& fa, int M, bool dedup, hipStream_t s) {
     // grid-stride over the device-counted list, which is short
     dim3 grid(64);
-    if (M <= 8) {
+    if (!fa.power) {
+        if (dedup) k_final_list<0, true><<<grid, 256, 0, s>>>(fa);
+        else k_final_list<0, false><<<grid, 256, 0, s>>>(fa);
+    } else if (M <= 8) {
         if (dedup) k_final_list<8, true><<<grid, 256, 0, s>>>(fa);
         else k_final_list<8, false><<<grid, 256, 0, s>>>(fa);
     } else {
