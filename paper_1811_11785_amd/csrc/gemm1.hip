@@ -115,9 +115,28 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
     // the range can have a rotation (no other workgroup starts in between)
     const int64_t tf = ub / nch, tl = (ue - 1) / nch;
     const int phf = g1s_phi(tf, nch, G, U), phl = g1s_phi(tl, nch, G, U);
-    auto chunk = [&](int64_t t, int64_t u) {
-        const int c = (int)(u - t * nch) + (t == tf ? phf : t == tl ? phl : 0);
-        return c >= nch ? c - nch : c;
+    // unit cursor: unit u = t nch + j, moved one unit at a time and held at
+    // the range's last unit (no division inside the loops)
+    struct Cur {
+        int64_t u, t;
+        int j;
+    };
+    auto cur_at = [&](int64_t u) {
+        const int64_t t = u / nch;
+        return Cur{u, t, (int)(u - t * nch)};
+    };
+    auto adv = [&](Cur& c) {
+        if (c.u + 1 < ue) {
+            ++c.u;
+            if (++c.j == nch) {
+                c.j = 0;
+                ++c.t;
+            }
+        }
+    };
+    auto chunk = [&](const Cur& c) {
+        const int v = c.j + (c.t == tf ? phf : c.t == tl ? phl : 0);
+        return v >= nch ? v - nch : v;
     };
 
     // padding columns of both tiles are zero (the PHAT phase never writes them)
@@ -142,9 +161,9 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
         // bins 0-1; the values are selected (or zeroed) where consumed.
         f4u xv[XD][MM];
         int xmode[XD];  // 2: both bins, 1: first bin only (shifted load), 0: none
-        auto fetch = [&](int d, int64_t u) {
-            const int64_t t = u / nch;
-            const int c = chunk(t, u);
+        auto fetch = [&](int d, const Cur& cu) {
+            const int64_t t = cu.t;
+            const int c = chunk(cu);
             const int64_t f = t * NF + fl;
             const int s0 = c * BB + b0;
             const int mode = f >= nfr ? 0 : s0 + 1 < B ? 2 : s0 < B ? 1 : 0;
@@ -208,28 +227,39 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
                 }
             }
         };
-        auto phat = [&](int d, int64_t u, T* xs) {
-            const int64_t t = u / nch;
-            const int c = chunk(t, u);
+        auto phat = [&](int d, const Cur& cu, T* xs) {
+            const int64_t t = cu.t;
+            const int c = chunk(cu);
             if ((t + 1) * NF <= nfr && (c + 1) * BB <= B) phat_impl(std::true_type{}, d, xs);
             else phat_impl(std::false_type{}, d, xs);
         };
+        // cursors: cf the next unit to fetch, cp the next unit to form
+        Cur cf = cur_at(ub), cp = cur_at(ub);
 #pragma unroll
-        for (int d = 0; d < XD; ++d) fetch(d, min(ub + d, ue - 1));
+        for (int d = 0; d < XD; ++d) {
+            fetch(d, cf);  // units ub + d (at most ue - 1)
+            adv(cf);
+        }
 #pragma unroll
         for (int d = 0; d < XD; ++d)
 #pragma unroll
             for (int m = 0; m < MM; ++m)
                 asm volatile("" : "+v"(xv[d][m].x), "+v"(xv[d][m].y), "+v"(xv[d][m].z), "+v"(xv[d][m].w));
-        phat(0, ub, xsb);
-        fetch(0, min(ub + XD, ue - 1));
+        phat(0, cp, xsb);
+        adv(cp);
+        fetch(0, cf);
+        adv(cf);
         for (int64_t u0 = ub; u0 < ue; u0 += XD) {
 #pragma unroll
             for (int d = 0; d < XD; ++d) {
                 const int64_t u = u0 + d;
                 if (u < ue) __syncthreads();  // tile of unit u complete; tile of u+1 free
-                if (u + 1 < ue) phat((d + 1) % XD, u + 1, xsb + ((d + 1) & 1) * NF * LDX);
-                fetch((d + 1) % XD, min(u + 1 + XD, ue - 1));
+                if (u + 1 < ue) {
+                    phat((d + 1) % XD, cp, xsb + ((d + 1) & 1) * NF * LDX);  // unit u + 1
+                    adv(cp);
+                }
+                fetch((d + 1) % XD, cf);  // unit u + 1 + XD (at most ue - 1)
+                adv(cf);
             }
         }
     } else {
@@ -241,17 +271,22 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
         const int nkk = (KSC - __builtin_amdgcn_readfirstlane(wave) + 3) / 4;
         auto has = [&](int kk) { return KSC % 4 == 0 || kk < nkk; };
         VT a[AD][KPW][NRB];
-        auto loadA = [&](int sl, int64_t u, int kk) {
-            const int c = chunk(u / nch, u);
+        auto loadA = [&](int sl, const Cur& cu, int kk) {
+            const int c = chunk(cu);
             const T* base = A + (((int64_t)c * KSC + wave + 4 * kk) * NRB * 64 + lane) * EPL;
 #pragma unroll
             for (int r = 0; r < NRB; ++r) a[sl][kk][r] = *reinterpret_cast<const VT*>(base + r * 64 * EPL);
         };
+        // cursors: cl the next unit whose fragments are loaded, cc the unit
+        // whose MFMAs run
+        Cur cl = cur_at(ub), cc = cur_at(ub);
 #pragma unroll
-        for (int sl = 0; sl < AD; ++sl)
+        for (int sl = 0; sl < AD; ++sl) {
 #pragma unroll
             for (int kk = 0; kk < KPW; ++kk)
-                if (has(kk)) loadA(sl, min(ub + sl, ue - 1), kk);
+                if (has(kk)) loadA(sl, cl, kk);  // unit ub + sl (at most ue - 1)
+            adv(cl);
+        }
 #pragma unroll
         for (int sl = 0; sl < AD; ++sl)
 #pragma unroll
@@ -262,7 +297,6 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
 #pragma unroll
             for (int sl = 0; sl < AD; ++sl) {
                 const int64_t u = u0 + sl;
-                const int64_t un = min(u + AD, ue - 1);
                 if (u < ue) {
                     __syncthreads();  // tile of unit u complete
                     const T* xs = xsb + ((u - ub) & 1) * NF * LDX;  // the producers' buffer of unit u
@@ -277,10 +311,10 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
                         for (int r = 0; r < NRB; ++r)
 #pragma unroll
                             for (int j = 0; j < FB; ++j) acc[r][j] = mfma(a[sl][kk][r], b[j], acc[r][j]);
-                        loadA(sl, un, kk);
+                        loadA(sl, cl, kk);  // unit u + AD (at most ue - 1)
                     }
-                    const int64_t t = u / nch;
-                    if (u - t * nch == nch - 1 || u == ue - 1) {
+                    const int64_t t = cc.t;
+                    if (cc.j == nch - 1 || u == ue - 1) {
                         // end of this workgroup's part of frame tile t: partial sum
                         // to slot 4 (w - w0) + wave.  D layout: lane holds rows
                         // 4 (lane / 16) + e of column lane % 16.
@@ -302,11 +336,13 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
                         // stores (vector stores count in vmcnt)
                         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
                     }
+                    adv(cc);
                 } else {
 #pragma unroll
                     for (int kk = 0; kk < KPW; ++kk)
-                        if (has(kk)) loadA(sl, un, kk);
+                        if (has(kk)) loadA(sl, cl, kk);
                 }
+                adv(cl);
             }
         }
     }
