@@ -40,7 +40,7 @@ constexpr int G1_IPT16 = 1;  // and of up to 16
 // and stored as (Re, Im) pairs), then the chunk's k-steps are shared out
 // round-robin to the waves; each wave accumulates all NRB x NF/16 output
 // blocks.  The four partial sums are added through LDS at the end.
-template <typename T, int NF, int NRB, int MAXM, int IPT, bool HILO>
+template <typename T, int NF, int NRB, int MAXM, int IPT, bool HILO, bool RED3 = false>
 __device__ __forceinline__ void gemm1_body(int bx, int by, int bz, const float2* __restrict__ X, int64_t nfr,
                                            int M, int P, int B, const T* __restrict__ A, const T* __restrict__ Alo,
                                            int nRB, int BB, int CW, int nch, int cps, float* __restrict__ zpart,
@@ -104,6 +104,20 @@ __device__ __forceinline__ void gemm1_body(int bx, int by, int bz, const float2*
         }
     };
     fetch(c0);
+    VT an[NRB], aln[NRB];
+    auto loadA = [&](int ch, int ks) {
+        const int64_t cbase = (int64_t)ch * ks_chunk * nRB;
+#pragma unroll
+        for (int r = 0; r < NRB; ++r)
+            if (r < nrb) {
+                const int64_t off = ((cbase + (int64_t)ks * nRB + rbs + r) * 64 + lane) * EPL;
+                an[r] = *reinterpret_cast<const VT*>(A + off);
+                if (HILO) aln[r] = *reinterpret_cast<const VT*>(Alo + off);
+            }
+    };
+    // the first chunk's A fragments do not depend on the STFT: load them
+    // with it
+    if (wave < ks_chunk) loadA(c0, wave);
     for (int ch = c0; ch < c1; ++ch) {
         __syncthreads();
 #pragma unroll
@@ -157,18 +171,7 @@ __device__ __forceinline__ void gemm1_body(int bx, int by, int bz, const float2*
         }
         __syncthreads();
         if (ch + 1 < c1) fetch(ch + 1);
-        const int64_t cbase = (int64_t)ch * ks_chunk * nRB;
-        VT an[NRB], aln[NRB];
-        auto loadA = [&](int ks) {
-#pragma unroll
-            for (int r = 0; r < NRB; ++r)
-                if (r < nrb) {
-                    const int64_t off = ((cbase + (int64_t)ks * nRB + rbs + r) * 64 + lane) * EPL;
-                    an[r] = *reinterpret_cast<const VT*>(A + off);
-                    if (HILO) aln[r] = *reinterpret_cast<const VT*>(Alo + off);
-                }
-        };
-        if (wave < ks_chunk) loadA(wave);
+        if (ch > c0 && wave < ks_chunk) loadA(ch, wave);
         for (int ks = wave; ks < ks_chunk; ks += 4) {
             VT a[NRB], al[NRB];
 #pragma unroll
@@ -176,7 +179,7 @@ __device__ __forceinline__ void gemm1_body(int bx, int by, int bz, const float2*
                 a[r] = an[r];
                 if (HILO) al[r] = aln[r];
             }
-            if (ks + 4 < ks_chunk) loadA(ks + 4);
+            if (ks + 4 < ks_chunk) loadA(ch, ks + 4);
             VT b[FB], bl[FB];
 #pragma unroll
             for (int j = 0; j < FB; ++j) {
@@ -197,10 +200,27 @@ __device__ __forceinline__ void gemm1_body(int bx, int by, int bz, const float2*
                     }
         }
     }
-    // add the four waves' partial sums through LDS
+    // add the four waves' partial sums through LDS (RED3: waves 1-3 at once,
+    // in three regions)
     __syncthreads();
     f4* red = reinterpret_cast<f4*>(smem);
-    for (int w = 1; w < 4; ++w) {
+    if constexpr (RED3) {
+        if (wave > 0)
+#pragma unroll
+            for (int r = 0; r < NRB; ++r)
+#pragma unroll
+                for (int j = 0; j < FB; ++j) red[(((wave - 1) * NRB + r) * FB + j) * 64 + lane] = acc[r][j];
+        __syncthreads();
+        if (wave == 0)
+#pragma unroll
+            for (int w = 0; w < 3; ++w)
+#pragma unroll
+                for (int r = 0; r < NRB; ++r)
+#pragma unroll
+                    for (int j = 0; j < FB; ++j) acc[r][j] += red[((w * NRB + r) * FB + j) * 64 + lane];
+        __syncthreads();  // LDS free for the next item
+    }
+    for (int w = 1; w < (RED3 ? 1 : 4); ++w) {
         if (wave == w)
 #pragma unroll
             for (int r = 0; r < NRB; ++r)
@@ -238,7 +258,7 @@ __global__ __launch_bounds__(256) void k_gemm1_list(const float2* __restrict__ X
     const int64_t n = *fcount;
     const int64_t items = (n + NF - 1) / NF * nsplit;
     for (int64_t it = blockIdx.x; it < items; it += gridDim.x)
-        gemm1_body<T, NF, NRB, MAXM, IPT, HILO>((int)(it / nsplit), (int)(it % nsplit), blockIdx.z, X, n, M, P, B, A,
+        gemm1_body<T, NF, NRB, MAXM, IPT, HILO, true>((int)(it / nsplit), (int)(it % nsplit), blockIdx.z, X, n, M, P, B, A,
                                                 Alo, nRB, BB, CW, nch, cps, zpart, zstride, Rp, flist, fcount);
 }
 
@@ -602,6 +622,27 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
         zpre[0] = z[min(lane, Rp - 1)];
         zpre[1] = z[min(lane + 64, Rp - 1)];
     }
+    // the list pass sums its GEMM1 partials; with up to 128 rows, 32 slots of
+    // both of a lane's rows are in flight at once
+    const bool zlist = a.zpart && Rp <= 128;
+    if (zlist) {
+        const int64_t b0 = pos * Rp + min(lane, Rp - 1), b1 = pos * Rp + min(lane + 64, Rp - 1);
+        for (int s0 = 0; s0 < a.zp_n; s0 += 32) {
+            float p0[32], p1[32];
+#pragma unroll
+            for (int k = 0; k < 32; ++k) {
+                const int64_t so = (int64_t)min(s0 + k, a.zp_n - 1) * a.zp_stride;
+                p0[k] = a.zpart[so + b0];
+                p1[k] = a.zpart[so + b1];
+            }
+#pragma unroll
+            for (int k = 0; k < 32; ++k)
+                if (s0 + k < a.zp_n) {
+                    zpre[0] += p0[k];
+                    zpre[1] += p1[k];
+                }
+        }
+    }
     for (int t0 = 0; t0 < T; t0 += 256) {
         float pv[4], kv[4];
 #pragma unroll
@@ -624,7 +665,7 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
     float dz2 = 0.f;
     for (int r = lane; r < Rp; r += 64) {
         float v = 0.f;
-        if (zfast) {
+        if (zfast || zlist) {
             v = r == lane ? zpre[0] : zpre[1];
         } else if (a.zpart) {
             // the GEMM1 partial sums of this list position, eight in flight
@@ -1057,7 +1098,7 @@ void launch_g1_list(hipStream_t s, const float2* X, svdphat_plan* p, int prec, c
     // list: one workgroup per CU
     dim3 grid(cu_count(p->device), 1, cdiv(nRB, NRB));
     const size_t xbytes = (size_t)2 * 32 * (g.CW + XPAD) * sizeof(T);
-    const size_t lds = std::max(xbytes, (size_t)NRB * 2 * 64 * sizeof(f4));
+    const size_t lds = std::max(xbytes, (size_t)3 * NRB * 2 * 64 * sizeof(f4));  // three waves' partial sums
     const T* A = (const T*)p->A[prec];
     const T* Alo = (const T*)p->Alo[prec];
     const int M = p->M;
