@@ -2,6 +2,7 @@
 // pool, and dispatch to the plan builder and the kernel launchers.
 #include "internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -11,6 +12,20 @@ namespace svdphat {
 static thread_local std::string g_last_error;
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+__global__ __launch_bounds__(256) void k_zero_words(uint32_t* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0u;
+}
+}  // namespace
+
+void zero_async(void* p, size_t bytes, hipStream_t s) {
+    const int64_t n = (int64_t)(bytes / 4);
+    if (n <= 0) return;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+    k_zero_words<<<dim3((unsigned)blocks), 256, 0, s>>>((uint32_t*)p, n);
+    SP_HIP(hipGetLastError());
+}
 void fail(int code, const std::string& msg) { throw Error{code, msg}; }
 
 // Workspace of one stream on one plan, grown on demand (hipMalloc outside any

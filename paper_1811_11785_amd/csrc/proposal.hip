@@ -452,7 +452,7 @@ void forward(svdphat_proposal* pr, const PW& o, int64_t F, hipStream_t s) {
 void backward(svdphat_proposal* pr, const PW& o, int64_t F, hipStream_t s) {
     const int H = pr->H, Cp = pr->Cp, D0 = pr->D0;
     const int ks = std::max(1, std::min(WSPLIT, (int)((F + 255) / 256)));
-    auto zero = [&](float* g, size_t n) { SP_HIP(hipMemsetAsync(g, 0, n * sizeof(float), s)); };
+    auto zero = [&](float* g, size_t n) { zero_async(g, n * sizeof(float), s); };
     // layer 3: dW3[c][h] = sum_f dlog[f][c] h2[f][h]; db3; dh2 = dlog W3, da2 = dh2 GELU'(a2)
     zero(o.g[4], (size_t)WSPLIT * Cp * H);
     mlp_gemm<true, true, EPI_F32>(o.dlog, Cp, o.h2, H, Cp, H, (int)F, ks, nullptr, nullptr, o.g[4], nullptr, H, s);
@@ -634,7 +634,7 @@ void proposal_locate(svdphat_proposal* pr, const float2* X, int64_t F, int topk,
     k_features<<<dim3((unsigned)((F * p->Rp + 255) / 256)), 256, 0, s>>>(o.z32, o.zn, F, p->Rp, o.feat);
     forward(pr, o, F, s);
     kt.end();
-    SP_HIP(hipMemsetAsync(pr->d_count, 0, sizeof(int), s));
+    zero_async(pr->d_count, sizeof(int), s);
     kt.begin("prop_rescore");
     if (p->M <= 8)
         k_propose<8><<<dim3((unsigned)((F + 3) / 4)), 256, 0, s>>>(

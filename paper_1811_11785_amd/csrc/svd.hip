@@ -1170,7 +1170,7 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     const size_t o_st = take(sizeof(unsigned long long) * 4);
     char* w = (char*)ws_get(p, s, off);
     unsigned long long* stats = counting_on() ? (unsigned long long*)(w + o_st) : nullptr;
-    if (stats) SP_HIP(hipMemsetAsync(stats, 0, sizeof(unsigned long long) * 4, s));
+    if (stats) zero_async(stats, sizeof(unsigned long long) * 4, s);
     float* zpart = (float*)(w + o_zpart);
     float* z32 = (float*)(w + o_z32);
     T* zfrag = (T*)(w + o_zfrag);
@@ -1182,7 +1182,7 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     int* hc = hilo ? (int*)(w + o_hc) : nullptr;
     // (the GEMM2 operand's padding frames feed only padding columns, whose
     // results are never written)
-    if (hilo) SP_HIP(hipMemsetAsync(hc, 0, sizeof(int), s));
+    if (hilo) zero_async(hc, sizeof(int), s);
 
     const int64_t zstride = Fc * Rp;
     KernelTimer kt(s);
