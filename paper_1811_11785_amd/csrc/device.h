@@ -70,13 +70,67 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Wave-wide reduction of N 32-bit words per lane with a commutative
+// combiner comb(v, o) (v := v combined with o), in registers: inside rows of
+// 16 lanes the partner comes by DPP (quad permutations xor 1 and xor 2, then
+// the half-row and row mirrors, which pair the already combined quads and
+// halves); across rows v_permlane16_swap and v_permlane32_swap hand every
+// lane both rows' (halves') values.  Every lane ends with the combination
+// of all 64 lanes.
+// m ? b : a on all 32 bits, by masks (a select between two arrays' words
+// can be folded into a select of the arrays' addresses, which puts them in
+// scratch memory; the bitwise blend keeps them in registers)
+__device__ __forceinline__ uint32_t blend(uint32_t a, uint32_t b, bool m) {
+    const uint32_t k = m ? ~0u : 0u;
+    return (a & ~k) | (b & k);
+}
+
+template <int CTRL, int N>
+__device__ __forceinline__ void dpp_words(const uint32_t (&v)[N], uint32_t (&o)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) o[i] = (uint32_t)__builtin_amdgcn_mov_dpp((int)v[i], CTRL, 0xF, 0xF, false);
+}
+
+template <int N, typename Comb>
+__device__ __forceinline__ void wave_reduce(uint32_t (&v)[N], Comb comb) {
+    uint32_t o[N];
+    dpp_words<0xB1>(v, o);  // quad_perm [1, 0, 3, 2]
+    comb(v, o);
+    dpp_words<0x4E>(v, o);  // quad_perm [2, 3, 0, 1]
+    comb(v, o);
+    dpp_words<0x141>(v, o);  // row_half_mirror
+    comb(v, o);
+    dpp_words<0x140>(v, o);  // row_mirror
+    comb(v, o);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v[i], v[i], false, false);
+        v[i] = r[0];
+        o[i] = r[1];
+    }
+    comb(v, o);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(v[i], v[i], false, false);
+        v[i] = r[0];
+        o[i] = r[1];
+    }
+    comb(v, o);
+}
+
 __device__ __forceinline__ float wave_max(float v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-    return v;
+    uint32_t w[1] = {__float_as_uint(v)};
+    wave_reduce(w, [](uint32_t (&a)[1], const uint32_t (&b)[1]) {
+        a[0] = __float_as_uint(fmaxf(__uint_as_float(a[0]), __uint_as_float(b[0])));
+    });
+    return __uint_as_float(w[0]);
 }
 __device__ __forceinline__ float wave_sum(float v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    uint32_t w[1] = {__float_as_uint(v)};
+    wave_reduce(w, [](uint32_t (&a)[1], const uint32_t (&b)[1]) {
+        a[0] = __float_as_uint(__uint_as_float(a[0]) + __uint_as_float(b[0]));
+    });
+    return __uint_as_float(w[0]);
 }
 
 // (value desc, index asc) order used for every argmax: ties go to the

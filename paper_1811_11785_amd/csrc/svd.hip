@@ -687,14 +687,17 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
         }
     }
     const float ef = a.ecoef * a.znorm1[f] + (a.z32_first ? 1.01f * sqrtf(wave_sum(dz2)) : 0.f);
-    for (int o = 32; o > 0; o >>= 1) {
-        const float oy = __shfl_xor(ym, o), ok = __shfl_xor(km, o);
-        const int ot = __shfl_xor(tm, o);
-        if (better(oy, ot, ym, tm)) {
-            ym = oy;
-            tm = ot;
-            km = ok;
-        }
+    {
+        // (maximum, its tile, the tile's bound) over the wave
+        uint32_t v[3] = {__float_as_uint(ym), (uint32_t)tm, __float_as_uint(km)};
+        wave_reduce(v, [](uint32_t (&x)[3], const uint32_t (&o)[3]) {
+            const bool ob = better(__uint_as_float(o[0]), (int)o[1], __uint_as_float(x[0]), (int)x[1]);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) x[i] = blend(x[i], o[i], ob);
+        });
+        ym = __uint_as_float(v[0]);
+        tm = (int)v[1];
+        km = __uint_as_float(v[2]);
     }
     wave_sync();
     const float thr = a.rescore ? ym - km * ef : ym;
@@ -738,34 +741,39 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
             }
         }
     }
-    // wave-wide best and (scored rows being distinct classes) runner-up
-    for (int o = 32; o > 0; o >>= 1) {
-        const float oy1 = __shfl_xor(y1, o), oy2 = __shfl_xor(y2, o);
-        const int oq1 = __shfl_xor(q1, o), oq2 = __shfl_xor(q2, o);
-        const int or1 = __shfl_xor(r1, o), or2 = __shfl_xor(r2, o);
-        const int oc1 = __shfl_xor(c1, o);
-        if (better(oy1, oq1, y1, q1)) {
-            // new best is the other lane's; runner-up is the better of mine-best and other's second
-            if (DEDUP) {
-                if (better(y1, q1, oy2, oq2)) {
-                    y2 = y1;
-                    q2 = q1;
-                    r2 = r1;
-                } else {
-                    y2 = oy2;
-                    q2 = oq2;
-                    r2 = or2;
-                }
-            }
-            y1 = oy1;
-            q1 = oq1;
-            r1 = or1;
-            c1 = oc1;
-        } else if (DEDUP && better(oy1, oq1, y2, q2)) {
-            y2 = oy1;
-            q2 = oq1;
-            r2 = or1;
-        }
+    // wave-wide best and (scored rows being distinct classes) runner-up:
+    // merging two (best, runner-up) pairs is commutative, as the butterfly
+    // of wave_reduce needs
+    {
+        uint32_t v[7] = {__float_as_uint(y1), (uint32_t)q1, (uint32_t)r1, (uint32_t)c1,
+                         __float_as_uint(y2), (uint32_t)q2, (uint32_t)r2};
+        wave_reduce(v, [](uint32_t (&x)[7], const uint32_t (&o)[7]) {
+            // selects only (no branches), so the words stay in registers
+            const float xy1 = __uint_as_float(x[0]), oy1 = __uint_as_float(o[0]);
+            const float xy2 = __uint_as_float(x[4]), oy2 = __uint_as_float(o[4]);
+            const bool ob = better(oy1, (int)o[1], xy1, (int)x[1]);  // the other best wins
+            // runner-up: if the other best wins, the better of this best and
+            // the other runner-up; else the better of this runner-up and the
+            // other best
+            const bool s_x1 = DEDUP && better(xy1, (int)x[1], oy2, (int)o[5]);
+            const bool s_o1 = DEDUP && better(oy1, (int)o[1], xy2, (int)x[5]);
+            uint32_t n[7];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) n[i] = blend(x[i], o[i], ob);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                n[4 + i] = !DEDUP ? x[4 + i]
+                                  : blend(blend(x[4 + i], o[i], s_o1), blend(o[4 + i], x[i], s_x1), ob);
+#pragma unroll
+            for (int i = 0; i < 7; ++i) x[i] = n[i];
+        });
+        y1 = __uint_as_float(v[0]);
+        q1 = (int)v[1];
+        r1 = (int)v[2];
+        c1 = (int)v[3];
+        y2 = __uint_as_float(v[4]);
+        q2 = (int)v[5];
+        r2 = (int)v[6];
     }
     if (q1 < 0 || q1 == 0x7fffffff) {  // no finite candidate
         q1 = a.rows[0];
@@ -795,13 +803,16 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
                 }
             }
         }
-        for (int o = 32; o > 0; o >>= 1) {
-            const float oy = __shfl_xor(sy, o);
-            const int orr = __shfl_xor(sr, o);
-            if (oy > sy) {
-                sy = oy;
-                sr = orr;
-            }
+        {
+            uint32_t v[2] = {__float_as_uint(sy), (uint32_t)sr};
+            wave_reduce(v, [](uint32_t (&x)[2], const uint32_t (&o)[2]) {
+                const float xy = __uint_as_float(x[0]), oy = __uint_as_float(o[0]);
+                const bool ob = oy > xy || (oy == xy && (int)o[1] < (int)x[1]);
+#pragma unroll
+                for (int i = 0; i < 2; ++i) x[i] = blend(x[i], o[i], ob);
+            });
+            sy = __uint_as_float(v[0]);
+            sr = (int)v[1];
         }
         y2 = sy;
         r2 = sr;
