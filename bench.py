@@ -110,6 +110,7 @@ def main():
     ap.add_argument("--workload", default="planar_q10242",
                     help="planar_q10242 (default, the headline line), ragged256 or proposal_q40962")
     ap.add_argument("--train-frames", type=int, default=2_000_000, help="training pairs of the proposal")
+    ap.add_argument("--train-epochs", type=int, default=1, help="passes over the proposal's training pairs")
     ap.add_argument("--arrays", type=int, default=256, help="arrays of the ragged workload")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MB (a known-size reference "
@@ -344,14 +345,16 @@ def bench_proposal(args, torch, amd, synth):
     log(f"plan {plan_s:.1f} s, K={plan.info['K']}, classes={plan.info['n_classes']}")
     batch = 8192
     nsteps = max(1, args.train_frames // batch)
+    total = nsteps * max(1, args.train_epochs)
     t0 = time.perf_counter()
     losses = []
-    for step in range(nsteps):
-        X = synth.plane_wave_fd_torch(mics, batch // 64, 64, 512, 16000.0, 343.0, seed=5_000_000 + step)
-        lr = 2e-3 if step < int(0.7 * nsteps) else 5e-4
+    for step in range(total):
+        # the same nsteps batches (train_frames pairs) in every epoch
+        X = synth.plane_wave_fd_torch(mics, batch // 64, 64, 512, 16000.0, 343.0, seed=5_000_000 + step % nsteps)
+        lr = 2e-3 if step < int(0.7 * total) else 5e-4
         losses.append(prop.train_step(X, lr=lr))
-        if step % 50 == 0:
-            log(f"train step {step}/{nsteps} loss {losses[-1]:.3f}")
+        if step % 100 == 0:
+            log(f"train step {step}/{total} loss {losses[-1]:.3f}")
     train_s = time.perf_counter() - t0
     # evaluation: 20000 fresh frames, SNR U[-5, 20] dB, 100-frame segments
     X = synth.plane_wave_fd_torch(mics, 200, 100, 512, 16000.0, 343.0, seed=9_999_999)
@@ -373,6 +376,15 @@ def bench_proposal(args, torch, amd, synth):
     _timed(full_step, args.warmup, torch)
     dtf = _timed(full_step, args.steps, torch)
     full = fdoa.cpu().numpy()
+    # per-kernel durations of the proposal path (HIP events on its stream)
+    amd.svdphat_timing_reset()
+    amd.svdphat_timing_enable(True)
+    for _ in range(args.steps):
+        prop_step()
+    amd.svdphat_timing_enable(False)
+    kt = amd.svdphat_timing_read()
+    amd.svdphat_timing_reset()
+    kernels = {k: dict(avg_us=1e3 * v[0] / v[1], launches=v[1]) for k, v in kt.items()}
     out = {
         "metric": "frames/s, learned proposal vs full search (planar, Q=40962)",
         "value": F * args.steps / dtp, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
@@ -380,12 +392,14 @@ def bench_proposal(args, torch, amd, synth):
         "scaling": "weak", "vs_baseline": None, "dtype": "fp16", "data": "synthetic",
         "config": {"workload": "proposal_q40962", "Q": 40962, "cells": 642, "hidden": 256,
                    "K": plan.info["K"], "frames_per_step": F, "train_pairs": nsteps * batch,
+                   "train_epochs": max(1, args.train_epochs),
                    "topk": 8, "conf_min": 0.5},
         "full_search_fps": F * args.steps / dtf, "speedup_vs_full_search": dtf / dtp,
         "miss_rate_vs_full_search": float(np.mean(pdoa != full)),
         "fallback_rate": float(pfell.mean()),
         "miss_rate_confident_frames": float(np.mean(pdoa[~pfell] != full[~pfell])) if (~pfell).any() else 0.0,
         "final_loss": float(np.mean(losses[-10:])), "train_s": train_s, "plan_build_s": plan_s,
+        "kernels_us": kernels,
     }
     print(json.dumps(out))
 

@@ -91,8 +91,9 @@ __device__ __forceinline__ void dpp_words(const uint32_t (&v)[N], uint32_t (&o)[
     for (int i = 0; i < N; ++i) o[i] = (uint32_t)__builtin_amdgcn_mov_dpp((int)v[i], CTRL, 0xF, 0xF, false);
 }
 
+// the same inside each row of 16 lanes only
 template <int N, typename Comb>
-__device__ __forceinline__ void wave_reduce(uint32_t (&v)[N], Comb comb) {
+__device__ __forceinline__ void row_reduce(uint32_t (&v)[N], Comb comb) {
     uint32_t o[N];
     dpp_words<0xB1>(v, o);  // quad_perm [1, 0, 3, 2]
     comb(v, o);
@@ -102,6 +103,12 @@ __device__ __forceinline__ void wave_reduce(uint32_t (&v)[N], Comb comb) {
     comb(v, o);
     dpp_words<0x140>(v, o);  // row_mirror
     comb(v, o);
+}
+
+template <int N, typename Comb>
+__device__ __forceinline__ void wave_reduce(uint32_t (&v)[N], Comb comb) {
+    uint32_t o[N];
+    row_reduce(v, comb);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         const auto r = __builtin_amdgcn_permlane16_swap(v[i], v[i], false, false);

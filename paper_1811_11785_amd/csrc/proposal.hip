@@ -25,6 +25,8 @@ constexpr int GPAD = 8;
 
 enum { EPI_GELU = 0, EPI_BIAS = 1, EPI_DGELU = 2, EPI_F32 = 3 };
 
+constexpr int RLIST = 1024;  // rows listed per wave before a rescoring pass
+
 __device__ __forceinline__ float gelu_f(float v) { return 0.5f * v * (1.f + erff(v * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_d(float v) {
     return 0.5f * (1.f + erff(v * 0.70710678118654752f)) + v * 0.39894228040143268f * __expf(-0.5f * v * v);
@@ -39,6 +41,33 @@ __device__ __forceinline__ float gelu_d(float v) {
 //   EPI_BIAS   out32 = acc + bias[n]
 //   EPI_DGELU  out16 = acc * GELU'(pre32[m, n])
 //   EPI_F32    out32[split][m][n] = acc (split-K partials over blockIdx.z)
+template <int EPI>
+__device__ __forceinline__ void mlp_epilogue(const f4 (&acc)[4], int m0, int n0, int wave, int lane, int M, int N,
+                                             const float* __restrict__ bias, const float* __restrict__ pre32,
+                                             float* __restrict__ out32, _Float16* __restrict__ out16, int ldo) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int m = m0 + wave * 16 + 4 * (lane >> 4) + e;
+            const int n = n0 + j * 16 + (lane & 15);
+            if (m >= M || n >= N) continue;
+            const float v = acc[j][e];
+            const int64_t o = (int64_t)m * ldo + n;
+            if (EPI == EPI_GELU) {
+                const float pv = v + bias[n];
+                out32[o] = pv;
+                out16[o] = (_Float16)gelu_f(pv);
+            } else if (EPI == EPI_BIAS) {
+                out32[o] = v + bias[n];
+            } else if (EPI == EPI_DGELU) {
+                out16[o] = (_Float16)(v * gelu_d(pre32[o]));
+            } else {
+                out32[(int64_t)blockIdx.z * M * ldo + o] = v;
+            }
+        }
+}
+
 template <bool AT, bool BT, int EPI>
 __global__ __launch_bounds__(256) void k_mlp_gemm(const _Float16* __restrict__ A, int lda,
                                                   const _Float16* __restrict__ Bm, int ldb, int M, int N, int K,
@@ -95,27 +124,62 @@ __global__ __launch_bounds__(256) void k_mlp_gemm(const _Float16* __restrict__ A
         }
         __syncthreads();
     }
+    mlp_epilogue<EPI>(acc, m0, n0, wave, lane, M, N, bias, pre32, out32, out16, ldo);
+}
+
+// The same for row-major operands whose reduction axis is contiguous (A(m,
+// k) = A[m lda + k], B(n, k) = B[n ldb + k]) with lda, ldb, the k range and
+// the pointers multiples of 8 elements: each thread stages one 16-byte piece
+// of each 64 x 32 tile, and the next tile's pieces are loaded before the
+// current tile's MFMAs.
+template <int EPI>
+__global__ __launch_bounds__(256) void k_mlp_gemm_v(const _Float16* __restrict__ A, int lda,
+                                                    const _Float16* __restrict__ Bm, int ldb, int M, int N, int K,
+                                                    int ksplit, const float* __restrict__ bias,
+                                                    const float* __restrict__ pre32, float* __restrict__ out32,
+                                                    _Float16* __restrict__ out16, int ldo) {
+    __shared__ __align__(16) _Float16 As[GT][GK + GPAD];
+    __shared__ __align__(16) _Float16 Bs[GT][GK + GPAD];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int m0 = blockIdx.x * GT, n0 = blockIdx.y * GT;
+    const int kper = (K + ksplit - 1) / ksplit;
+    const int kbeg = blockIdx.z * kper, kend = min(K, kbeg + kper);
+    const int r = tid >> 2, kk = (tid & 3) * 8;
+    const int m = m0 + r, n = n0 + r;
+    const _Float16* pa = A + (int64_t)min(m, M - 1) * lda;
+    const _Float16* pb = Bm + (int64_t)min(n, N - 1) * ldb;
+    f4 acc[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+    const h8 zero = {};
+    h8 va = zero, vb = zero;
+    auto load = [&](int k0) {
+        // rows past M or N and k past the range stage zeros (the clamped
+        // address stays inside the operand)
+        // (k range and lengths are multiples of 8: a piece is all inside or
+        // all outside; the clamped offset keeps its 8 elements in the row)
+        const bool ka = k0 + kk < kend;
+        const int ko = min(k0 + kk, kend - 8);
+        const h8 la = *reinterpret_cast<const h8*>(pa + ko);
+        const h8 lb = *reinterpret_cast<const h8*>(pb + ko);
+        va = (m < M && ka) ? la : zero;
+        vb = (n < N && ka) ? lb : zero;
+    };
+    if (kbeg < kend) load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
+        *reinterpret_cast<h8*>(&As[r][kk]) = va;
+        *reinterpret_cast<h8*>(&Bs[r][kk]) = vb;
+        __syncthreads();
+        if (k0 + GK < kend) load(k0 + GK);
+        const h8 a = *reinterpret_cast<const h8*>(&As[wave * 16 + (lane & 15)][8 * (lane >> 4)]);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int m = m0 + wave * 16 + 4 * (lane >> 4) + e;
-            const int n = n0 + j * 16 + (lane & 15);
-            if (m >= M || n >= N) continue;
-            const float v = acc[j][e];
-            const int64_t o = (int64_t)m * ldo + n;
-            if (EPI == EPI_GELU) {
-                const float pv = v + bias[n];
-                out32[o] = pv;
-                out16[o] = (_Float16)gelu_f(pv);
-            } else if (EPI == EPI_BIAS) {
-                out32[o] = v + bias[n];
-            } else if (EPI == EPI_DGELU) {
-                out16[o] = (_Float16)(v * gelu_d(pre32[o]));
-            } else {
-                out32[(int64_t)blockIdx.z * M * ldo + o] = v;
-            }
+        for (int j = 0; j < 4; ++j) {
+            const h8 b = *reinterpret_cast<const h8*>(&Bs[j * 16 + (lane & 15)][8 * (lane >> 4)]);
+            acc[j] = mfma(a, b, acc[j]);
         }
+        __syncthreads();
+    }
+    mlp_epilogue<EPI>(acc, m0, n0, wave, lane, M, N, bias, pre32, out32, out16, ldo);
 }
 
 // f = z / ||z|| in f16 (0 for z = 0); z32 rows [F][Rp] already stacked.
@@ -222,7 +286,8 @@ __global__ __launch_bounds__(256) void k_propose(const float* __restrict__ logit
                                                  const float* __restrict__ tauM, int64_t F, int32_t* __restrict__ doa,
                                                  float* __restrict__ power, uint8_t* __restrict__ fell,
                                                  int* __restrict__ flist, int* __restrict__ fcount) {
-    __shared__ float zs[4][1024];
+    __shared__ __align__(16) float zs[4][1024];
+    __shared__ int rlist[4][RLIST];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t f = (int64_t)blockIdx.x * 4 + wave;
     if (f >= F) return;
@@ -252,9 +317,46 @@ __global__ __launch_bounds__(256) void k_propose(const float* __restrict__ logit
     }
     float* zw = zs[wave];
     for (int r = lane; r < Rp; r += 64) zw[r] = z32[f * Rp + r];
-    wave_sync();
     float by = -INFINITY;
     int bq = 0x7fffffff;
+    // the scored rows of the chosen cells are listed first, then rescored
+    // 64 at a time (one row per lane), so the passes are few and full
+    int* rl = rlist[wave];
+    int nl = 0;
+    auto flush = [&]() {
+        wave_sync();
+        for (int i0 = 0; i0 < nl; i0 += 64) {
+            const int i = i0 + lane;
+            if (i < nl) {
+                const int row = rl[i];
+                // the row in 16-byte pieces, one 128-byte line (8 pieces) per
+                // batch, so each lane's line is read in one go
+                const float* u = U32R + (int64_t)row * Rp;
+                float acc[4] = {0.f, 0.f, 0.f, 0.f};
+                for (int r0 = 0; r0 < Rp; r0 += 32) {
+                    float4 pv[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) pv[k] = *reinterpret_cast<const float4*>(u + r0 + 4 * k);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const float4 zz = *reinterpret_cast<const float4*>(zw + r0 + 4 * k);
+                        acc[0] = fmaf(pv[k].x, zz.x, acc[0]);
+                        acc[1] = fmaf(pv[k].y, zz.y, acc[1]);
+                        acc[2] = fmaf(pv[k].z, zz.z, acc[2]);
+                        acc[3] = fmaf(pv[k].w, zz.w, acc[3]);
+                    }
+                }
+                const float y = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+                const int q = rows[row];
+                if (better(y, q, by, bq)) {
+                    by = y;
+                    bq = q;
+                }
+            }
+        }
+        wave_sync();
+        nl = 0;
+    };
     for (int t = 0; t < topk; ++t) {
         // next most probable cell (lowest index on ties)
         float v = -INFINITY;
@@ -265,41 +367,39 @@ __global__ __launch_bounds__(256) void k_propose(const float* __restrict__ logit
                 v = lv[j];
                 c = lane + 64 * j;
             }
-        for (int o = 32; o > 0; o >>= 1) {
-            const float ov = __shfl_xor(v, o);
-            const int oc = __shfl_xor(c, o);
-            if (better(ov, oc, v, c)) {
-                v = ov;
-                c = oc;
-            }
+        {
+            uint32_t w[2] = {__float_as_uint(v), (uint32_t)c};
+            wave_reduce(w, [](uint32_t (&x)[2], const uint32_t (&o)[2]) {
+                const bool ob = better(__uint_as_float(o[0]), (int)o[1], __uint_as_float(x[0]), (int)x[1]);
+                x[0] = blend(x[0], o[0], ob);
+                x[1] = blend(x[1], o[1], ob);
+            });
+            v = __uint_as_float(w[0]);
+            c = (int)w[1];
         }
         if (c >= C || v == -INFINITY) break;
 #pragma unroll
         for (int j = 0; j < 16; ++j)
             if (lane + 64 * j == c) lv[j] = -INFINITY;
-        for (int i = cstart[c] + lane; i < cstart[c + 1]; i += 64) {
-            const int row = crows[i];
-            const float* u = U32R + (int64_t)row * Rp;
-            float s0 = 0.f, s1 = 0.f;
-            for (int r = 0; r < Rp; r += 2) {
-                s0 = fmaf(u[r], zw[r], s0);
-                s1 = fmaf(u[r + 1], zw[r + 1], s1);
-            }
-            const float y = s0 + s1;
-            const int q = rows[row];
-            if (better(y, q, by, bq)) {
-                by = y;
-                bq = q;
-            }
+        const int b = cstart[c], e = cstart[c + 1];
+        if (nl + (e - b) > RLIST) flush();
+        for (int i = b; i < e; i += RLIST) {  // (a cell larger than the list: in pieces)
+            const int n = min(e - i, RLIST);
+            if (nl + n > RLIST) flush();
+            for (int k = lane; k < n; k += 64) rl[nl + k] = crows[i + k];
+            nl += n;
         }
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        const float oy = __shfl_xor(by, o);
-        const int oq = __shfl_xor(bq, o);
-        if (better(oy, oq, by, bq)) {
-            by = oy;
-            bq = oq;
-        }
+    flush();
+    {
+        uint32_t w[2] = {__float_as_uint(by), (uint32_t)bq};
+        wave_reduce(w, [](uint32_t (&x)[2], const uint32_t (&o)[2]) {
+            const bool ob = better(__uint_as_float(o[0]), (int)o[1], __uint_as_float(x[0]), (int)x[1]);
+            x[0] = blend(x[0], o[0], ob);
+            x[1] = blend(x[1], o[1], ob);
+        });
+        by = __uint_as_float(w[0]);
+        bq = (int)w[1];
     }
     if (bq < 0 || bq == 0x7fffffff) bq = rows[0];
     float t[MAXM];
@@ -350,6 +450,16 @@ template <bool AT, bool BT, int EPI>
 void mlp_gemm(const _Float16* A, int lda, const _Float16* Bm, int ldb, int M, int N, int K, int ksplit,
               const float* bias, const float* pre32, float* out32, _Float16* out16, int ldo, hipStream_t s) {
     dim3 grid(cdiv(M, GT), cdiv(N, GT), ksplit);
+    const int kper = cdiv(K, ksplit);
+    const bool vec = !AT && !BT && lda % 8 == 0 && ldb % 8 == 0 && K % 8 == 0 && kper % 8 == 0 && K >= 8 &&
+                     M > 0 && N > 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)Bm % 16) == 0;
+    if constexpr (!AT && !BT) {
+        if (vec) {
+            k_mlp_gemm_v<EPI><<<grid, 256, 0, s>>>(A, lda, Bm, ldb, M, N, K, ksplit, bias, pre32, out32, out16, ldo);
+            SP_HIP(hipGetLastError());
+            return;
+        }
+    }
     k_mlp_gemm<AT, BT, EPI><<<grid, 256, 0, s>>>(A, lda, Bm, ldb, M, N, K, ksplit, bias, pre32, out32, out16, ldo);
     SP_HIP(hipGetLastError());
 }

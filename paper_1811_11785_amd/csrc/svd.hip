@@ -381,10 +381,15 @@ __global__ __launch_bounds__(256) void k_zprep16(const float* __restrict__ zpart
         mx = fmaxf(mx, fabsf(v[e]));
         ss = fmaf(v[e], v[e], ss);
     }
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) {
-        mx = fmaxf(mx, __shfl_xor(mx, o));
-        ss += __shfl_xor(ss, o);
+    {
+        // over the frame's 16 lanes (one row), in registers
+        uint32_t v[2] = {__float_as_uint(mx), __float_as_uint(ss)};
+        row_reduce(v, [](uint32_t (&x)[2], const uint32_t (&o)[2]) {
+            x[0] = __float_as_uint(fmaxf(__uint_as_float(x[0]), __uint_as_float(o[0])));
+            x[1] = __float_as_uint(__uint_as_float(x[1]) + __uint_as_float(o[1]));
+        });
+        mx = __uint_as_float(v[0]);
+        ss = __uint_as_float(v[1]);
     }
     float sc = 1.f;
     if (scale16 && mx > 0.f) {
