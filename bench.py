@@ -34,9 +34,9 @@ HBM_PEAK_GBS = 8000.0
 GEMM1_TRAFFIC = {
     "sources": ["paper_1811_11785_amd/csrc/gemm1.hip", "paper_1811_11785_amd/csrc/device.h"],
     "sha256": "aa2b81368de679052e9e73ae7d9d0f72ae80ff65f4cc76745f32ca071521df48 "
-              "9423d8845f3a9560d4ec1300cfd8c2a94532c2a7fe0f808cdd94ba1214b7f8c4",
+              "012ce64b28aebbf506939a96bb58bb2188b07ebc7d2fd881ba769f6007672f8c",
     "frames": 20000,
-    "bytes": 425.1e6 + 55.1e6,
+    "bytes": 425.0e6 + 55.1e6,
 }
 
 
