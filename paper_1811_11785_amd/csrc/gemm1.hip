@@ -17,11 +17,12 @@
 //     unit's KSC = ceil(8 MM (MM - 1) / 32) k-steps, keep a ring of A
 //     fragments in flight and run the MFMAs, each accumulating every (row
 //     block, frame block) of the tile's Z; at the end of a frame tile (or
-//     of the range) each consumer writes its partial sum to its own slot:
-//     slot 4 (w - w0) + wave, w0 the first workgroup whose range meets the
+//     of the range) the four consumers' partial sums are added through LDS
+//     (three rounds, with the producers taking part in the barriers) and
+//     written to slot w - w0, w0 the first workgroup whose range meets the
 //     tile.
 // One barrier per unit hands a PHAT tile from the producers to the
-// consumers.  The Z preparation sums the 4 (w1 - w0 + 1) slots of a frame.
+// consumers.  The Z preparation sums the w1 - w0 + 1 slots of a frame.
 //
 // Memory order.  Vector-memory loads complete in issue order for a wave's
 // wait counter, so a wave that waits for one load also waits for every load
@@ -106,6 +107,8 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
     typedef typename Vec<T>::pair VP;
     extern __shared__ __align__(16) char smem[];
     T* xsb = reinterpret_cast<T*>(smem);  // two tiles of NF x LDX
+    // then the region where the consumers add their partial sums
+    f4* red = reinterpret_cast<f4*>(smem + (size_t)2 * NF * LDX * sizeof(T));
 
     const int G = gridDim.x, w = blockIdx.x;
     const int64_t ub = (int64_t)w * U / G, ue = (int64_t)(w + 1) * U / G;  // this workgroup's units
@@ -233,8 +236,10 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
             if ((t + 1) * NF <= nfr && (c + 1) * BB <= B) phat_impl(std::true_type{}, d, xs);
             else phat_impl(std::false_type{}, d, xs);
         };
-        // cursors: cf the next unit to fetch, cp the next unit to form
-        Cur cf = cur_at(ub), cp = cur_at(ub);
+        // cursors: cf the next unit to fetch, cp the next unit to form, cu
+        // the unit whose MFMAs the consumers run (its tile end brings the
+        // six barriers of their partial-sum rounds)
+        Cur cf = cur_at(ub), cp = cur_at(ub), cu = cur_at(ub);
 #pragma unroll
         for (int d = 0; d < XD; ++d) {
             fetch(d, cf);  // units ub + d (at most ue - 1)
@@ -260,6 +265,11 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
                 }
                 fetch((d + 1) % XD, cf);  // unit u + 1 + XD (at most ue - 1)
                 adv(cf);
+                if (u < ue) {
+                    if (cu.j == nch - 1 || u == ue - 1)
+                        for (int k = 0; k < 6; ++k) __syncthreads();
+                    adv(cu);
+                }
             }
         }
     } else {
@@ -315,15 +325,32 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
                     }
                     const int64_t t = cc.t;
                     if (cc.j == nch - 1 || u == ue - 1) {
-                        // end of this workgroup's part of frame tile t: partial sum
-                        // to slot 4 (w - w0) + wave.  D layout: lane holds rows
-                        // 4 (lane / 16) + e of column lane % 16.
-                        const int slot = 4 * (w - g1s_owner(t * nch, G, U)) + wave;
+                        // end of this workgroup's part of frame tile t: the four
+                        // consumers' sums are added in wave 0 (wave k writes,
+                        // wave 0 adds, k = 3, 2, 1; every round between two
+                        // barriers the producers also pass), which writes slot
+                        // w - w0.  D layout: lane holds rows 4 (lane / 16) + e
+                        // of column lane % 16.
+                        for (int k = 3; k >= 1; --k) {
+                            if (wave == k)
+#pragma unroll
+                                for (int r = 0; r < NRB; ++r)
+#pragma unroll
+                                    for (int j = 0; j < FB; ++j) red[(r * FB + j) * 64 + lane] = acc[r][j];
+                            __syncthreads();
+                            if (wave == 0)
+#pragma unroll
+                                for (int r = 0; r < NRB; ++r)
+#pragma unroll
+                                    for (int j = 0; j < FB; ++j) acc[r][j] += red[(r * FB + j) * 64 + lane];
+                            __syncthreads();
+                        }
+                        const int slot = w - g1s_owner(t * nch, G, U);
 #pragma unroll
                         for (int j = 0; j < FB; ++j) {
                             const int64_t fpos = t * NF + j * 16 + (lane & 15);
                             float* zp = zpart + (int64_t)slot * zstride + fpos * Rp;
-                            if (fpos < nfr)
+                            if (wave == 0 && fpos < nfr)
 #pragma unroll
                                 for (int r = 0; r < NRB; ++r)
                                     *reinterpret_cast<f4*>(zp + r * 16 + 4 * (lane >> 4)) = acc[r][j];
@@ -353,10 +380,11 @@ constexpr bool g1s_ok(int M, int nRB) { return M >= 6 && M <= 8 && (nRB == 2 || 
 
 // LDS of the streamed kernel: two PHAT tiles, and at least 81 KiB so that
 // one workgroup runs per CU
-template <typename T, int MM>
+template <typename T, int MM, int NRB>
 constexpr size_t g1s_lds() {
     constexpr size_t tiles = 2 * G1S_NF * (g1s_ksc(MM) * Mf<T>::KSTEP + G1S_PAD) * sizeof(T);
-    return tiles > 81 * 1024 ? tiles : 81 * 1024;
+    constexpr size_t b = tiles + (size_t)NRB * (G1S_NF / 16) * 64 * sizeof(f4);  // + the reduction region
+    return b > 81 * 1024 ? b : 81 * 1024;
 }
 
 template <typename T, int MM>
@@ -367,7 +395,7 @@ void launch_mm(int nRB, int G, hipStream_t s, const float2* X, int64_t F, int B,
 #define G1S_CASE(NRB_)                                                                                         \
     case NRB_:                                                                                                 \
         if constexpr (g1s_ok(MM, NRB_))                                                                        \
-            k_gemm1s<T, MM, NRB_, G1S_XD><<<G, 512, g1s_lds<T, MM>(), s>>>(X, F, B, a, nch, U, zpart, zstride, \
+            k_gemm1s<T, MM, NRB_, G1S_XD><<<G, 512, g1s_lds<T, MM, NRB_>(), s>>>(X, F, B, a, nch, U, zpart, zstride, \
                                                                            Rp);                               \
         return;
         G1S_CASE(2)
@@ -412,7 +440,7 @@ bool g1s_sched(int prec, const svdphat_plan* p, int64_t F, G1Sched* out) {
     int runs = 1;
     for (int64_t t = 0; t < ftiles; ++t)
         runs = std::max(runs, g1s_owner((t + 1) * sc.nch - 1, sc.G, sc.U) - g1s_owner(t * sc.nch, sc.G, sc.U) + 1);
-    sc.slots = 4 * runs;
+    sc.slots = runs;
     *out = sc;
     return true;
 }

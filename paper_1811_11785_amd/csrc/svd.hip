@@ -277,13 +277,13 @@ __global__ __launch_bounds__(256) void k_gemm1(const float2* __restrict__ X, int
 // [2^13, 2^14)), in B-operand fragment order [frame/16][k-step][lane][EPL].
 // Partial sums of GEMM1 to add for frame f: nsplit, or with the streamed
 // GEMM1 (sG > 0 workgroups over sU units of snch chunks per 64-frame tile)
-// four per workgroup whose unit range meets the frame's tile.
+// one per workgroup whose unit range meets the frame's tile.
 __device__ __forceinline__ int zpart_count(int64_t f, int nsplit, int sG, int64_t sU, int snch) {
     if (sG <= 0) return nsplit;
     const int64_t t = f >> 6;
     const int64_t u0 = t * snch, u1 = u0 + snch - 1;
     const int w0 = (int)(((u0 + 1) * sG - 1) / sU), w1 = (int)(((u1 + 1) * sG - 1) / sU);
-    return 4 * (w1 - w0 + 1);
+    return w1 - w0 + 1;
 }
 
 template <typename T>
