@@ -12,7 +12,8 @@
 //   k_gemm2   Y = Re(U Z) (eqs. (13)-(14)) with MFMA.  Each wave holds the U
 //             fragments of one tile of 64 scored directions in registers and
 //             streams frames; its epilogue keeps one maximum per (frame, tile).
-//   k_final   per frame: every tile whose maximum is within the rounding bound
+//   k_final   (k_final_np without the power) per frame: every tile whose
+//             maximum is within the rounding bound
 //             of the frame maximum is rescored in FP32; best class, runner-up
 //             and margin; frames whose margin is within the modelled GEMM1
 //             rounding are queued for a hi/lo recomputation, which
