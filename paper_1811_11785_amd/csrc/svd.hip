@@ -927,7 +927,11 @@ __global__ __launch_bounds__(256) void k_power(const float2* __restrict__ X, int
 void launch_power(const svdphat_plan* p, const float2* X, const int32_t* doa, int64_t F, float* power,
                   const int* flist, const int* fcount, hipStream_t s) {
     const dim3 grid(flist ? 512u : (unsigned)((F + 3) / 4));
-    if (p->M <= 8) k_power<8><<<grid, 256, 0, s>>>(X, p->M, p->B, doa, p->d_tauM_all, F, power, flist, fcount);
+    // the exact microphone count where it is common (no padded microphone's
+    // loads, fewer registers)
+    if (p->M == 6) k_power<6><<<grid, 256, 0, s>>>(X, p->M, p->B, doa, p->d_tauM_all, F, power, flist, fcount);
+    else if (p->M == 7) k_power<7><<<grid, 256, 0, s>>>(X, p->M, p->B, doa, p->d_tauM_all, F, power, flist, fcount);
+    else if (p->M <= 8) k_power<8><<<grid, 256, 0, s>>>(X, p->M, p->B, doa, p->d_tauM_all, F, power, flist, fcount);
     else k_power<16><<<grid, 256, 0, s>>>(X, p->M, p->B, doa, p->d_tauM_all, F, power, flist, fcount);
 }
 
