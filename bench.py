@@ -33,10 +33,10 @@ HBM_PEAK_GBS = 8000.0
 # were measured on, identified by the SHA-256 of those files.
 GEMM1_TRAFFIC = {
     "sources": ["paper_1811_11785_amd/csrc/gemm1.hip", "paper_1811_11785_amd/csrc/device.h"],
-    "sha256": "aa2b81368de679052e9e73ae7d9d0f72ae80ff65f4cc76745f32ca071521df48 "
+    "sha256": "d69c0bab699f2e4e706732af65545eac11ae2606fde741dc4fe14676404d1eda "
               "012ce64b28aebbf506939a96bb58bb2188b07ebc7d2fd881ba769f6007672f8c",
     "frames": 20000,
-    "bytes": 425.0e6 + 55.1e6,
+    "bytes": 412.3e6 + 13.8e6,
 }
 
 
