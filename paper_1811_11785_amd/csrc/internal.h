@@ -93,7 +93,7 @@ struct FinalArgs {
     int Rp;
     float ecoef;            // eps_t = kappa_t * (ecoef ||z1|| + 1.01 ||z - z1||)
     int rescore;
-    const float* U32T;      // [ntile][Rp][64]
+    const float* U32T;      // [ntile][Rp/4][64][4]
     const float* tkappa;    // [ntile] max ||U_q|| in the tile
     const float* sig;       // [Rp] singular value of each stacked row of Z
     const int32_t* rows;    // [ncls] direction of each scored row
@@ -222,7 +222,7 @@ struct svdphat_plan {
     void* Alo[3] = {nullptr, nullptr, nullptr};  // low parts (16-bit only)
     void* Ufr[3] = {nullptr, nullptr, nullptr};  // GEMM2 operand per precision
     float uscale[3] = {1.f, 1.f, 1.f};           // exact power-of-two scale of U per precision
-    float* U32T = nullptr;                       // [ntile][Rp][QTILE] FP32 rescoring rows
+    float* U32T = nullptr;                       // [ntile][Rp/4][QTILE][4] FP32 rescoring rows
     float* d_tkappa = nullptr;                   // [ntile] largest ||U_q|| of each tile
     float* d_sig = nullptr;                      // [Rp] singular value of each stacked row of Z
     int32_t* d_rows = nullptr;                   // [ncls] direction index of row

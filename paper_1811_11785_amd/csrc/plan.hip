@@ -470,12 +470,15 @@ void build_plan(svdphat_plan* p, const double* mics, const double* grid) {
         pack_U<__bf16>(p, Ust, 1.f, ub);
         upload(ub, &p->Ufr[P_BF16], bytes);
         p->uscale[P_BF16] = 1.f;
-        // FP32 rescoring rows, transposed per tile: [tile][k][QTILE]
+        // FP32 rescoring rows, per tile [tile][k/4][QTILE][4]: a lane (row)
+        // reads four consecutive k in one 16-byte piece, and a wave's pieces
+        // for one k/4 are contiguous
         const int ntile = p->ncls_pad / QTILE;
         std::vector<float> t((size_t)ntile * p->Rp * QTILE, 0.f);
         for (int r = 0; r < p->ncls; ++r)
             for (int k = 0; k < p->Rp; ++k)
-                t[((size_t)(r / QTILE) * p->Rp + k) * QTILE + r % QTILE] = Ust[(size_t)r * p->Rp + k];
+                t[(((size_t)(r / QTILE) * (p->Rp / 4) + k / 4) * QTILE + r % QTILE) * 4 + k % 4] =
+                    Ust[(size_t)r * p->Rp + k];
         void* d = nullptr;
         upload(t, &d, bytes);
         p->U32T = (float*)d;

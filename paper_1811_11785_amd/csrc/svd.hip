@@ -65,12 +65,19 @@ __device__ __forceinline__ void gemm1_body(int bx, int by, int bz, const float2*
     const int ks_chunk = CW / KS;
     const int twoP = 2 * P;
 
-    for (int i = threadIdx.x; i < NF * ldx; i += 256) {
-        if (i % ldx >= BB * twoP) {
-            xs[i] = cvt<T>(0.f);
-            if (HILO) xl[i] = cvt<T>(0.f);
-        }
-    }
+    // the first chunk's A fragments depend on nothing: they go out first
+    VT an[NRB], aln[NRB];
+    auto loadA = [&](int ch, int ks) {
+        const int64_t cbase = (int64_t)ch * ks_chunk * nRB;
+#pragma unroll
+        for (int r = 0; r < NRB; ++r)
+            if (r < nrb) {
+                const int64_t off = ((cbase + (int64_t)ks * nRB + rbs + r) * 64 + lane) * EPL;
+                an[r] = *reinterpret_cast<const VT*>(A + off);
+                if (HILO) aln[r] = *reinterpret_cast<const VT*>(Alo + off);
+            }
+    };
+    if (wave < ks_chunk) loadA(c0, wave);
     f4 acc[NRB][FB];
 #pragma unroll
     for (int r = 0; r < NRB; ++r)
@@ -105,20 +112,17 @@ __device__ __forceinline__ void gemm1_body(int bx, int by, int bz, const float2*
         }
     };
     fetch(c0);
-    VT an[NRB], aln[NRB];
-    auto loadA = [&](int ch, int ks) {
-        const int64_t cbase = (int64_t)ch * ks_chunk * nRB;
-#pragma unroll
-        for (int r = 0; r < NRB; ++r)
-            if (r < nrb) {
-                const int64_t off = ((cbase + (int64_t)ks * nRB + rbs + r) * 64 + lane) * EPL;
-                an[r] = *reinterpret_cast<const VT*>(A + off);
-                if (HILO) aln[r] = *reinterpret_cast<const VT*>(Alo + off);
-            }
-    };
-    // the first chunk's A fragments do not depend on the STFT: load them
-    // with it
-    if (wave < ks_chunk) loadA(c0, wave);
+    // zero the pad columns past the chunk's pair products (read by the last
+    // k-step) while the loads are in flight
+    {
+        const int c0w = BB * twoP, pw = ldx - c0w;
+        for (int i = threadIdx.x; i < NF * pw; i += 256) {
+            const int fl = i / pw;
+            const int idx = fl * ldx + c0w + (i - fl * pw);
+            xs[idx] = cvt<T>(0.f);
+            if (HILO) xl[idx] = cvt<T>(0.f);
+        }
+    }
     for (int ch = c0; ch < c1; ++ch) {
         __syncthreads();
 #pragma unroll
@@ -584,17 +588,34 @@ __global__ __launch_bounds__(256) void k_gemm2_list(const _Float16* __restrict__
 
 
 
-// y = sum_r ut[r * QTILE] zw[r] (one lane's row of a tile in the transposed
-// FP32 rescoring copy; Rp is a multiple of 32).  The loads of a 32-row batch
-// are all issued before their FMAs so that many are in flight at once.
+// y = sum_r U[row, r] zw[r] for one lane's row of a tile of the FP32
+// rescoring copy, laid out [tile][Rp/4][QTILE][4] (four consecutive r of a
+// row in one 16-byte piece, a wave's pieces for one r/4 in 1 KiB); ut points
+// at the lane's first piece.  Batches of NB pieces are issued before their
+// FMAs; NB = 8 keeps the registers of a many-wave kernel down, a larger NB
+// puts a whole row in flight where few waves run.  The products go into
+// four partial sums by r mod 4, each in increasing r, whatever NB is.
+// (Rp is a multiple of 32.)
+template <int NB>
 __device__ __forceinline__ float row_dot(const float* __restrict__ ut, const float* zw, int Rp) {
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int r0 = 0; r0 < Rp; r0 += 32) {
-        float v[32];
+    const int nq = Rp / 4;
+    for (int q0 = 0; q0 < nq; q0 += NB) {
+        f4 v[NB];
 #pragma unroll
-        for (int i = 0; i < 32; ++i) v[i] = ut[(int64_t)(r0 + i) * QTILE];
+        for (int b = 0; b < NB; b += 8)
+            if (q0 + b < nq)
 #pragma unroll
-        for (int i = 0; i < 32; ++i) acc[i & 3] = fmaf(v[i], zw[r0 + i], acc[i & 3]);
+                for (int i = b; i < b + 8; ++i) v[i] = *reinterpret_cast<const f4*>(ut + (int64_t)(q0 + i) * (QTILE * 4));
+#pragma unroll
+        for (int b = 0; b < NB; b += 8)
+            if (q0 + b < nq)
+#pragma unroll
+                for (int i = b; i < b + 8; ++i) {
+                    const f4 zv = *reinterpret_cast<const f4*>(zw + 4 * (q0 + i));
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc[e] = fmaf(v[i][e], zv[e], acc[e]);
+                }
     }
     return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
@@ -604,15 +625,46 @@ __device__ __forceinline__ float row_dot(const float* __restrict__ ut, const flo
 // candidate tile, its rows of the FP32 copy of U with their directions and
 // classes; (3) the per-microphone delays of the chosen class and the
 // frame's STFT values (the power).  Each round's loads are issued together.
-template <int MAXM, bool DEDUP>
+// HILO: the hi/lo pass over its frame list, with z the sum of the list
+// GEMM1's zp_n partials (zpart) and the first pass's z in z32_first; it runs
+// few waves, so every round trip is exposed and the loads are issued as
+// early as their addresses are known.
+template <int MAXM, bool DEDUP, bool HILO = false>
 __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
     __shared__ float zs[4][1024];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the frame position is wave-uniform: list entries and per-frame scalars
+    // come in on scalar loads, apart from the vector loads
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t n = a.flist ? (int64_t)*a.fcount : a.nfr;
     const int64_t pos = (int64_t)bx * 4 + wave;
     if (pos >= n) return;
-    const int64_t f = a.flist ? (int64_t)a.flist[pos] : pos;
     const int Rp = a.Rp, T = a.ntile;
+    const bool r128 = Rp <= 128;
+    // HILO: the partial slots of this list position (run k = Rp floats at
+    // zpart + k * zp_stride + pos * Rp) depend on the position only, so they
+    // are issued before the frame index arrives: up to 16 16-byte pieces per
+    // lane, later staged in LDS and summed per row in slot order
+    constexpr int ZQ = HILO ? 16 : 1;
+    __shared__ float zpl[HILO ? 4 : 1][HILO ? 64 * 4 * ZQ : 1];
+    const int nq = Rp / 4, nitem = a.zp_n * nq;
+    const bool zlist = HILO && r128 && nitem <= 64 * ZQ;
+    f4 zq[ZQ];
+    int zit[ZQ];
+    if constexpr (HILO) {
+        const float rnq = __builtin_amdgcn_rcpf((float)nq);
+#pragma unroll
+        for (int i = 0; i < ZQ; ++i) {
+            // piece it = (run k, 16-byte column j), clamped into range (the
+            // clamped copies are loaded but not used); the +0.5 keeps the
+            // float quotient at least 1/64 clear of integers, so truncating
+            // it is exact
+            const int it = min(lane + 64 * i, nitem - 1);
+            const int k = (int)(((float)it + 0.5f) * rnq), j = it - k * nq;
+            zit[i] = it;
+            zq[i] = *reinterpret_cast<const f4*>(a.zpart + (int64_t)k * a.zp_stride + pos * Rp + 4 * j);
+        }
+    }
+    const int64_t f = a.flist ? (int64_t)a.flist[pos] : pos;
     const float* pm = a.pmax + f * a.pstride;
 
     // ---- round 1: frame maximum over tiles, the tile holding it and that
@@ -622,32 +674,15 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
     // z of up to 128 rows is loaded with the tile maxima, so both arrive
     // in one round trip
     const float* z = a.z32 + pos * Rp;
-    const bool zfast = !a.zpart && Rp <= 128;
-    float zpre[2] = {0.f, 0.f};
+    const bool zfast = !HILO && r128;
+    float zpre[2] = {0.f, 0.f}, zf[2] = {0.f, 0.f};
     if (zfast) {
         zpre[0] = z[min(lane, Rp - 1)];
         zpre[1] = z[min(lane + 64, Rp - 1)];
     }
-    // the list pass sums its GEMM1 partials; with up to 128 rows, 32 slots of
-    // both of a lane's rows are in flight at once
-    const bool zlist = a.zpart && Rp <= 128;
-    if (zlist) {
-        const int64_t b0 = pos * Rp + min(lane, Rp - 1), b1 = pos * Rp + min(lane + 64, Rp - 1);
-        for (int s0 = 0; s0 < a.zp_n; s0 += 32) {
-            float p0[32], p1[32];
-#pragma unroll
-            for (int k = 0; k < 32; ++k) {
-                const int64_t so = (int64_t)min(s0 + k, a.zp_n - 1) * a.zp_stride;
-                p0[k] = a.zpart[so + b0];
-                p1[k] = a.zpart[so + b1];
-            }
-#pragma unroll
-            for (int k = 0; k < 32; ++k)
-                if (s0 + k < a.zp_n) {
-                    zpre[0] += p0[k];
-                    zpre[1] += p1[k];
-                }
-        }
+    if (HILO && r128 && a.z32_first) {
+        zf[0] = a.z32_first[f * Rp + min(lane, Rp - 1)];
+        zf[1] = a.z32_first[f * Rp + min(lane + 64, Rp - 1)];
     }
     for (int t0 = 0; t0 < T; t0 += 256) {
         float pv[4], kv[4];
@@ -667,13 +702,27 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
             }
         }
     }
+    // the partial slots through LDS, each row summed in slot order
+    if constexpr (HILO) {
+        if (zlist) {
+            float* zl = zpl[wave];
+#pragma unroll
+            for (int i = 0; i < ZQ; ++i) *reinterpret_cast<f4*>(zl + 4 * zit[i]) = zq[i];  // copies: same value
+            wave_sync();
+            const int l0 = min(lane, Rp - 1), l1 = min(lane + 64, Rp - 1);
+            for (int k = 0; k < a.zp_n; ++k) {
+                zpre[0] += zl[k * Rp + l0];
+                zpre[1] += zl[k * Rp + l1];
+            }
+        }
+    }
     float* zw = zs[wave];
     float dz2 = 0.f;
     for (int r = lane; r < Rp; r += 64) {
         float v = 0.f;
         if (zfast || zlist) {
             v = r == lane ? zpre[0] : zpre[1];
-        } else if (a.zpart) {
+        } else if (HILO) {
             // the GEMM1 partial sums of this list position, eight in flight
             for (int s0 = 0; s0 < a.zp_n; s0 += 8) {
                 float part[8];
@@ -687,12 +736,12 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
             v = z[r];
         }
         zw[r] = v;
-        if (a.z32_first) {
-            const float d = v - a.z32_first[f * Rp + r];
+        if (HILO && a.z32_first) {
+            const float d = v - (r128 ? (r == lane ? zf[0] : zf[1]) : a.z32_first[f * Rp + r]);
             dz2 += d * d;
         }
     }
-    const float ef = a.ecoef * a.znorm1[f] + (a.z32_first ? 1.01f * sqrtf(wave_sum(dz2)) : 0.f);
+    const float ef = a.ecoef * a.znorm1[f] + (HILO && a.z32_first ? 1.01f * sqrtf(wave_sum(dz2)) : 0.f);
     {
         // (maximum, its tile, the tile's bound) over the wave
         uint32_t v[3] = {__float_as_uint(ym), (uint32_t)tm, __float_as_uint(km)};
@@ -727,7 +776,8 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
             const int row = tt * QTILE + lane;
             const int q = a.rows[row < a.ncls ? row : 0];
             const int c = a.rowcls[row];
-            const float y = row_dot(a.U32T + (int64_t)tt * Rp * QTILE + lane, zw, Rp);
+            const float* ut = a.U32T + (int64_t)tt * Rp * QTILE + 4 * lane;
+            const float y = HILO && r128 ? row_dot<32>(ut, zw, Rp) : row_dot<8>(ut, zw, Rp);
             if (row < a.ncls) {
                 if (better(y, q, y1, q1)) {
                     if (DEDUP) {
@@ -801,7 +851,8 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
                 mask &= mask - 1;
                 const int row = tt * QTILE + lane;
                 if (row < a.ncls && a.rowcls[row] != cls) {
-                    const float y = row_dot(a.U32T + (int64_t)tt * Rp * QTILE + lane, zw, Rp);
+                    const float* ut = a.U32T + (int64_t)tt * Rp * QTILE + 4 * lane;
+                    const float y = HILO && r128 ? row_dot<32>(ut, zw, Rp) : row_dot<8>(ut, zw, Rp);
                     if (y > sy) {
                         sy = y;
                         sr = row;
@@ -833,13 +884,14 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
     // redone.  ||(U_q1 - U_q2) sigma|| <= 2 max_q ||U_q sigma|| decides most
     // frames without loading the two rows.
     bool redo = false;
-    if (a.hlist && !a.flist && (y1 - yr) < a.hilo_k * a.u * 2.f * a.usig_max) {
+    if (!HILO && a.hlist && !a.flist && (y1 - yr) < a.hilo_k * a.u * 2.f * a.usig_max) {
         float d2 = 0.f;
         if (r2 >= 0 && y2 >= ncmax) {
-            const float* u1 = a.U32T + (int64_t)(r1 / QTILE) * Rp * QTILE + r1 % QTILE;
-            const float* u2 = a.U32T + (int64_t)(r2 / QTILE) * Rp * QTILE + r2 % QTILE;
+            const float* u1 = a.U32T + (int64_t)(r1 / QTILE) * Rp * QTILE + 4 * (r1 % QTILE);
+            const float* u2 = a.U32T + (int64_t)(r2 / QTILE) * Rp * QTILE + 4 * (r2 % QTILE);
             for (int r = lane; r < Rp; r += 64) {
-                const float d = (u1[(int64_t)r * QTILE] - u2[(int64_t)r * QTILE]) * a.sig[r];
+                const int64_t o = (int64_t)(r / 4) * (QTILE * 4) + r % 4;
+                const float d = (u1[o] - u2[o]) * a.sig[r];
                 d2 += d * d;
             }
             d2 = wave_sum(d2);
@@ -893,11 +945,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     final_body<0, DEDUP>(blockIdx.x, a);
 }
 
-// the same over a device-counted frame list, grid-stride (few frames)
+// the hi/lo pass over its device-counted frame list, grid-stride (few
+// frames)
 template <int MAXM, bool DEDUP>
 __global__ __launch_bounds__(256) void k_final_list(FinalArgs a) {
     const int64_t n = *a.fcount;
-    for (int64_t bx = blockIdx.x; bx * 4 < n; bx += gridDim.x) final_body<MAXM, DEDUP>((int)bx, a);
+    for (int64_t bx = blockIdx.x; bx * 4 < n; bx += gridDim.x) final_body<MAXM, DEDUP, true>((int)bx, a);
 }
 
 
