@@ -592,26 +592,27 @@ __global__ __launch_bounds__(256) void k_gemm2_list(const _Float16* __restrict__
 // rescoring copy, laid out [tile][Rp/4][QTILE][4] (four consecutive r of a
 // row in one 16-byte piece, a wave's pieces for one r/4 in 1 KiB); ut points
 // at the lane's first piece.  Batches of NB pieces are issued before their
-// FMAs; NB = 8 keeps the registers of a many-wave kernel down, a larger NB
-// puts a whole row in flight where few waves run.  The products go into
+// FMAs; a small NB keeps the registers of a many-wave kernel down, a larger
+// NB puts a whole row in flight where few waves run.  The products go into
 // four partial sums by r mod 4, each in increasing r, whatever NB is.
 // (Rp is a multiple of 32.)
 template <int NB>
 __device__ __forceinline__ float row_dot(const float* __restrict__ ut, const float* zw, int Rp) {
+    constexpr int SB = NB < 8 ? NB : 8;  // nq is a multiple of 8, so of SB
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
     const int nq = Rp / 4;
     for (int q0 = 0; q0 < nq; q0 += NB) {
         f4 v[NB];
 #pragma unroll
-        for (int b = 0; b < NB; b += 8)
+        for (int b = 0; b < NB; b += SB)
             if (q0 + b < nq)
 #pragma unroll
-                for (int i = b; i < b + 8; ++i) v[i] = *reinterpret_cast<const f4*>(ut + (int64_t)(q0 + i) * (QTILE * 4));
+                for (int i = b; i < b + SB; ++i) v[i] = *reinterpret_cast<const f4*>(ut + (int64_t)(q0 + i) * (QTILE * 4));
 #pragma unroll
-        for (int b = 0; b < NB; b += 8)
+        for (int b = 0; b < NB; b += SB)
             if (q0 + b < nq)
 #pragma unroll
-                for (int i = b; i < b + 8; ++i) {
+                for (int i = b; i < b + SB; ++i) {
                     const f4 zv = *reinterpret_cast<const f4*>(zw + 4 * (q0 + i));
 #pragma unroll
                     for (int e = 0; e < 4; ++e) acc[e] = fmaf(v[i][e], zv[e], acc[e]);
@@ -777,7 +778,7 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
             const int q = a.rows[row < a.ncls ? row : 0];
             const int c = a.rowcls[row];
             const float* ut = a.U32T + (int64_t)tt * Rp * QTILE + 4 * lane;
-            const float y = HILO && r128 ? row_dot<32>(ut, zw, Rp) : row_dot<8>(ut, zw, Rp);
+            const float y = HILO && r128 ? row_dot<32>(ut, zw, Rp) : row_dot<4>(ut, zw, Rp);
             if (row < a.ncls) {
                 if (better(y, q, y1, q1)) {
                     if (DEDUP) {
@@ -852,7 +853,7 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
                 const int row = tt * QTILE + lane;
                 if (row < a.ncls && a.rowcls[row] != cls) {
                     const float* ut = a.U32T + (int64_t)tt * Rp * QTILE + 4 * lane;
-                    const float y = HILO && r128 ? row_dot<32>(ut, zw, Rp) : row_dot<8>(ut, zw, Rp);
+                    const float y = HILO && r128 ? row_dot<32>(ut, zw, Rp) : row_dot<4>(ut, zw, Rp);
                     if (y > sy) {
                         sy = y;
                         sr = row;
@@ -939,9 +940,11 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs a) {
 
 
 // the same without the power (k_power computes it afterwards): few enough
-// registers for five waves per SIMD, so more frames' dependent loads overlap
+// registers (rows rescored four pieces at a time) for eight waves per SIMD,
+// so more frames' dependent loads overlap; that beats fewer, larger load
+// rounds per candidate tile at fewer waves
 template <bool DEDUP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_final_np(FinalArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_final_np(FinalArgs a) {
     final_body<0, DEDUP>(blockIdx.x, a);
 }
 
