@@ -61,6 +61,9 @@ extern "C" {
 #define SVDPHAT_HILO     0x2u /* recompute Z = S V^H X with a split hi/lo
                                  (compensated) product for frames whose
                                  rescored top-two margin is small */
+#define SVDPHAT_HILO_ALL 0x4u /* the hi/lo pass for every frame, whatever
+                                 its margin (implies SVDPHAT_HILO; with
+                                 FP32 operands there is no hi/lo pass) */
 
 typedef struct svdphat_plan svdphat_plan;
 
@@ -129,7 +132,7 @@ int svdphat_plan_export(const svdphat_plan* plan, double* sigma, double* U,
  *   X          device, complex64 [F][M][N/2+1] STFT frames.
  *   F          number of frames, >= 0 (0 is a no-op).
  *   precision  SVDPHAT_FP32 | SVDPHAT_BF16 | SVDPHAT_FP16.
- *   mode       SVDPHAT_RESCORE | SVDPHAT_HILO.
+ *   mode       SVDPHAT_RESCORE | SVDPHAT_HILO | SVDPHAT_HILO_ALL.
  *   doa        device, int32 [F]: class-lowest index of argmax_q Y_q.
  *   power      device, f32 [F]: Y at doa from the row of W (step 4, eq. (9)).
  *   yhat       device, f32 [F] or NULL: the reduced power Re{D_q Z} at doa.

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libsvdphat.so")
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NUMERIC, E_NODEV, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 KEEP_W, NO_DEDUP = 0x1, 0x2
 FP32, BF16, FP16 = 0, 1, 2
-RESCORE, HILO = 0x1, 0x2
+RESCORE, HILO, HILO_ALL = 0x1, 0x2, 0x4
 RAGGED_TUNE = 0x1
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16}
 
@@ -238,9 +238,10 @@ class Plan:
     def handle(self):
         return self._h
 
-    def locate(self, X, precision="fp32", rescore=True, hilo=False, want_y=False, stream=None):
+    def locate(self, X, precision="fp32", rescore=True, hilo=False, want_y=False, stream=None, hilo_all=False):
         """X: complex64 CUDA tensor [F, M, N/2+1].  Returns a dict of device
-        tensors doa (int32), power, yhat, margin (f32) and y ([F, Q]) if asked."""
+        tensors doa (int32), power, yhat, margin (f32) and y ([F, Q]) if asked.
+        hilo_all: the hi/lo pass for every frame (16-bit precisions)."""
         import torch
         assert X.is_cuda and X.dtype == torch.complex64 and X.is_contiguous()
         F = X.shape[0]
@@ -250,7 +251,7 @@ class Plan:
         yhat = torch.empty(F, dtype=torch.float32, device=dev)
         margin = torch.empty(F, dtype=torch.float32, device=dev)
         y = torch.empty((F, self.info["Q"]), dtype=torch.float32, device=dev) if want_y else None
-        mode = (RESCORE if rescore else 0) | (HILO if hilo else 0)
+        mode = (RESCORE if rescore else 0) | (HILO if hilo else 0) | (HILO_ALL if hilo_all else 0)
         svdphat_locate(self._h, X, PRECISIONS[precision], mode, doa, power, yhat, margin, y, stream)
         out = dict(doa=doa, power=power, yhat=yhat, margin=margin)
         if want_y:

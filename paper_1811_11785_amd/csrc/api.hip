@@ -261,7 +261,8 @@ int svdphat_locate(svdphat_plan* p, const void* X, int64_t F, int32_t precision,
         SP_REQUIRE(F >= 0 && F < ((int64_t)1 << 31), SVDPHAT_E_INVAL, "F out of range");
         SP_REQUIRE(precision == SVDPHAT_FP32 || precision == SVDPHAT_BF16 || precision == SVDPHAT_FP16,
                    SVDPHAT_E_INVAL, "unknown precision");
-        SP_REQUIRE((mode & ~(uint32_t)(SVDPHAT_RESCORE | SVDPHAT_HILO)) == 0, SVDPHAT_E_INVAL, "unknown mode bits");
+        SP_REQUIRE((mode & ~(uint32_t)(SVDPHAT_RESCORE | SVDPHAT_HILO | SVDPHAT_HILO_ALL)) == 0, SVDPHAT_E_INVAL,
+                   "unknown mode bits");
         if (F == 0) return;
         SP_REQUIRE(X && doa && power, SVDPHAT_E_INVAL, "NULL X, doa or power");
         SP_HIP(hipSetDevice(p->device));

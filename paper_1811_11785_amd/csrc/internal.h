@@ -110,6 +110,7 @@ struct FinalArgs {
     float* yhat;
     float* margin;
     float hilo_k;           // hi/lo trigger: y1 - y2 < hilo_k u ||(U_q1 - U_q2) sigma||
+    int hilo_all;           // every frame into the hi/lo list
     float u;                // unit roundoff of the GEMM1 operands
     int* hlist;
     int* hcount;

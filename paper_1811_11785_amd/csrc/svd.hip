@@ -902,6 +902,7 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
         }
         redo = (y1 - yr) < a.hilo_k * a.u * sqrtf(d2);
     }
+    if (!HILO && a.hlist && !a.flist && a.hilo_all) redo = true;
 
     // ---- round 3 (when the power is not left to k_power): Algorithm 1
     // online step 4, the power of the chosen direction from its row of W
@@ -1223,7 +1224,7 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     G1Sched sc;
     const bool streamed = g1s_sched(prec, p, F, &sc);
     const int zslots = streamed ? sc.slots : nsplit;
-    const bool hilo = (mode & SVDPHAT_HILO) && prec != P_FP32;
+    const bool hilo = (mode & (SVDPHAT_HILO | SVDPHAT_HILO_ALL)) && prec != P_FP32;
     // the hi/lo pass covers few frames: more splits keep the grid busy
     int hsplit = g.nch, hcps = 1;
 
@@ -1331,6 +1332,7 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     fa.yhat = yhat;
     fa.margin = margin;
     fa.hilo_k = 4.f;
+    fa.hilo_all = (mode & SVDPHAT_HILO_ALL) ? 1 : 0;
     fa.u = (float)u;
     fa.hlist = hl;
     fa.hcount = hc;

@@ -124,6 +124,24 @@ def test_locate_tiny(amd, torch, case, prec):
     plan.close()
 
 
+@pytest.mark.parametrize("case", TINY)
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_locate_tiny_hilo_all(amd, torch, case, prec):
+    """Every frame through the hi/lo pass (list GEMM1 and list rescoring),
+    with Rp from 64 to 320: the list rescoring's one-round loads (Rp <= 128)
+    and its general loops (Rp = 320)."""
+    seed, M, N, level, delta, F = case
+    mics, grid, X = _tiny_case(seed, M, N, level, delta, F)
+    print(f"hilo_all case seed={seed} M={M} N={N} F={F} prec={prec}", flush=True)
+    ref_plan = oracle.make_plan(mics, grid, 16000.0, 343.0, N, delta)
+    ref = oracle.locate(ref_plan, X)
+    plan = amd.Plan(mics, grid, 16000.0, 343.0, N, delta)
+    out = plan.locate(_dev(torch, X), precision=prec, rescore=True, hilo_all=True, want_y=True)
+    torch.cuda.synchronize()
+    _check_locate(out, ref, prec, ref_plan.W.shape[1], F)
+    plan.close()
+
+
 @pytest.fixture(scope="module")
 def linear(amd, torch):
     w = synth.workload("linear_q642")

@@ -120,3 +120,34 @@ def test_streamed_large_batch_sampled(amd, torch, planar642):
                power=out["power"][torch.as_tensor(sel, device=X.device)])
     _check(sub, ref, slice(None), "fp16", L)
     del X
+
+
+@pytest.mark.parametrize("N_", [512, 1024])
+def test_hilo_all_planar(amd, torch, N_):
+    """Every frame of a 7-microphone batch through the hi/lo pass.  At N = 512
+    the list rescoring stages the 33 partial slots of a frame in LDS; at
+    N = 1024 (65 slots) it takes the general path.  Against the oracle, and
+    equal to the default pass wherever the oracle's margin judges the frame."""
+    print(f"hilo_all planar N={N_}", flush=True)
+    mics = synth.geometry("2d")
+    grid = synth.icosphere(3)
+    rng = np.random.default_rng(11785400 + N_)
+    F = 130 if N_ == 512 else 70
+    X = np.concatenate([synth.plane_wave_fd(mics, synth.random_direction(rng), 10, N_, FS, C, rng,
+                                            snr_db=rng.uniform(0.0, 20.0)) for _ in range(F // 10)])
+    X = X.astype(np.complex64)
+    X[3] = 0  # silent frame
+    ref_plan = oracle.make_plan(mics, grid, FS, C, N_, 1e-5)
+    ref = oracle.locate(ref_plan, X)
+    plan = amd.Plan(mics, grid, FS, C, N_, 1e-5)
+    L = plan.info["L"]
+    Xd = torch.from_numpy(X).cuda()
+    for prec in ("fp16", "bf16"):
+        out = plan.locate(Xd, precision=prec, rescore=True, hilo_all=True)
+        base = plan.locate(Xd, precision=prec, rescore=True, hilo=True)
+        torch.cuda.synchronize()
+        _check(out, ref, slice(None), prec, L)
+        judged = ref["margin"] > MARGIN_TOL[prec]
+        assert np.array_equal(out["doa"].cpu().numpy()[judged], base["doa"].cpu().numpy()[judged])
+        assert out["power"].cpu().numpy()[3] == 0.0
+    plan.close()
