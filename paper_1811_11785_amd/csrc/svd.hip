@@ -352,9 +352,12 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_zprep16(const float* __restrict__ zpart, int nsplit0, int64_t zstride,
                                                  int64_t nfr, int Rp, float* __restrict__ z32, T* __restrict__ zfrag,
                                                  float* __restrict__ zscale, float* __restrict__ znorm, int scale16,
-                                                 int sG, int64_t sU, int snch) {
+                                                 int sG, int64_t sU, int snch, int* __restrict__ clear = nullptr) {
     constexpr int KS = Mf<T>::KSTEP, EPL = Mf<T>::EPL;
     static_assert(EPL == 8, "16-bit fragment layout");
+    // a word the later kernels of the call count into (the hi/lo list
+    // count), cleared here instead of by a launch of its own
+    if (clear && blockIdx.x == 0 && threadIdx.x == 0) *clear = 0;
     typedef typename Vec<T>::t VT;
     const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
     const int64_t f = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 6) * 4 + g;
@@ -423,7 +426,8 @@ __global__ __launch_bounds__(256) void k_zprep(const float* __restrict__ zpart, 
                                                int64_t nfr, const int* __restrict__ fcount, int Rp,
                                                float* __restrict__ z32, T* __restrict__ zfrag,
                                                float* __restrict__ zscale, float* __restrict__ znorm, int scale16,
-                                               int sG, int64_t sU, int snch) {
+                                               int sG, int64_t sU, int snch, int* __restrict__ clear = nullptr) {
+    if (clear && blockIdx.x == 0 && threadIdx.x == 0) *clear = 0;  // as in k_zprep16
     zprep_body<T>(blockIdx.x, zpart, nsplit, zstride, nfr, fcount, Rp, z32, zfrag, zscale, znorm, scale16, sG, sU,
                   snch);
 }
@@ -1260,7 +1264,7 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     int* hc = hilo ? (int*)(w + o_hc) : nullptr;
     // (the GEMM2 operand's padding frames feed only padding columns, whose
     // results are never written)
-    if (hilo) zero_async(hc, sizeof(int), s);
+    // (hc, the hi/lo list count, is cleared by the Z preparation kernel)
 
     const int64_t zstride = Fc * Rp;
     KernelTimer kt(s);
@@ -1274,14 +1278,14 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
         if (Rp <= 128)
             k_zprep16<T><<<dim3((unsigned)((F + 15) / 16)), 256, 0, s>>>(zpart, zslots, zstride, F, Rp, z32, zfrag, zsc,
                                                                     zn, prec == P_FP16 ? 1 : 0,
-                                                                    streamed ? sc.G : 0, sc.U, sc.nch);
+                                                                    streamed ? sc.G : 0, sc.U, sc.nch, hc);
         else
             k_zprep<T><<<dim3((unsigned)(Fc / 4)), 256, 0, s>>>(zpart, zslots, zstride, F, nullptr, Rp, z32, zfrag,
                                                                 zsc, zn, prec == P_FP16 ? 1 : 0,
-                                                                streamed ? sc.G : 0, sc.U, sc.nch);
+                                                                streamed ? sc.G : 0, sc.U, sc.nch, hc);
     } else {
         k_zprep<T><<<dim3((unsigned)(Fc / 4)), 256, 0, s>>>(zpart, zslots, zstride, F, nullptr, Rp, z32, zfrag, zsc,
-                                                            zn, 0, streamed ? sc.G : 0, sc.U, sc.nch);
+                                                            zn, 0, streamed ? sc.G : 0, sc.U, sc.nch, hc);
     }
     SP_HIP(hipGetLastError());
     kt.end();
