@@ -148,20 +148,19 @@ def _advance(sig: np.ndarray, adv: np.ndarray) -> np.ndarray:
     return np.fft.irfft(S[None, :] * ph, n=T)
 
 
-def plane_wave_td(mics: np.ndarray, dirs, F: int, N: int, hop: int, fs: float,
-                  c: float, rng: np.random.Generator, snr_db=None,
-                  powers_db=None) -> np.ndarray:
-    """STFT frames of white-Gaussian plane-wave source(s) in the time domain.
+def plane_wave_pcm(mics: np.ndarray, dirs, T: int, fs: float, c: float,
+                   rng: np.random.Generator, snr_db=None, powers_db=None) -> np.ndarray:
+    """Microphone signals [M, T] (float64) of white-Gaussian plane-wave
+    source(s): each source advanced by fs r_m . u / c samples per microphone.
 
     ``dirs`` is one unit vector or a list of them (simultaneous independent
     sources).  ``powers_db`` gives each source's power relative to the first.
     If ``snr_db`` is given, independent white Gaussian noise is added to
     every microphone so that (total source variance) / (noise variance)
-    equals that ratio.  Returns complex128 [F, M, N/2+1].
+    equals that ratio.
     """
     dirs = np.atleast_2d(np.asarray(dirs, dtype=np.float64))
     M = mics.shape[0]
-    T = (F - 1) * hop + N
     if powers_db is None:
         powers_db = np.zeros(len(dirs))
     sig = np.zeros((M, T))
@@ -175,7 +174,15 @@ def plane_wave_td(mics: np.ndarray, dirs, F: int, N: int, hop: int, fs: float,
     if snr_db is not None:
         nvar = total_var / (10.0 ** (snr_db / 10.0))
         sig += np.sqrt(nvar) * rng.standard_normal((M, T))
-    return stft(sig, N, hop)
+    return sig
+
+
+def plane_wave_td(mics: np.ndarray, dirs, F: int, N: int, hop: int, fs: float,
+                  c: float, rng: np.random.Generator, snr_db=None,
+                  powers_db=None) -> np.ndarray:
+    """STFT frames of the signals of ``plane_wave_pcm`` over (F - 1) hop + N
+    samples.  Returns complex128 [F, M, N/2+1]."""
+    return stft(plane_wave_pcm(mics, dirs, (F - 1) * hop + N, fs, c, rng, snr_db, powers_db), N, hop)
 
 
 def plane_wave_fd(mics: np.ndarray, u: np.ndarray, F: int, N: int, fs: float,

@@ -352,3 +352,63 @@ def test_coarse_cells_nesting():
     for q in range(0, fine.shape[0], 97):
         ang = np.arccos(np.clip(coarse @ fine[q], -1, 1))
         assert ang[cell[q]] <= ang.min() + 1e-9
+
+
+# ------------------------------------------------------------ STFT front end
+def _geom_sum(alpha, N):
+    """sum_{n<N} exp(i alpha n), closed form (alpha not a multiple of 2 pi)."""
+    return (1 - np.exp(1j * alpha * N)) / (1 - np.exp(1j * alpha))
+
+
+@pytest.mark.parametrize("N,hop,k0", [(512, 256, 37.3), (64, 16, 5.0), (16, 8, 2.71)])
+def test_stft_tone_closed_form(N, hop, k0):
+    """A cosine A cos(theta t + phi) (on or off a bin) through the sine
+    window: writing w[n] = (e^{i pi n/N} - e^{-i pi n/N}) / 2i makes every
+    bin a sum of four geometric series, in closed form, frame by frame."""
+    A, phi, F = 1.7, 0.4, 5
+    theta = 2 * np.pi * k0 / N
+    T = (F - 1) * hop + N
+    pcm = (A * np.cos(theta * np.arange(T) + phi))[None, :]
+    X = oracle.stft(pcm, N, hop)[:, 0, :]
+    k = np.arange(N // 2 + 1)
+    for f in range(F):
+        pf = phi + theta * f * hop
+        b = 2 * np.pi * k / N
+        s = lambda a: _geom_sum(a, N)
+        ref = A / (4j) * (np.exp(1j * pf) * (s(theta + np.pi / N - b) - s(theta - np.pi / N - b))
+                          + np.exp(-1j * pf) * (s(-theta + np.pi / N - b) - s(-theta - np.pi / N - b)))
+        assert np.abs(X[f] - ref).max() <= 1e-9 * N
+
+
+def test_stft_brute_force_tiny():
+    """Tiny case against the double sum written with math.cos / math.sin."""
+    rng = np.random.default_rng(4)
+    N, hop, M, T = 8, 3, 2, 20
+    pcm = rng.standard_normal((M, T))
+    X = oracle.stft(pcm, N, hop)
+    F = 1 + (T - N) // hop
+    assert X.shape == (F, M, N // 2 + 1)
+    for f in range(F):
+        for m in range(M):
+            for k in range(N // 2 + 1):
+                re = im = 0.0
+                for n in range(N):
+                    v = math.sin(math.pi * n / N) * pcm[m, f * hop + n]
+                    re += v * math.cos(2 * math.pi * k * n / N)
+                    im -= v * math.sin(2 * math.pi * k * n / N)
+                assert abs(X[f, m, k] - complex(re, im)) < 1e-12
+
+
+def test_stft_frames_and_shift():
+    """Frame count 1 + (T - N) // hop (0 below one frame), and shifting the
+    signal by one hop shifts the frames by one."""
+    assert oracle.stft_frames(15, 16, 8) == 0
+    assert oracle.stft_frames(16, 16, 8) == 1
+    assert oracle.stft_frames(23, 16, 8) == 1
+    assert oracle.stft_frames(24, 16, 8) == 2
+    assert oracle.stft(np.zeros((3, 10)), 16, 8).shape == (0, 3, 9)
+    rng = np.random.default_rng(8)
+    pcm = rng.standard_normal((3, 200))
+    X = oracle.stft(pcm, 32, 12)
+    Xs = oracle.stft(pcm[:, 12:], 32, 12)
+    assert np.allclose(X[1:1 + Xs.shape[0]], Xs, rtol=0, atol=1e-12)
