@@ -259,6 +259,33 @@ const char* svdphat_last_error(void);
 /* svdphat_sync -- waits for the stream and reports any pending device error. */
 int svdphat_sync(void* stream);
 
+/* ---- STFT front end ---------------------------------------------------- */
+/*
+ * svdphat_stft_frames -- number of whole frames in T samples:
+ * 1 + (T - N) / hop, or 0 when T < N; -1 for T < 0, N < 1 or hop < 1.
+ */
+int64_t svdphat_stft_frames(int64_t T, int32_t N, int32_t hop);
+
+/*
+ * svdphat_stft -- the short-time Fourier transform that Section 2 applies to
+ * each microphone signal before the PHAT (frames of N samples, sine window),
+ * on the GPU, writing the STFT frames svdphat_locate reads:
+ *   X[f][m][k] = sum_{n<N} w[n] pcm[m][f hop + n] exp(-2 pi i k n / N),
+ *   w[n] = sin(pi n / N), k = 0 .. N/2, f < F = svdphat_stft_frames(T, N, hop).
+ *   pcm    device, f32: microphone m's T samples at pcm + m * ld.
+ *   M      microphones, >= 1.
+ *   T      samples per microphone, >= 0;  ld >= T the microphone stride.
+ *   N      frame size: a power of two, 16 <= N <= 2048.
+ *   hop    samples between frame starts, >= 1.
+ *   X      device, complex64 [F][M][N/2+1], written (owned by the caller).
+ *   stream hipStream_t or NULL; asynchronous.  The current HIP device runs it.
+ * FP32 arithmetic (twiddles and window evaluated in FP64, rounded to FP32).
+ * F = 0 is a no-op.  Errors: E_INVAL (M < 1, T < 0, ld < T, hop < 1, NULL
+ * pointers with F > 0), E_UNSUPPORTED (N), E_NODEV, E_DEVICE.
+ */
+int svdphat_stft(const float* pcm, int32_t M, int64_t T, int64_t ld,
+                 int32_t N, int32_t hop, void* X, void* stream);
+
 /*
  * Per-kernel timing (instrumentation, not part of the method).
  * svdphat_timing_enable(enable): bit 0 brackets every kernel that the

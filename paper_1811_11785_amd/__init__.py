@@ -63,6 +63,9 @@ SIGNATURES = {
                                      C.c_void_p, C.c_void_p]),
     "svdphat_plan_destroy": (None, [C.c_void_p]),
     "svdphat_sync": (C.c_int, [C.c_void_p]),
+    "svdphat_stft_frames": (C.c_int64, [C.c_int64, C.c_int32, C.c_int32]),
+    "svdphat_stft": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_void_p,
+                               C.c_void_p]),
     "svdphat_ragged_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_int64),
                                         C.c_uint32, C.c_char_p, C.POINTER(C.c_void_p)]),
     "svdphat_ragged_locate": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
@@ -169,6 +172,31 @@ def svdphat_plan_destroy(plan):
 
 def svdphat_sync(stream=None):
     _check(lib().svdphat_sync(_stream(stream)))
+
+
+def svdphat_stft(pcm, N, hop, X, stream=None):
+    """pcm: float32 CUDA tensor [M, T] (row stride ld = pcm.stride(0));
+    X: complex64 CUDA tensor [F, M, N/2+1] with F = stft_frames(T, N, hop)."""
+    M, T = pcm.shape
+    assert pcm.stride(1) == 1
+    _check(lib().svdphat_stft(_ptr(pcm), M, T, pcm.stride(0), N, hop, _ptr(X), _stream(stream)))
+
+
+def stft_frames(T, N, hop):
+    return lib().svdphat_stft_frames(T, N, hop)
+
+
+def stft(pcm, N=512, hop=256, stream=None):
+    """STFT frames [F, M, N/2+1] (complex64, on pcm's device) of the
+    microphone signals pcm [M, T] (float32 CUDA tensor), sine window."""
+    import torch
+    assert pcm.is_cuda and pcm.dtype == torch.float32
+    F = stft_frames(pcm.shape[1], N, hop)
+    if F < 0:
+        raise SvdphatError(E_INVAL, "invalid STFT sizes")
+    X = torch.empty((F, pcm.shape[0], N // 2 + 1), dtype=torch.complex64, device=pcm.device)
+    svdphat_stft(pcm, N, hop, X, stream)
+    return X
 
 
 def svdphat_timing_enable(enable, counts: bool = False):

@@ -447,6 +447,29 @@ int svdphat_timing_read(int32_t index, char* name, int32_t name_len, double* tot
     });
 }
 
+int64_t svdphat_stft_frames(int64_t T, int32_t N, int32_t hop) {
+    if (T < 0 || N < 1 || hop < 1) return -1;
+    return T < N ? 0 : 1 + (T - N) / hop;
+}
+
+int svdphat_stft(const float* pcm, int32_t M, int64_t T, int64_t ld, int32_t N, int32_t hop, void* X,
+                 void* stream) {
+    return guarded([&] {
+        SP_REQUIRE(M >= 1 && T >= 0 && ld >= T && hop >= 1, SVDPHAT_E_INVAL, "need M >= 1, 0 <= T <= ld, hop >= 1");
+        SP_REQUIRE(N >= 16 && N <= 2048 && (N & (N - 1)) == 0, SVDPHAT_E_UNSUPPORTED,
+                   "N must be a power of two in [16, 2048]");
+        const int64_t F = svdphat_stft_frames(T, N, hop);
+        SP_REQUIRE(F * M < ((int64_t)1 << 40), SVDPHAT_E_INVAL, "too many frames");
+        if (F == 0) return;
+        SP_REQUIRE(pcm && X, SVDPHAT_E_INVAL, "NULL pcm or X");
+        require_device();
+        int dev = 0;
+        SP_HIP(hipGetDevice(&dev));
+        launch_stft(pcm, M, ld, N, hop, (float2*)X, F, dev, (hipStream_t)stream);
+        SP_HIP(hipGetLastError());
+    });
+}
+
 int svdphat_sync(void* stream) {
     return guarded([&] {
         require_device();

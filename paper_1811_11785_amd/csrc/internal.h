@@ -281,6 +281,10 @@ void* ws_get(svdphat_plan* p, hipStream_t s, size_t bytes);
 // zero `bytes` (a multiple of 4) of device memory on stream s with a kernel,
 // so that a caller capturing the stream into a graph records a kernel node
 void zero_async(void* p, size_t bytes, hipStream_t s);
+// STFT front end (stft.hip): F frames of M signals into X [F][M][N/2+1]
+size_t stft_lds_bytes(int N);
+void launch_stft(const float* pcm, int M, int64_t ld, int N, int hop, float2* X, int64_t F, int device,
+                 hipStream_t s);
 svdphat_ragged* ragged_new(svdphat_plan* const* plans, int n, const int64_t* maxF);
 void ragged_build(svdphat_ragged* r, uint32_t flags, const char* cache_path);
 void ragged_locate(svdphat_ragged* r, const void* const* X, const int64_t* F, int32_t* const* doa,

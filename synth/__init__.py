@@ -273,6 +273,31 @@ def workload(name: str, frames: int | None = None, seed_offset: int = 0):
                 delta=1e-5, **STFT)
 
 
+def workload_pcm(name: str, frames: int | None = None) -> np.ndarray:
+    """Microphone signals standing in for the named workload in the time
+    domain: float32 [M, T] with T = F hop + (N - hop), so that exactly F
+    frames fit.  The signal is a concatenation of 100-frame segments (100 hop
+    samples each), each a plane wave from its own uniformly random direction
+    at SNR U[0, 20] dB, as in ``segments`` (own seed stream: the workload's
+    seed + 100)."""
+    spec = {"planar_q10242": dict(geo="2d", frames=20000, num=2),
+            "linear_q642": dict(geo="1d", frames=200, num=1)}[name]
+    F = spec["frames"] if frames is None else frames
+    N, hop = STFT["N"], STFT["hop"]
+    rng = np.random.default_rng(SEED0 + spec["num"] + 100)
+    mics = geometry(spec["geo"])
+    seg = 100
+    parts = []
+    for _ in range(max(1, -(-F // seg))):
+        u = random_direction(rng)
+        parts.append(plane_wave_pcm(mics, [u], seg * hop, STFT["fs"], STFT["c"], rng,
+                                    snr_db=rng.uniform(0.0, 20.0)))
+    tail = plane_wave_pcm(mics, [random_direction(rng)], N - hop, STFT["fs"], STFT["c"], rng,
+                          snr_db=rng.uniform(0.0, 20.0))
+    sig = np.concatenate(parts + [tail], axis=1)[:, :F * hop + N - hop]
+    return np.ascontiguousarray(sig.astype(np.float32))
+
+
 def ragged_workload(n_arrays: int = 256, seed_offset: int = 0, frames_range=(64, 1024),
                     levels=(3, 4, 5)):
     """Many independent arrays: M ~ U{4..16} microphones at random positions

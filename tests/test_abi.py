@@ -87,3 +87,16 @@ def test_no_device_reported():
     with pytest.raises(amd.SvdphatError) as e:
         amd.svdphat_plan_create(mics, np.eye(3), 16000.0, 343.0, 32, 1e-5)
     assert e.value.code == amd.E_NODEV
+
+
+def test_stft_validation_without_gpu():
+    """Frame counting and the STFT's argument checks happen before any device
+    call; F = 0 is a no-op."""
+    L = amd.lib()
+    assert L.svdphat_stft_frames(1000, 512, 256) == 2
+    assert L.svdphat_stft_frames(511, 512, 256) == 0
+    assert L.svdphat_stft_frames(-1, 512, 256) == -1
+    assert L.svdphat_stft(None, 7, 1000, 1000, 500, 250, None, None) == amd.E_UNSUPPORTED
+    assert L.svdphat_stft(None, 0, 1000, 1000, 512, 256, None, None) == amd.E_INVAL
+    assert L.svdphat_stft(None, 7, 1000, 999, 512, 256, None, None) == amd.E_INVAL
+    assert L.svdphat_stft(None, 7, 100, 100, 512, 256, None, None) == amd.OK
