@@ -181,6 +181,34 @@ def main():
     srp_doa = doa.cpu().numpy()
     log(f"plain fp32 srp: {srp_fps:.4g} frames/s")
 
+    # STFT front end on the same number of frames of microphone samples
+    # (HIP events on the launch stream, which is torch's current stream), and
+    # the whole path from samples: STFT, then the FP16 search
+    pcm = torch.from_numpy(synth.workload_pcm("planar_q10242", F)).cuda()
+    Tm = pcm.shape[1]
+    Xs = torch.empty((F, info["M"], info["B"]), dtype=torch.complex64, device=dev)
+    st = lambda: amd.svdphat_stft(pcm, info["N"], info["N"] // 2, Xs)
+    _timed(st, 2, torch)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        st()
+    e1.record()
+    torch.cuda.synchronize()
+    stft_us = 1e3 * e0.elapsed_time(e1) / args.steps
+    prec16, mode16 = forms["fp16"]
+    e2e = lambda: (st(), amd.svdphat_locate(h, Xs, prec16, mode16, doa, power, yhat, margin))
+    _timed(e2e, 2, torch)
+    dt = _timed(e2e, args.steps, torch)
+    stft_bytes = info["M"] * Tm * 4 + F * info["M"] * info["B"] * 8
+    stft = dict(kernel="k_stft", us_per_launch=stft_us, frames_per_s=F / (stft_us * 1e-6),
+                algorithmic_bytes=stft_bytes, achieved_GBps=stft_bytes / (stft_us * 1e-6) / 1e9,
+                peak_GBps=HBM_PEAK_GBS, frac=stft_bytes / (stft_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                end_to_end_fps=F * args.steps / dt, end_to_end_ms_per_step=1e3 * dt / args.steps,
+                samples_per_mic=Tm)
+    log(f"stft: {stft_us:.1f} us per {F} frames; samples -> directions {stft['end_to_end_fps']:.4g} frames/s")
+    del pcm, Xs
+
     # per-kernel durations with HIP events on the launch stream (same work)
     amd.svdphat_timing_reset()
     amd.svdphat_timing_enable(True)
@@ -272,6 +300,7 @@ def main():
         "kernels_us": kernels,
         "kernels_srp_us": kernels_srp,
         "per_frame_counts": counts,
+        "stft_front_end": stft,
         "plan_build_s": plan_s,
     }
     if cpu is not None:

@@ -6,8 +6,9 @@
 //
 // One wave per (frame, microphone), grid-stride over the F M pairs.  The N
 // windowed real samples are taken as N/2 complex points z[n] = x[2n] +
-// i x[2n+1]; their FFT (radix-2 Stockham, natural order, in the wave's two
-// LDS buffers) gives the N/2+1 real-input bins by the even/odd split
+// i x[2n+1]; their FFT (Stockham radix-4 stages and at most one radix-2
+// stage, natural order, in the wave's two LDS buffers) gives the N/2+1
+// real-input bins by the even/odd split
 //   X[k] = (Z[k] + conj Z[N/2-k]) / 2 + e^{-2 pi i k / N} (Z[k] - conj Z[N/2-k]) / 2i.
 // The twiddles and the window are evaluated once per workgroup in FP64 and
 // kept in LDS as FP32.  All arithmetic is FP32.
@@ -19,9 +20,17 @@ namespace {
 
 constexpr int STFT_WAVES = 4;  // waves (pairs in flight) per workgroup
 
-__global__ __launch_bounds__(256) void k_stft(const float* __restrict__ pcm, int M, int64_t ld, int N, int hop,
+__device__ __forceinline__ float2 cmul(float2 u, float2 w) {
+    return float2{u.x * w.x - u.y * w.y, u.x * w.y + u.y * w.x};
+}
+
+// NL = max(1, N / 64) samples per lane; NC = N where it is fixed by NL
+// (N >= 64), so the stages unroll, else 0 (N from the argument)
+template <int NL, int NC>
+__global__ __launch_bounds__(256) void k_stft(const float* __restrict__ pcm, int M, int64_t ld, int Nrt, int hop,
                                               float2* __restrict__ X, int64_t npair) {
     extern __shared__ __align__(16) char smem[];
+    const int N = NC > 0 ? NC : Nrt;
     const int N2 = N / 2, B = N2 + 1;
     float2* tw1 = reinterpret_cast<float2*>(smem);  // e^{-2 pi i j / N2}, j < N2
     float2* tw2 = tw1 + N2;                          // e^{-2 pi i k / N}, k <= N2
@@ -45,29 +54,64 @@ __global__ __launch_bounds__(256) void k_stft(const float* __restrict__ pcm, int
     float2* b1 = b0 + N2;
     float* b0f = reinterpret_cast<float*>(b0);
     const int64_t step = (int64_t)gridDim.x * STFT_WAVES;
-    for (int64_t pr = (int64_t)blockIdx.x * STFT_WAVES + wave; pr < npair; pr += step) {
+    // the samples of the wave's next pair are loaded into registers while
+    // the current pair's transform runs (sample n = lane + 64 i; lanes past
+    // N re-read sample N - 1 and are not used)
+    float xs[NL];
+    auto fetch = [&](int64_t pr) {
         const int64_t f = pr / M;
         const int m = (int)(pr - f * M);
         const float* src = pcm + (int64_t)m * ld + f * hop;
+#pragma unroll
+        for (int i = 0; i < NL; ++i) xs[i] = src[min(lane + 64 * i, N - 1)];
+    };
+    int64_t pr = (int64_t)blockIdx.x * STFT_WAVES + wave;
+    if (pr < npair) fetch(pr);
+    for (; pr < npair; pr += step) {
         wave_sync();  // the previous pair's reads of the buffers are done
         // windowed samples, read as z[n] = x[2n] + i x[2n+1]
-        for (int n = lane; n < N; n += 64) b0f[n] = win[n] * src[n];
+#pragma unroll
+        for (int i = 0; i < NL; ++i)
+            if (lane + 64 * i < N) b0f[lane + 64 * i] = win[lane + 64 * i] * xs[i];
         wave_sync();
+        if (pr + step < npair) fetch(pr + step);
         float2* a = b0;
         float2* b = b1;
-        for (int Ns = 1; Ns < N2; Ns <<= 1) {
-            // butterflies t of span Ns: inputs t and t + N2/2, twiddle
-            // e^{-2 pi i (t mod Ns) / (2 Ns)}, outputs 2 (t - t mod Ns) + t mod Ns
-            // and that + Ns
-            const int ts = N2 / (2 * Ns);
-            for (int t = lane; t < N2 / 2; t += 64) {
-                const int k = t & (Ns - 1);
-                const float2 w = tw1[k * ts];
-                const float2 v0 = a[t], u = a[t + N2 / 2];
-                const float2 v1 = float2{u.x * w.x - u.y * w.y, u.x * w.y + u.y * w.x};
-                const int idx = ((t - k) << 1) + k;
-                b[idx] = float2{v0.x + v1.x, v0.y + v1.y};
-                b[idx + Ns] = float2{v0.x - v1.x, v0.y - v1.y};
+        // radix-4 stages while four spans fit, then one radix-2 stage if
+        // log2(N/2) is odd.  Butterfly j of span Ns takes inputs j + r N2/R,
+        // multiplies input r by e^{-2 pi i r (j mod Ns) / (R Ns)}, and writes
+        // the R-point DFT to R (j - j mod Ns) + j mod Ns + r Ns
+#pragma unroll
+        for (int Ns = 1; Ns < N2;) {
+            if (Ns * 4 <= N2) {
+                const int Q = N2 / 4, ts = N2 / (4 * Ns);
+#pragma unroll
+                for (int j = lane; j < Q; j += 64) {
+                    const int k = j & (Ns - 1);
+                    const float2 v0 = a[j];
+                    const float2 v1 = cmul(a[j + Q], tw1[k * ts]);
+                    const float2 v2 = cmul(a[j + 2 * Q], tw1[2 * k * ts]);
+                    const float2 v3 = cmul(a[j + 3 * Q], tw1[3 * k * ts]);
+                    const float2 s02 = float2{v0.x + v2.x, v0.y + v2.y}, d02 = float2{v0.x - v2.x, v0.y - v2.y};
+                    const float2 s13 = float2{v1.x + v3.x, v1.y + v3.y}, d13 = float2{v1.x - v3.x, v1.y - v3.y};
+                    const int idx = ((j - k) << 2) + k;
+                    b[idx] = float2{s02.x + s13.x, s02.y + s13.y};
+                    b[idx + Ns] = float2{d02.x + d13.y, d02.y - d13.x};  // d02 - i d13
+                    b[idx + 2 * Ns] = float2{s02.x - s13.x, s02.y - s13.y};
+                    b[idx + 3 * Ns] = float2{d02.x - d13.y, d02.y + d13.x};  // d02 + i d13
+                }
+                Ns *= 4;
+            } else {
+                const int ts = N2 / (2 * Ns);
+#pragma unroll
+                for (int t = lane; t < N2 / 2; t += 64) {
+                    const int k = t & (Ns - 1);
+                    const float2 v0 = a[t], v1 = cmul(a[t + N2 / 2], tw1[k * ts]);
+                    const int idx = ((t - k) << 1) + k;
+                    b[idx] = float2{v0.x + v1.x, v0.y + v1.y};
+                    b[idx + Ns] = float2{v0.x - v1.x, v0.y - v1.y};
+                }
+                Ns *= 2;
             }
             wave_sync();
             float2* tmp = a;
@@ -99,9 +143,20 @@ void launch_stft(const float* pcm, int M, int64_t ld, int N, int hop, float2* X,
                  hipStream_t s) {
     const int64_t npair = F * M;
     const int64_t want = (npair + STFT_WAVES - 1) / STFT_WAVES;
-    const int64_t cap = (int64_t)cu_count(device) * 6;
+    // as many workgroups as the LDS lets one CU hold
+    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)(160 * 1024) / (int64_t)stft_lds_bytes(N)));
+    const int64_t cap = (int64_t)cu_count(device) * per_cu;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min(want, cap));
-    k_stft<<<grid, 64 * STFT_WAVES, stft_lds_bytes(N), s>>>(pcm, M, ld, N, hop, X, npair);
+    const size_t lds = stft_lds_bytes(N);
+    switch (N) {
+        case 16: case 32: k_stft<1, 0><<<grid, 64 * STFT_WAVES, lds, s>>>(pcm, M, ld, N, hop, X, npair); break;
+        case 64: k_stft<1, 64><<<grid, 64 * STFT_WAVES, lds, s>>>(pcm, M, ld, N, hop, X, npair); break;
+        case 128: k_stft<2, 128><<<grid, 64 * STFT_WAVES, lds, s>>>(pcm, M, ld, N, hop, X, npair); break;
+        case 256: k_stft<4, 256><<<grid, 64 * STFT_WAVES, lds, s>>>(pcm, M, ld, N, hop, X, npair); break;
+        case 512: k_stft<8, 512><<<grid, 64 * STFT_WAVES, lds, s>>>(pcm, M, ld, N, hop, X, npair); break;
+        case 1024: k_stft<16, 1024><<<grid, 64 * STFT_WAVES, lds, s>>>(pcm, M, ld, N, hop, X, npair); break;
+        default: k_stft<32, 2048><<<grid, 64 * STFT_WAVES, lds, s>>>(pcm, M, ld, N, hop, X, npair); break;
+    }
 }
 
 }  // namespace svdphat
