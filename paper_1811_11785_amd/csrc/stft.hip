@@ -20,6 +20,8 @@ namespace {
 
 constexpr int STFT_WAVES = 4;  // waves (pairs in flight) per workgroup
 
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
+
 __device__ __forceinline__ float2 cmul(float2 u, float2 w) {
     return float2{u.x * w.x - u.y * w.y, u.x * w.y + u.y * w.x};
 }
@@ -65,6 +67,19 @@ __global__ __launch_bounds__(256) void k_stft(const float* __restrict__ pcm, int
 #pragma unroll
         for (int i = 0; i < NL; ++i) xs[i] = src[min(lane + 64 * i, N - 1)];
     };
+    // a pair's bins k = lane + 64 i stay in registers until the next pair's
+    // samples are in LDS; their stores then go out before the next prefetch,
+    // so they drain during a whole transform (vector stores count in the same
+    // in-order counter as the loads)
+    constexpr int KO = NC > 0 ? (NC / 2 + 64) / 64 : 1;
+    float2 xo[KO];
+    int64_t opr = -1;  // pair whose bins are in xo
+    auto store = [&]() {
+        float2* out = X + opr * B;  // pair index f M + m is the row of X
+#pragma unroll
+        for (int i = 0; i < KO; ++i)
+            if (lane + 64 * i <= N2) out[lane + 64 * i] = xo[i];
+    };
     int64_t pr = (int64_t)blockIdx.x * STFT_WAVES + wave;
     if (pr < npair) fetch(pr);
     for (; pr < npair; pr += step) {
@@ -74,6 +89,7 @@ __global__ __launch_bounds__(256) void k_stft(const float* __restrict__ pcm, int
         for (int i = 0; i < NL; ++i)
             if (lane + 64 * i < N) b0f[lane + 64 * i] = win[lane + 64 * i] * xs[i];
         wave_sync();
+        if (opr >= 0) store();
         if (pr + step < npair) fetch(pr + step);
         float2* a = b0;
         float2* b = b1;
@@ -81,54 +97,60 @@ __global__ __launch_bounds__(256) void k_stft(const float* __restrict__ pcm, int
         // log2(N/2) is odd.  Butterfly j of span Ns takes inputs j + r N2/R,
         // multiplies input r by e^{-2 pi i r (j mod Ns) / (R Ns)}, and writes
         // the R-point DFT to R (j - j mod Ns) + j mod Ns + r Ns
+        const int lg = NC > 0 ? ilog2c(NC / 2) : 31 - __builtin_clz(N2);
+        int Ns = 1;
 #pragma unroll
-        for (int Ns = 1; Ns < N2;) {
-            if (Ns * 4 <= N2) {
-                const int Q = N2 / 4, ts = N2 / (4 * Ns);
+        for (int r4 = 0; r4 < lg / 2; ++r4, Ns *= 4) {
+            const int Q = N2 / 4, ts = N2 / (4 * Ns);
 #pragma unroll
-                for (int j = lane; j < Q; j += 64) {
-                    const int k = j & (Ns - 1);
-                    const float2 v0 = a[j];
-                    const float2 v1 = cmul(a[j + Q], tw1[k * ts]);
-                    const float2 v2 = cmul(a[j + 2 * Q], tw1[2 * k * ts]);
-                    const float2 v3 = cmul(a[j + 3 * Q], tw1[3 * k * ts]);
-                    const float2 s02 = float2{v0.x + v2.x, v0.y + v2.y}, d02 = float2{v0.x - v2.x, v0.y - v2.y};
-                    const float2 s13 = float2{v1.x + v3.x, v1.y + v3.y}, d13 = float2{v1.x - v3.x, v1.y - v3.y};
-                    const int idx = ((j - k) << 2) + k;
-                    b[idx] = float2{s02.x + s13.x, s02.y + s13.y};
-                    b[idx + Ns] = float2{d02.x + d13.y, d02.y - d13.x};  // d02 - i d13
-                    b[idx + 2 * Ns] = float2{s02.x - s13.x, s02.y - s13.y};
-                    b[idx + 3 * Ns] = float2{d02.x - d13.y, d02.y + d13.x};  // d02 + i d13
-                }
-                Ns *= 4;
-            } else {
-                const int ts = N2 / (2 * Ns);
-#pragma unroll
-                for (int t = lane; t < N2 / 2; t += 64) {
-                    const int k = t & (Ns - 1);
-                    const float2 v0 = a[t], v1 = cmul(a[t + N2 / 2], tw1[k * ts]);
-                    const int idx = ((t - k) << 1) + k;
-                    b[idx] = float2{v0.x + v1.x, v0.y + v1.y};
-                    b[idx + Ns] = float2{v0.x - v1.x, v0.y - v1.y};
-                }
-                Ns *= 2;
+            for (int j = lane; j < Q; j += 64) {
+                const int k = j & (Ns - 1);
+                const float2 v0 = a[j];
+                const float2 v1 = cmul(a[j + Q], tw1[k * ts]);
+                const float2 v2 = cmul(a[j + 2 * Q], tw1[2 * k * ts]);
+                const float2 v3 = cmul(a[j + 3 * Q], tw1[3 * k * ts]);
+                const float2 s02 = float2{v0.x + v2.x, v0.y + v2.y}, d02 = float2{v0.x - v2.x, v0.y - v2.y};
+                const float2 s13 = float2{v1.x + v3.x, v1.y + v3.y}, d13 = float2{v1.x - v3.x, v1.y - v3.y};
+                const int idx = ((j - k) << 2) + k;
+                b[idx] = float2{s02.x + s13.x, s02.y + s13.y};
+                b[idx + Ns] = float2{d02.x + d13.y, d02.y - d13.x};  // d02 - i d13
+                b[idx + 2 * Ns] = float2{s02.x - s13.x, s02.y - s13.y};
+                b[idx + 3 * Ns] = float2{d02.x - d13.y, d02.y + d13.x};  // d02 + i d13
             }
             wave_sync();
             float2* tmp = a;
             a = b;
             b = tmp;
         }
-        // even/odd split into the real-input bins; pair index f M + m is the
-        // row of X
-        float2* out = X + pr * B;
-        for (int k = lane; k <= N2; k += 64) {
+        if (lg & 1) {
+            const int ts = N2 / (2 * Ns);
+#pragma unroll
+            for (int t = lane; t < N2 / 2; t += 64) {
+                const int k = t & (Ns - 1);
+                const float2 v0 = a[t], v1 = cmul(a[t + N2 / 2], tw1[k * ts]);
+                const int idx = ((t - k) << 1) + k;
+                b[idx] = float2{v0.x + v1.x, v0.y + v1.y};
+                b[idx + Ns] = float2{v0.x - v1.x, v0.y - v1.y};
+            }
+            wave_sync();
+            float2* tmp = a;
+            a = b;
+            b = tmp;
+        }
+        // even/odd split into the real-input bins (lanes past bin N/2 compute
+        // bin N/2 again; it is not stored)
+#pragma unroll
+        for (int i = 0; i < KO; ++i) {
+            const int k = min(lane + 64 * i, N2);
             const float2 zk = a[k & (N2 - 1)], zn = a[(N2 - k) & (N2 - 1)];
             const float er = 0.5f * (zk.x + zn.x), ei = 0.5f * (zk.y - zn.y);   // (Z[k] + conj Z[N2-k]) / 2
             const float orr = 0.5f * (zk.y + zn.y), oi = -0.5f * (zk.x - zn.x);  // (Z[k] - conj Z[N2-k]) / 2i
             const float2 w = tw2[k];
-            out[k] = float2{er + w.x * orr - w.y * oi, ei + w.x * oi + w.y * orr};
+            xo[i] = float2{er + w.x * orr - w.y * oi, ei + w.x * oi + w.y * orr};
         }
+        opr = pr;
     }
+    if (opr >= 0) store();
 }
 
 }  // namespace
