@@ -60,13 +60,28 @@ __global__ __launch_bounds__(256) void k_stft(const float* __restrict__ pcm, int
     // the current pair's transform runs (sample n = lane + 64 i; lanes past
     // N re-read sample N - 1 and are not used)
     float xs[NL];
-    auto fetch = [&](int64_t pr) {
-        const int64_t f = pr / M;
-        const int m = (int)(pr - f * M);
-        const float* src = pcm + (int64_t)m * ld + f * hop;
+    // (frame, microphone) of the pair to fetch, moved by the grid stride
+    // without a division per pair
+    const int64_t pr0 = (int64_t)blockIdx.x * STFT_WAVES + wave;
+    int64_t ff = pr0 / M;
+    int fm = (int)(pr0 - ff * M);
+    const int64_t sf = step / M;
+    const int sm = (int)(step - sf * M);
+    auto fetch = [&]() {
+        const float* src = pcm + (int64_t)fm * ld + ff * hop;
 #pragma unroll
         for (int i = 0; i < NL; ++i) xs[i] = src[min(lane + 64 * i, N - 1)];
+        ff += sf;
+        fm += sm;
+        if (fm >= M) {
+            fm -= M;
+            ++ff;
+        }
     };
+    // the lane's window values and split twiddles stay in registers
+    float wr[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) wr[i] = win[min(lane + 64 * i, N - 1)];
     // a pair's bins k = lane + 64 i stay in registers until the next pair's
     // samples are in LDS; their stores then go out before the next prefetch,
     // so they drain during a whole transform (vector stores count in the same
@@ -80,17 +95,20 @@ __global__ __launch_bounds__(256) void k_stft(const float* __restrict__ pcm, int
         for (int i = 0; i < KO; ++i)
             if (lane + 64 * i <= N2) out[lane + 64 * i] = xo[i];
     };
-    int64_t pr = (int64_t)blockIdx.x * STFT_WAVES + wave;
-    if (pr < npair) fetch(pr);
+    float2 w2r[KO];
+#pragma unroll
+    for (int i = 0; i < KO; ++i) w2r[i] = tw2[min(lane + 64 * i, N2)];
+    int64_t pr = pr0;
+    if (pr < npair) fetch();
     for (; pr < npair; pr += step) {
         wave_sync();  // the previous pair's reads of the buffers are done
         // windowed samples, read as z[n] = x[2n] + i x[2n+1]
 #pragma unroll
         for (int i = 0; i < NL; ++i)
-            if (lane + 64 * i < N) b0f[lane + 64 * i] = win[lane + 64 * i] * xs[i];
+            if (lane + 64 * i < N) b0f[lane + 64 * i] = wr[i] * xs[i];
         wave_sync();
         if (opr >= 0) store();
-        if (pr + step < npair) fetch(pr + step);
+        if (pr + step < npair) fetch();
         float2* a = b0;
         float2* b = b1;
         // radix-4 stages while four spans fit, then one radix-2 stage if
@@ -145,7 +163,7 @@ __global__ __launch_bounds__(256) void k_stft(const float* __restrict__ pcm, int
             const float2 zk = a[k & (N2 - 1)], zn = a[(N2 - k) & (N2 - 1)];
             const float er = 0.5f * (zk.x + zn.x), ei = 0.5f * (zk.y - zn.y);   // (Z[k] + conj Z[N2-k]) / 2
             const float orr = 0.5f * (zk.y + zn.y), oi = -0.5f * (zk.x - zn.x);  // (Z[k] - conj Z[N2-k]) / 2i
-            const float2 w = tw2[k];
+            const float2 w = w2r[i];
             xo[i] = float2{er + w.x * orr - w.y * oi, ei + w.x * oi + w.y * orr};
         }
         opr = pr;
