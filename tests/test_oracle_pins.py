@@ -412,3 +412,43 @@ def test_stft_frames_and_shift():
     X = oracle.stft(pcm, 32, 12)
     Xs = oracle.stft(pcm[:, 12:], 32, 12)
     assert np.allclose(X[1:1 + Xs.shape[0]], Xs, rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------- error measure, eq. (20)
+def test_doa_maps():
+    """f_1 keeps only the elevation (unit vectors in the x-z half plane,
+    the same for every azimuth); f_2 folds z; f_3 is the identity."""
+    rng = np.random.default_rng(12)
+    s = np.array([synth.random_direction(rng) for _ in range(50)])
+    f1 = oracle.doa_map(s, 1)
+    assert np.allclose(np.linalg.norm(f1, axis=1), 1.0) and np.all(f1[:, 1] == 0) and np.all(f1[:, 0] >= 0)
+    assert np.allclose(f1[:, 2], s[:, 2])                      # sin(elevation) = s_z on the unit sphere
+    rot = s @ np.array([[0.6, -0.8, 0], [0.8, 0.6, 0], [0, 0, 1.0]]).T   # any azimuth rotation
+    assert np.allclose(oracle.doa_map(rot, 1), f1)
+    xz = np.array([[np.cos(a), 0.0, np.sin(a)] for a in np.linspace(-1.5, 1.5, 7)])
+    assert np.allclose(oracle.doa_map(xz, 1), xz)
+    f2 = oracle.doa_map(s, 2)
+    assert np.allclose(f2[:, :2], s[:, :2]) and np.allclose(f2[:, 2], np.abs(s[:, 2]))
+    assert np.array_equal(oracle.doa_map(s, 3), s)
+
+
+def test_rmse_alpha_cases():
+    """Eq. (20): zero when every estimate is the true direction, whatever
+    the weights; the distance of the one estimate when all agree; the
+    weighted mean for two estimates; mirror images count as equal for the
+    planar array."""
+    s0 = np.array([0.0, 0.6, 0.8])
+    a = np.array([0.6, 0.0, 0.8])
+    Y = np.array([1.0, 3.0, 0.5])
+    for alpha in (1, 2, 3):
+        assert oracle.rmse_alpha(np.tile(s0, (3, 1)), Y, s0, alpha) < 1e-15
+    assert abs(oracle.rmse_alpha(np.tile(a, (3, 1)), Y, s0, 3) - np.linalg.norm(a - s0)) < 1e-15
+    est = np.stack([s0, a])
+    w = np.array([1.0, 3.0])
+    want = np.linalg.norm((s0 * 1 + a * 3) / 4 - s0)
+    assert abs(oracle.rmse_alpha(est, w, s0, 3) - want) < 1e-15
+    mirror = np.array([[0.0, 0.6, -0.8]])
+    assert oracle.rmse_alpha(mirror, np.ones(1), s0, 2) < 1e-15
+    assert oracle.rmse_alpha(mirror, np.ones(1), s0, 3) > 1.5
+    # the linear array sees azimuth as nothing: a = s0 rotated about z
+    assert oracle.rmse_alpha(np.array([[0.6, 0.0, 0.8]]), np.ones(1), s0, 1) < 1e-15
