@@ -367,16 +367,18 @@ __global__ __launch_bounds__(256) void k_zprep16(const float* __restrict__ zpart
     const int ns = zpart_count(fc, nsplit0, sG, sU, snch);
     float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     const float* src = zpart + fc * Rp + 8 * (act ? j : 0);
-    for (int s0 = 0; s0 < ns; s0 += 4) {
-        float4 a[4][2];
+    // slots two at a time: most frames have one or two (a frame tile that
+    // one or two workgroups cover), so no clamped copies are loaded
+    for (int s0 = 0; s0 < ns; s0 += 2) {
+        float4 a[2][2];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < 2; ++s) {
             const float* p = src + (int64_t)min(s0 + s, ns - 1) * zstride;
             a[s][0] = *reinterpret_cast<const float4*>(p);
             a[s][1] = *reinterpret_cast<const float4*>(p + 4);
         }
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int s = 0; s < 2; ++s)
             if (s0 + s < ns) {
                 v[0] += a[s][0].x; v[1] += a[s][0].y; v[2] += a[s][0].z; v[3] += a[s][0].w;
                 v[4] += a[s][1].x; v[5] += a[s][1].y; v[6] += a[s][1].z; v[7] += a[s][1].w;
