@@ -452,3 +452,37 @@ def test_rmse_alpha_cases():
     assert oracle.rmse_alpha(mirror, np.ones(1), s0, 3) > 1.5
     # the linear array sees azimuth as nothing: a = s0 rotated about z
     assert oracle.rmse_alpha(np.array([[0.6, 0.0, 0.8]]), np.ones(1), s0, 1) < 1e-15
+
+
+# ---------------------------------------------------- several sources (peaks)
+def test_peaks_no_separation_is_top_n():
+    """With a separation no pair of directions meets (cos_sep > 1), the
+    peaks are the n largest values in decreasing order, ties to the lower
+    index (numpy's stable sort)."""
+    rng = np.random.default_rng(21)
+    grid = synth.icosphere(2)
+    y = rng.integers(0, 40, size=(30, grid.shape[0])).astype(np.float32)   # many ties
+    idx, val = oracle.peaks(y, grid, 5, 1.5)
+    for f in range(30):
+        order = np.argsort(-y[f], kind="stable")[:5]
+        assert np.array_equal(idx[f], order) and np.array_equal(val[f], y[f, order])
+
+
+def test_peaks_full_separation_and_separated_bumps():
+    """cos_sep below -1 removes every direction after the first peak; two bumps
+    far apart are both found, each at its own maximum, and a third peak
+    never lies within the separation of the first two."""
+    grid = synth.icosphere(3)
+    rng = np.random.default_rng(22)
+    y = rng.standard_normal((4, grid.shape[0])).astype(np.float32)
+    idx, val = oracle.peaks(y, grid, 3, -1.5)
+    assert np.array_equal(idx[:, 0], np.argmax(y, axis=1)) and np.all(idx[:, 1:] == -1)
+    assert np.all(np.isinf(val[:, 1:]))
+    ia = 17
+    ib = int(np.argmin(np.abs(grid @ grid[ia])))    # about 90 degrees away
+    a, b = grid[ia], grid[ib]
+    assert abs(a @ b) < 0.1
+    yb = (np.exp(8 * (grid @ a - 1)) + 0.8 * np.exp(8 * (grid @ b - 1))).astype(np.float32)[None]
+    idx, _ = oracle.peaks(yb, grid, 3, np.cos(np.deg2rad(30)))
+    assert idx[0, 0] == ia and idx[0, 1] == ib
+    assert grid[idx[0, 2]] @ a < np.cos(np.deg2rad(30)) and grid[idx[0, 2]] @ b < np.cos(np.deg2rad(30))
