@@ -259,6 +259,28 @@ const char* svdphat_last_error(void);
 /* svdphat_sync -- waits for the stream and reports any pending device error. */
 int svdphat_sync(void* stream);
 
+/* ---- several sources per frame ----------------------------------------- */
+/*
+ * svdphat_peaks -- the n strongest separated directions of each frame (the
+ * paper leaves several sources to future work, Section 5): peak p is the
+ * largest y among the directions that are not an earlier peak and whose
+ * unit vector has a dot product below cos_sep with every earlier peak's
+ * (ties to the lowest index); with no direction left, idx = -1 and
+ * val = -inf.  NaN powers never count.  Dot products are rounded product
+ * by product, (x x' + y y') + z z', in FP32.
+ *   y      device, f32 [F][ldy]: powers of the Q directions of each frame
+ *          (e.g. the y_opt output of svdphat_locate, ldy = Q).
+ *   dirs   device, f32 [Q][3]: unit vectors of the directions.
+ *   n      peaks per frame, 1 <= n <= 16.  cos_sep: cosine of the separation.
+ *   idx    device, int32 [F][n];  val  device, f32 [F][n] (written).
+ *   stream hipStream_t or NULL; asynchronous.  F = 0 is a no-op.
+ * Errors: E_INVAL (F < 0, Q < 1, ldy < Q, n out of range, NULL pointers
+ * with F > 0), E_NODEV, E_DEVICE.
+ */
+int svdphat_peaks(const float* y, int64_t F, int32_t Q, int64_t ldy,
+                  const float* dirs, int32_t n, float cos_sep, int32_t* idx,
+                  float* val, void* stream);
+
 /* ---- STFT front end ---------------------------------------------------- */
 /*
  * svdphat_stft_frames -- number of whole frames in T samples:

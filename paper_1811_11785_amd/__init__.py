@@ -64,6 +64,8 @@ SIGNATURES = {
     "svdphat_plan_destroy": (None, [C.c_void_p]),
     "svdphat_sync": (C.c_int, [C.c_void_p]),
     "svdphat_stft_frames": (C.c_int64, [C.c_int64, C.c_int32, C.c_int32]),
+    "svdphat_peaks": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_void_p, C.c_int32, C.c_float,
+                                C.c_void_p, C.c_void_p, C.c_void_p]),
     "svdphat_stft": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_void_p,
                                C.c_void_p]),
     "svdphat_ragged_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_int64),
@@ -180,6 +182,20 @@ def svdphat_stft(pcm, N, hop, X, stream=None):
     M, T = pcm.shape
     assert pcm.stride(1) == 1
     _check(lib().svdphat_stft(_ptr(pcm), M, T, pcm.stride(0), N, hop, _ptr(X), _stream(stream)))
+
+
+def peaks(y, dirs, n, cos_sep, stream=None):
+    """The n strongest separated directions per frame: y float32 CUDA [F, Q]
+    (row stride y.stride(0)), dirs float32 CUDA [Q, 3] unit vectors.  Returns
+    (idx int32 [F, n], val float32 [F, n]) on y's device."""
+    import torch
+    F, Q = y.shape
+    assert y.stride(1) == 1 and dirs.is_contiguous() and dirs.shape == (Q, 3)
+    idx = torch.empty((F, n), dtype=torch.int32, device=y.device)
+    val = torch.empty((F, n), dtype=torch.float32, device=y.device)
+    _check(lib().svdphat_peaks(_ptr(y), F, Q, y.stride(0), _ptr(dirs), n, float(cos_sep), _ptr(idx), _ptr(val),
+                               _stream(stream)))
+    return idx, val
 
 
 def stft_frames(T, N, hop):

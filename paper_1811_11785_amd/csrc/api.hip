@@ -447,6 +447,20 @@ int svdphat_timing_read(int32_t index, char* name, int32_t name_len, double* tot
     });
 }
 
+int svdphat_peaks(const float* y, int64_t F, int32_t Q, int64_t ldy, const float* dirs, int32_t n, float cos_sep,
+                  int32_t* idx, float* val, void* stream) {
+    return guarded([&] {
+        SP_REQUIRE(F >= 0 && F < ((int64_t)1 << 31) && Q >= 1 && ldy >= Q, SVDPHAT_E_INVAL,
+                   "need 0 <= F < 2^31, Q >= 1, ldy >= Q");
+        SP_REQUIRE(n >= 1 && n <= peaks_max(), SVDPHAT_E_INVAL, "n must be in [1, " + std::to_string(peaks_max()) + "]");
+        if (F == 0) return;
+        SP_REQUIRE(y && dirs && idx && val, SVDPHAT_E_INVAL, "NULL y, dirs, idx or val");
+        require_device();
+        launch_peaks(y, F, Q, ldy, dirs, n, cos_sep, idx, val, (hipStream_t)stream);
+        SP_HIP(hipGetLastError());
+    });
+}
+
 int64_t svdphat_stft_frames(int64_t T, int32_t N, int32_t hop) {
     if (T < 0 || N < 1 || hop < 1) return -1;
     return T < N ? 0 : 1 + (T - N) / hop;

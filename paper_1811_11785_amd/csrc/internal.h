@@ -281,6 +281,10 @@ void* ws_get(svdphat_plan* p, hipStream_t s, size_t bytes);
 // zero `bytes` (a multiple of 4) of device memory on stream s with a kernel,
 // so that a caller capturing the stream into a graph records a kernel node
 void zero_async(void* p, size_t bytes, hipStream_t s);
+// several peaks per frame (peaks.hip)
+int peaks_max();
+void launch_peaks(const float* y, int64_t F, int Q, int64_t ldy, const float* dirs, int n, float cos_sep,
+                  int32_t* idx, float* val, hipStream_t s);
 // STFT front end (stft.hip): F frames of M signals into X [F][M][N/2+1]
 size_t stft_lds_bytes(int N);
 void launch_stft(const float* pcm, int M, int64_t ld, int N, int hop, float2* X, int64_t F, int device,

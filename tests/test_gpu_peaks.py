@@ -1,0 +1,81 @@
+"""GPU parity of svdphat_peaks (several separated peaks per frame) with the
+oracle's greedy peak picking on the same powers, bit for bit (indices and
+values): on the reduced powers svdphat_locate returns for frames of two
+simultaneous sources, and on integer-valued powers full of ties with NaNs,
+n = 16 and the no-separation and full-separation limits.  Needs an MI355X
+and the built library."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FS, C, N = 16000.0, 343.0, 512
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def amd(torch):
+    import paper_1811_11785_amd as amd
+    amd.lib()
+    return amd
+
+
+def test_peaks_two_sources(amd, torch):
+    print("peaks two sources", flush=True)
+    mics = synth.geometry("3d")
+    grid = synth.icosphere(3)
+    rng = np.random.default_rng(11785700)
+    X, dirs, _ = synth.segments(mics, 8, 12, rng, snr_range=(15.0, 15.0), n_src=2, ratio_db_range=(0.0, 0.0))
+    X = np.ascontiguousarray(X)
+    plan = amd.Plan(mics, grid, FS, C, N, 1e-5)
+    out = plan.locate(torch.from_numpy(X).cuda(), precision="fp32", rescore=True, want_y=True)
+    y = out["y"]
+    d = torch.from_numpy(grid.astype(np.float32)).cuda()
+    cs = np.float32(np.cos(np.deg2rad(25.0)))
+    idx, val = amd.peaks(y, d, 3, cs)
+    torch.cuda.synchronize()
+    ri, rv = oracle.peaks(y.cpu().numpy(), grid.astype(np.float32), 3, cs)
+    assert np.array_equal(idx.cpu().numpy(), ri)
+    assert np.array_equal(val.cpu().numpy(), rv)
+    # the two leading peaks near the two sources (within 20 degrees) in most frames
+    ii = idx.cpu().numpy()
+    hit = 0
+    for f in range(X.shape[0]):
+        src = dirs[f // 12]
+        got = grid[ii[f, :2]]
+        near = (got @ src.T) >= np.cos(np.deg2rad(20.0))
+        hit += bool(near[:, 0].any() and near[:, 1].any())
+    print(f"frames with both sources among the two leading peaks: {hit}/{X.shape[0]}", flush=True)
+    assert hit >= 0.5 * X.shape[0]
+    plan.close()
+
+
+@pytest.mark.parametrize("n,cos_sep", [(16, 0.9), (5, 1.5), (3, -1.5), (1, 0.5)])
+def test_peaks_ties_and_limits(amd, torch, n, cos_sep):
+    print(f"peaks ties n={n} cos={cos_sep}", flush=True)
+    grid = synth.icosphere(3)
+    Q = grid.shape[0]
+    rng = np.random.default_rng(11785710 + n)
+    F = 37
+    y = rng.integers(0, 25, size=(F, Q)).astype(np.float32)   # many equal values
+    y[3, rng.integers(0, Q, 50)] = np.nan
+    y[4] = np.nan                                              # a frame with nothing to pick
+    buf = torch.zeros((F, Q + 9), dtype=torch.float32, device="cuda")
+    buf[:, :Q] = torch.from_numpy(y).cuda()
+    d = torch.from_numpy(grid.astype(np.float32)).cuda()
+    idx, val = amd.peaks(buf[:, :Q], d, n, cos_sep)
+    torch.cuda.synchronize()
+    ri, rv = oracle.peaks(y, grid.astype(np.float32), n, cos_sep)
+    assert np.array_equal(idx.cpu().numpy(), ri)
+    assert np.array_equal(val.cpu().numpy(), rv)
+    assert np.all(ri[4] == -1)
