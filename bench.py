@@ -17,6 +17,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -323,8 +324,8 @@ def bench_ragged(args, torch, amd, synth):
     Xs = [torch.from_numpy(a["X"]).cuda() for a in arrs]
     Ftot = sum(x.shape[0] for x in Xs)
     t0 = time.perf_counter()
-    cache = os.path.join(ROOT, "gpurun_out", "ragged_tune.jsonl") if os.path.isdir(
-        os.path.join(ROOT, "gpurun_out")) else None
+    # tuning results cached across runs of this process's machine (tmp dir)
+    cache = os.path.join(tempfile.gettempdir(), "svdphat_ragged_tune.jsonl")
     rg = amd.Ragged(plans, [x.shape[0] for x in Xs], tune=True, tune_cache=cache)
     tune_s = time.perf_counter() - t0
     tuned, cached = rg.info()
