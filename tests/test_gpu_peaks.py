@@ -79,3 +79,24 @@ def test_peaks_ties_and_limits(amd, torch, n, cos_sep):
     assert np.array_equal(idx.cpu().numpy(), ri)
     assert np.array_equal(val.cpu().numpy(), rv)
     assert np.all(ri[4] == -1)
+
+
+def test_peaks_large_grid(amd, torch):
+    """The benchmark's 10,242-direction grid (161 lane-strided loads per pass),
+    smooth random fields with several bumps, n = 8, 15 degrees apart."""
+    print("peaks large grid", flush=True)
+    grid = synth.icosphere(5)
+    Q = grid.shape[0]
+    rng = np.random.default_rng(11785720)
+    F = 24
+    centres = np.array([[synth.random_direction(rng) for _ in range(5)] for _ in range(F)])
+    y = np.einsum("fcd,qd->fqc", centres, grid)
+    y = np.exp(6.0 * (y - 1.0)).sum(axis=2) + 0.05 * rng.standard_normal((F, Q))
+    y = y.astype(np.float32)
+    d = torch.from_numpy(grid.astype(np.float32)).cuda()
+    cs = np.float32(np.cos(np.deg2rad(15.0)))
+    idx, val = amd.peaks(torch.from_numpy(y).cuda(), d, 8, cs)
+    torch.cuda.synchronize()
+    ri, rv = oracle.peaks(y, grid.astype(np.float32), 8, cs)
+    assert np.array_equal(idx.cpu().numpy(), ri)
+    assert np.array_equal(val.cpu().numpy(), rv)
