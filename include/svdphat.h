@@ -93,9 +93,12 @@ typedef struct svdphat_info {
  *              length; each row is normalised as in eq. (2)).
  *   fs, c      sample rate (Hz) and speed of sound (m/s), both > 0.
  *   N          STFT frame size, even, >= 2.
- *   delta      tolerated relative reconstruction error of eq. (11),
- *              0 <= delta < 1; 0 keeps every singular value above
- *              1e-6 times the largest (the full numerical rank).
+ *   delta      tolerated relative reconstruction error of eq. (11), a
+ *              small positive value as Section 3 defines it: 0 < delta < 1.
+ *              The singular values come from the eigenvalues of the smaller
+ *              Gram matrix, which are accurate to about 1e-16 s_1^2 (absolute,
+ *              in s^2), so a delta below about 1e-12 can place the cut where
+ *              the tail energy is not resolved.
  *   flags      SVDPHAT_KEEP_W | SVDPHAT_NO_DEDUP.
  *   out        receives the new plan (set to NULL on failure).
  * Builds the far-field delays (eq. (2)), W (eqs. (4), (8)) in FP64 on the
@@ -103,7 +106,7 @@ typedef struct svdphat_info {
  * decomposition of the smaller Gram matrix, chooses K by eq. (11) (extended
  * over a cluster of equal singular values at the cut), and packs the device
  * operands.  Synchronous.  The plan owns all the device memory it creates.
- * Errors: E_INVAL (M < 2, Q < 1, N odd or < 2, delta outside [0,1), a zero
+ * Errors: E_INVAL (M < 2 or > 16, Q < 1, N odd or < 2, delta outside (0,1), a zero
  * grid row, non-finite input), E_NODEV, E_NOMEM, E_DEVICE, E_NUMERIC.
  */
 int svdphat_plan_create(const double* mic_xyz_m, int32_t M,
@@ -220,7 +223,9 @@ void svdphat_ragged_destroy(svdphat_ragged* ragged);
  *   softmax cross-entropy (written to *loss_host).  FP16 operands on MFMA,
  *   FP32 accumulation and master weights.  Synchronous.
  * svdphat_proposal_locate  doa [F] int32, power [F] f32 as svdphat_locate,
- *   fell_back [F] u8 = 1 where the full search was used.  Asynchronous.
+ *   fell_back [F] u8 = 1 where the full search was used (top probability
+ *   below conf_min, or no scored direction in any of the topk cells).
+ *   Asynchronous.
  * svdphat_proposal_params  copies the FP32 parameters to (set = 0) or from
  *   (set = 1) a host buffer of svdphat_proposal_nparams() floats laid out
  *   W1 [hidden][2K], b1 [hidden], W2 [hidden][hidden], b2 [hidden],
@@ -228,6 +233,16 @@ void svdphat_ragged_destroy(svdphat_ragged* ragged);
  * svdphat_proposal_grad  testing aid: mean loss and its gradient (same layout)
  *   for host features [F][2K] and labels [F].
  * svdphat_proposal_cells  host [Q]: cell of every fine direction.
+ * svdphat_proposal_features  testing aid: the network input of F device frames
+ *   X, written to device f32 [F][2K] (the FP16 values the network reads,
+ *   widened); synchronous.  The columns follow the plan's singular vectors,
+ *   so they are defined up to a unitary change of basis within each group of
+ *   equal singular values (a phase per vector when they are distinct).
+ * svdphat_proposal_apply_grad  testing aid: one Adam step (beta 0.9 / 0.999,
+ *   eps 1e-8, bias correction at the proposal's next step count) with the
+ *   given host mean gradient of svdphat_proposal_nparams() floats in the
+ *   layout of svdphat_proposal_params; the same update kernel as the
+ *   training step.  Synchronous.
  */
 typedef struct svdphat_proposal svdphat_proposal;
 int svdphat_proposal_create(svdphat_plan* fine, const double* coarse_xyz,
@@ -248,6 +263,10 @@ int svdphat_proposal_grad(svdphat_proposal* proposal, const float* features,
                           float* loss_host);
 int svdphat_proposal_cells(const svdphat_proposal* proposal,
                            int32_t* cell_of_direction);
+int svdphat_proposal_features(svdphat_proposal* proposal, const void* X,
+                              int64_t F, float* feat, void* stream);
+int svdphat_proposal_apply_grad(svdphat_proposal* proposal, const float* grad,
+                                int64_t n, float lr);
 void svdphat_proposal_destroy(svdphat_proposal* proposal);
 
 /* svdphat_plan_destroy -- frees the plan and its device memory; NULL is a no-op. */

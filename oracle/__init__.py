@@ -33,7 +33,7 @@ from .svdphat import (  # noqa: F401
 )
 from .stft import stft, stft_frames, sine_window, dft_matrix  # noqa: F401
 from .rmse import doa_map, rmse_alpha  # noqa: F401
-from .peaks import peaks  # noqa: F401
+from .peaks import peaks, valid_peaks  # noqa: F401
 from .mlp import (  # noqa: F401
     gelu, gelu_grad, mlp_forward, mlp_backward, softmax_xent, adam_step,
     coarse_cells, proposal_features,

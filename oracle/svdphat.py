@@ -80,20 +80,17 @@ def dirichlet_power(tau: np.ndarray, tau_src: np.ndarray, N: int) -> np.ndarray:
 def choose_rank(sigma: np.ndarray, delta: float, energy: float | None = None,
                 cluster_rtol: float = 1e-9) -> tuple[int, int]:
     """Rank rule of eq. (11): K_paper is the smallest K >= 1 with
-    sum_{k<=K} s_k^2 >= (1 - delta) * ||W||_F^2.  delta = 0 asks for the full
-    numerical rank, read as every singular value above 1e-6 s_1 (a threshold
-    both an SVD of W and an eigendecomposition of its Gram matrix, which
-    resolves s only down to about sqrt(eps) s_1, place alike).  K_used extends
-    K_paper over a cluster of equal singular values at the cut.  Returns
+    sum_{k<=K} s_k^2 >= (1 - delta) * ||W||_F^2, for the small positive delta
+    Section 3 defines (delta <= 0 raises ValueError).  K_used extends K_paper
+    over a cluster of equal singular values at the cut.  Returns
     (K_paper, K_used)."""
+    if not delta > 0.0:
+        raise ValueError("eq. (11) takes a positive delta")
     s2 = sigma.astype(np.float64) ** 2
     E = s2.sum() if energy is None else energy
     cum = np.cumsum(s2)
-    if delta <= 0.0:
-        Kp = int(max(1, np.count_nonzero(sigma > 1e-6 * sigma[0])))
-    else:
-        Kp = int(np.searchsorted(cum, (1.0 - delta) * E, side="left") + 1)
-        Kp = min(max(Kp, 1), sigma.size)
+    Kp = int(np.searchsorted(cum, (1.0 - delta) * E, side="left") + 1)
+    Kp = min(max(Kp, 1), sigma.size)
     K = Kp
     while K < sigma.size and sigma[K] >= (1.0 - cluster_rtol) * sigma[K - 1]:
         K += 1

@@ -85,6 +85,8 @@ SIGNATURES = {
     "svdphat_proposal_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                         C.POINTER(C.c_float)]),
     "svdphat_proposal_cells": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "svdphat_proposal_features": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "svdphat_proposal_apply_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_float]),
     "svdphat_proposal_destroy": (None, [C.c_void_p]),
     "svdphat_timing_enable": (C.c_int, [C.c_int]),
     "svdphat_timing_reset": (C.c_int, []),
@@ -408,6 +410,19 @@ class Proposal:
         _check(lib().svdphat_proposal_grad(self._h, features.ctypes.data, labels.ctypes.data,
                                            features.shape[0], g.ctypes.data, C.byref(loss)))
         return loss.value, g
+
+    def features(self, X, stream=None):
+        """Network input [F, 2K] (float32 device tensor) of device frames X."""
+        import torch
+        F = X.shape[0]
+        out = torch.empty((F, 2 * self.plan.info["K"]), dtype=torch.float32, device=X.device)
+        _check(lib().svdphat_proposal_features(self._h, _ptr(X), F, _ptr(out), _stream(stream)))
+        return out
+
+    def apply_grad(self, grad, lr):
+        """One Adam step with the given mean gradient (host, parameter layout)."""
+        grad = np.ascontiguousarray(grad, dtype=np.float32)
+        _check(lib().svdphat_proposal_apply_grad(self._h, grad.ctypes.data, grad.size, lr))
 
     def cells(self):
         out = np.zeros(self.plan.info["Q"], dtype=np.int32)

@@ -29,23 +29,30 @@ void zero_async(void* p, size_t bytes, hipStream_t s) {
 void fail(int code, const std::string& msg) { throw Error{code, msg}; }
 
 // Workspace of one stream on one plan, grown on demand (hipMalloc outside any
-// kernel; calls on the same plan and stream are ordered by the stream).
+// kernel; calls on the same plan and stream are ordered by the stream).  A
+// HIP graph captured earlier on the stream may still reference a superseded
+// buffer, so a grown-out buffer is kept until the plan is destroyed (growth
+// is by at least 1.5x, so the kept buffers add at most twice the largest).
+// Growing while the stream is being captured is refused: a capture must be
+// preceded by one eager call of at least its size on the same stream.
 void* ws_get(svdphat_plan* p, hipStream_t s, size_t bytes) {
     std::lock_guard<std::mutex> lk(p->ws_mu);
     Workspace& w = p->ws[(void*)s];
     if (w.bytes < bytes) {
-        if (w.buf) {
-            SP_HIP(hipStreamSynchronize(s));
-            (void)hipFree(w.buf);
-            w.buf = nullptr;
-            w.bytes = 0;
-        }
-        size_t n = (size_t)round_up64((int64_t)bytes, 1 << 20);
-        if (hipMalloc(&w.buf, n) != hipSuccess) {
-            w.buf = nullptr;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        SP_HIP(hipStreamIsCapturing(s, &cs));
+        SP_REQUIRE(cs == hipStreamCaptureStatusNone, SVDPHAT_E_INVAL,
+                   "the workspace of this stream must grow to " + std::to_string(bytes) +
+                       " bytes while the stream is being captured: make one call of this size on the stream "
+                       "before capturing");
+        if (w.buf) p->ws_retired.push_back(w.buf);
+        size_t n = (size_t)round_up64((int64_t)std::max(bytes, w.bytes + w.bytes / 2), 1 << 20);
+        void* nb = nullptr;
+        if (hipMalloc(&nb, n) != hipSuccess) {
             (void)hipGetLastError();
             fail(SVDPHAT_E_NOMEM, "workspace allocation of " + std::to_string(n) + " bytes failed");
         }
+        w.buf = nb;
         w.bytes = n;
     }
     return w.buf;
@@ -85,6 +92,7 @@ static void free_plan(svdphat_plan* p) {
         if (b) (void)hipFree(b);
     for (auto& kv : p->ws)
         if (kv.second.buf) (void)hipFree(kv.second.buf);
+    for (void* b : p->ws_retired) (void)hipFree(b);
     delete p;
 }
 
@@ -179,7 +187,7 @@ int svdphat_plan_create(const double* mic_xyz_m, int32_t M, const double* grid_x
         SP_REQUIRE(N >= 2 && N % 2 == 0, SVDPHAT_E_INVAL, "N must be even and >= 2");
         SP_REQUIRE(std::isfinite(fs) && fs > 0 && std::isfinite(c) && c > 0, SVDPHAT_E_INVAL,
                    "fs and c must be finite and > 0");
-        SP_REQUIRE(std::isfinite(delta) && delta >= 0.0 && delta < 1.0, SVDPHAT_E_INVAL, "delta must be in [0, 1)");
+        SP_REQUIRE(std::isfinite(delta) && delta > 0.0 && delta < 1.0, SVDPHAT_E_INVAL, "delta must be in (0, 1)");
         SP_REQUIRE((flags & ~(uint32_t)(SVDPHAT_KEEP_W | SVDPHAT_NO_DEDUP)) == 0, SVDPHAT_E_INVAL, "unknown flags");
         for (int i = 0; i < 3 * M; ++i)
             SP_REQUIRE(std::isfinite(mic_xyz_m[i]), SVDPHAT_E_INVAL, "non-finite microphone position");
@@ -404,6 +412,28 @@ int svdphat_proposal_grad(svdphat_proposal* pr, const float* features, const int
         SP_HIP(hipSetDevice(pr->plan->device));
         const float l = proposal_grad(pr, features, labels, F, grad);
         if (loss_host) *loss_host = l;
+    });
+}
+
+int svdphat_proposal_features(svdphat_proposal* pr, const void* X, int64_t F, float* feat, void* stream) {
+    return guarded([&] {
+        SP_REQUIRE(pr, SVDPHAT_E_INVAL, "NULL proposal");
+        SP_REQUIRE(F >= 0 && F < ((int64_t)1 << 31), SVDPHAT_E_INVAL, "F out of range");
+        if (F == 0) return;
+        SP_REQUIRE(X && feat, SVDPHAT_E_INVAL, "NULL X or feat");
+        SP_HIP(hipSetDevice(pr->plan->device));
+        proposal_features(pr, (const float2*)X, F, feat, (hipStream_t)stream);
+    });
+}
+
+int svdphat_proposal_apply_grad(svdphat_proposal* pr, const float* grad, int64_t n, float lr) {
+    return guarded([&] {
+        SP_REQUIRE(pr && grad, SVDPHAT_E_INVAL, "NULL proposal or gradient");
+        SP_REQUIRE(n == proposal_nparams(pr), SVDPHAT_E_INVAL,
+                   "gradient length must be " + std::to_string(proposal_nparams(pr)));
+        SP_REQUIRE(std::isfinite(lr) && lr > 0.f, SVDPHAT_E_INVAL, "lr must be > 0");
+        SP_HIP(hipSetDevice(pr->plan->device));
+        proposal_apply_grad(pr, grad, lr);
     });
 }
 

@@ -181,6 +181,8 @@ void proposal_locate(svdphat_proposal* pr, const float2* X, int64_t F, int topk,
 int64_t proposal_nparams(const svdphat_proposal* pr);
 void proposal_params(svdphat_proposal* pr, float* host, bool set);
 float proposal_grad(svdphat_proposal* pr, const float* feat, const int32_t* lab, int64_t F, float* grad);
+void proposal_features(svdphat_proposal* pr, const float2* X, int64_t F, float* feat, hipStream_t s);
+void proposal_apply_grad(svdphat_proposal* pr, const float* grad, float lr);
 void proposal_free(svdphat_proposal* pr);
 int64_t front_zpart_floats(const svdphat_plan* p, int64_t F);
 void front_fp16(svdphat_plan* p, const float2* X, int64_t F, float* zpart, float* z32, _Float16* zfrag, float* zsc,
@@ -241,6 +243,7 @@ struct svdphat_plan {
 
     std::mutex ws_mu;
     std::map<void*, svdphat::Workspace> ws;  // per stream
+    std::vector<void*> ws_retired;           // grown-out workspaces (freed with the plan)
 };
 
 // Learned proposal state (see the proposal calls of the ABI).
@@ -264,6 +267,7 @@ struct svdphat_proposal {
     // workspace
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    std::vector<void*> ws_retired;  // grown-out workspaces (freed with the proposal)
     int* d_count = nullptr;  // [4]
 };
 

@@ -344,24 +344,14 @@ void build_plan(svdphat_plan* p, const double* mics, const double* grid) {
         p->sigma[k] = std::sqrt(std::max(l, 0.0));
     }
     p->fro2 = fro2;
-    int Kp;
-    if (p->delta <= 0.0) {
-        // full numerical rank: the Gram route resolves s only down to about
-        // sqrt(eps) s_1, so every singular value above 1e-6 s_1 is kept
-        const double tol = 1e-6 * p->sigma[0];
-        Kp = 0;
-        for (int k = 0; k < n; ++k)
-            if (p->sigma[k] > tol) ++Kp;
-        Kp = std::max(Kp, 1);
-    } else {
-        double target = (1.0 - p->delta) * fro2, cum = 0.0;
-        Kp = n;
-        for (int k = 0; k < n; ++k) {
-            cum += p->sigma[k] * p->sigma[k];
-            if (cum >= target) {
-                Kp = k + 1;
-                break;
-            }
+    // smallest K with sum_{k<=K} s_k^2 >= (1 - delta) ||W||_F^2 (delta > 0)
+    double target = (1.0 - p->delta) * fro2, cum = 0.0;
+    int Kp = n;
+    for (int k = 0; k < n; ++k) {
+        cum += p->sigma[k] * p->sigma[k];
+        if (cum >= target) {
+            Kp = k + 1;
+            break;
         }
     }
     int K = Kp;

@@ -192,6 +192,13 @@ __global__ void k_features(const float* __restrict__ z32, const float* __restric
     feat[i] = (_Float16)(n > 0.f ? z32[i] / n : 0.f);
 }
 
+// FP16 network input [F][ld] widened to FP32 [F][D] (testing aid)
+__global__ void k_widen(const _Float16* __restrict__ h, int64_t F, int D, int ld, float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= F * D) return;
+    out[i] = (float)h[(i / D) * ld + i % D];
+}
+
 __global__ void k_labels(const int32_t* __restrict__ doa, const int32_t* __restrict__ cell_of_dir, int64_t F,
                          int32_t* __restrict__ lab) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -401,7 +408,15 @@ __global__ __launch_bounds__(256) void k_propose(const float* __restrict__ logit
         by = __uint_as_float(w[0]);
         bq = (int)w[1];
     }
-    if (bq < 0 || bq == 0x7fffffff) bq = rows[0];
+    if (bq < 0 || bq == 0x7fffffff) {
+        // no scored direction in any proposed cell (empty cells): full search
+        if (lane == 0) {
+            fell[f] = 1;
+            const int k = atomicAdd(fcount, 1);
+            flist[k] = (int)f;
+        }
+        return;
+    }
     float t[MAXM];
 #pragma unroll
     for (int m = 0; m < MAXM; ++m) t[m] = m < M ? tauM[(int64_t)bq * M + m] : 0.f;
@@ -500,17 +515,21 @@ PW carve(svdphat_proposal* pr, int64_t F, hipStream_t s) {
     const size_t o_pm = take(sizeof(float) * pmax_stride(p) * Fc), o_zg = take(sizeof(float) * Fc * Rp);
     const size_t o_zgf = take(sizeof(_Float16) * Fc * Rp), o_zgs = take(sizeof(float) * Fc);
     if (pr->ws_bytes < off) {
-        if (pr->ws) {
-            SP_HIP(hipStreamSynchronize(s));
-            (void)hipFree(pr->ws);
-            pr->ws = nullptr;
-            pr->ws_bytes = 0;
+        // a grown-out buffer is kept until the proposal is destroyed (a graph
+        // captured earlier may reference it); no growth during a capture
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        SP_HIP(hipStreamIsCapturing(s, &cs));
+        SP_REQUIRE(cs == hipStreamCaptureStatusNone, SVDPHAT_E_INVAL,
+                   "the proposal workspace must grow while the stream is being captured");
+        const size_t n = std::max(off, pr->ws_bytes + pr->ws_bytes / 2);
+        void* nb = nullptr;
+        if (hipMalloc(&nb, n) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(SVDPHAT_E_NOMEM, "proposal workspace of " + std::to_string(n) + " bytes");
         }
-        if (hipMalloc(&pr->ws, off) != hipSuccess) {
-            pr->ws = nullptr;
-            fail(SVDPHAT_E_NOMEM, "proposal workspace of " + std::to_string(off) + " bytes");
-        }
-        pr->ws_bytes = off;
+        if (pr->ws) pr->ws_retired.push_back(pr->ws);
+        pr->ws = nb;
+        pr->ws_bytes = n;
     }
     char* w = (char*)pr->ws;
     PW o;
@@ -580,7 +599,7 @@ void backward(svdphat_proposal* pr, const PW& o, int64_t F, hipStream_t s) {
     SP_HIP(hipGetLastError());
 }
 
-void adam(svdphat_proposal* pr, const PW& o, int64_t F, float lr, hipStream_t s) {
+void adam(svdphat_proposal* pr, const PW& o, int64_t F, float lr, hipStream_t s, float inv_f = -1.f) {
     const int H = pr->H, Cp = pr->Cp, D0 = pr->D0;
     pr->step += 1;
     const float b1 = 0.9f, b2 = 0.999f;
@@ -596,7 +615,8 @@ void adam(svdphat_proposal* pr, const PW& o, int64_t F, float lr, hipStream_t s)
     };
     for (auto& sg : seg) {
         const int64_t n = (int64_t)sg.rows * sg.cols;
-        k_adam<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(sg, pr->P, pr->Mm, pr->Vv, 1.f / (float)F, lr, b1,
+        k_adam<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(sg, pr->P, pr->Mm, pr->Vv,
+                                                                  inv_f > 0.f ? inv_f : 1.f / (float)F, lr, b1,
                                                                   b2, 1e-8f, c1, c2);
     }
     SP_HIP(hipGetLastError());
@@ -839,12 +859,47 @@ float proposal_grad(svdphat_proposal* pr, const float* feat, const int32_t* lab,
     return (float)(sum / (double)F);
 }
 
+// network input of F frames as FP32 [F][2K] (testing aid)
+void proposal_features(svdphat_proposal* pr, const float2* X, int64_t F, float* feat, hipStream_t s) {
+    svdphat_plan* p = pr->plan;
+    PW o = carve(pr, F, s);
+    front_fp16(p, X, F, o.zpart, o.z32, o.zfrag, o.zsc, o.zn, s);
+    k_features<<<dim3((unsigned)((F * p->Rp + 255) / 256)), 256, 0, s>>>(o.z32, o.zn, F, p->Rp, o.feat);
+    k_widen<<<dim3((unsigned)((F * pr->D + 255) / 256)), 256, 0, s>>>(o.feat, F, pr->D, pr->D0, feat);
+    SP_HIP(hipGetLastError());
+    SP_HIP(hipStreamSynchronize(s));
+}
+
+// one Adam step with a given mean gradient in the host parameter layout
+// (testing aid; the same update kernel as the training step)
+void proposal_apply_grad(svdphat_proposal* pr, const float* grad, float lr) {
+    const int H = pr->H, D = pr->D, D0 = pr->D0, C = pr->C, Cp = pr->Cp;
+    hipStream_t s = nullptr;
+    PW o = carve(pr, 1, s);
+    int64_t h = 0;
+    auto put = [&](float* g, int rows, int cols, int prow, int ld) {
+        std::vector<float> t((size_t)prow * ld, 0.f);
+        for (int r = 0; r < rows; ++r)
+            for (int c = 0; c < cols; ++c, ++h) t[(size_t)r * ld + c] = grad[h];
+        SP_HIP(hipMemcpy(g, t.data(), sizeof(float) * t.size(), hipMemcpyHostToDevice));
+    };
+    put(o.g[0], H, D, H, D0);
+    put(o.g[1], 1, H, 1, H);
+    put(o.g[2], H, H, H, H);
+    put(o.g[3], 1, H, 1, H);
+    put(o.g[4], C, H, Cp, H);
+    put(o.g[5], 1, C, 1, Cp);
+    adam(pr, o, 1, lr, s, 1.f);
+    SP_HIP(hipDeviceSynchronize());
+}
+
 void proposal_free(svdphat_proposal* pr) {
     if (!pr) return;
     void* bufs[] = {pr->d_cell_of_dir, pr->d_cell_start, pr->d_cell_rows, pr->d_U32R, pr->P, pr->Mm, pr->Vv,
                     pr->ws, pr->d_count, pr->Wh[0], pr->Wh[1], pr->Wh[2], pr->Wt[0], pr->Wt[1], pr->Wt[2]};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    for (void* b : pr->ws_retired) (void)hipFree(b);
     delete pr;
 }
 

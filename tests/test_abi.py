@@ -39,7 +39,8 @@ def test_version():
 
 @pytest.mark.parametrize("kw,what", [
     (dict(N=31), "N odd"), (dict(N=0), "N zero"), (dict(delta=1.0), "delta 1"),
-    (dict(delta=-1e-3), "delta negative"), (dict(fs=0.0), "fs zero"), (dict(c=-1.0), "c negative"),
+    (dict(delta=-1e-3), "delta negative"), (dict(delta=0.0), "delta zero (eq. (11) takes delta > 0)"),
+    (dict(fs=0.0), "fs zero"), (dict(c=-1.0), "c negative"),
 ])
 def test_plan_create_rejects(kw, what):
     mics = np.zeros((4, 3))

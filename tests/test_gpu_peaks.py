@@ -1,9 +1,17 @@
 """GPU parity of svdphat_peaks (several separated peaks per frame) with the
-oracle's greedy peak picking on the same powers, bit for bit (indices and
-values): on the reduced powers svdphat_locate returns for frames of two
-simultaneous sources, and on integer-valued powers full of ties with NaNs,
-n = 16 and the no-separation and full-separation limits.  Needs an MI355X
-and the built library."""
+oracle's greedy peak picking on the same powers: on the reduced powers
+svdphat_locate returns for frames of two simultaneous sources, and on
+integer-valued powers full of ties with NaNs, n = 16 and the no-separation
+and full-separation limits.  Needs an MI355X and the built library.
+
+The oracle takes its separation decisions in FP64 from the FP64 directions;
+the kernel forms the dot products in FP32 from FP32 directions.  Those
+differ by at most about 5 u = 3e-7 (u = 2^-24: rounding of the unit vectors,
+two of each product's factors, and three FP32 operations, each relative to
+sum |x x'| <= 1), so a comparison is undecided only within BAND = 1e-6 of
+cos_sep.  Peaks that precede any undecided comparison must equal the
+oracle's bit for bit; every peak must pass the oracle's validity check, and
+every value must be the frame's power at the returned index."""
 import numpy as np
 import pytest
 
@@ -13,6 +21,22 @@ import synth
 pytestmark = pytest.mark.gpu
 
 FS, C, N = 16000.0, 343.0, 512
+BAND = 1e-6
+
+
+def _check(idx, val, y, grid, n, cs):
+    """idx/val from the GPU; y [F, Q] the powers the GPU was given."""
+    idx = idx.cpu().numpy().astype(np.int64)
+    val = val.cpu().numpy()
+    ri, rv, dec = oracle.peaks(y, grid, n, float(cs), band=BAND)
+    for f in range(y.shape[0]):
+        k = dec[f]
+        assert np.array_equal(idx[f, :k], ri[f, :k]), f"frame {f}: {idx[f]} vs {ri[f]} (decided {k})"
+    assert np.all(oracle.valid_peaks(y, grid, float(cs), BAND, idx))
+    rows = np.arange(y.shape[0])[:, None]
+    want = np.where(idx >= 0, y[rows, np.maximum(idx, 0)], -np.inf).astype(np.float32)
+    assert np.array_equal(val, want)
+    return int(np.sum(dec == n))
 
 
 @pytest.fixture(scope="module")
@@ -44,9 +68,8 @@ def test_peaks_two_sources(amd, torch):
     cs = np.float32(np.cos(np.deg2rad(25.0)))
     idx, val = amd.peaks(y, d, 3, cs)
     torch.cuda.synchronize()
-    ri, rv = oracle.peaks(y.cpu().numpy(), grid.astype(np.float32), 3, cs)
-    assert np.array_equal(idx.cpu().numpy(), ri)
-    assert np.array_equal(val.cpu().numpy(), rv)
+    full = _check(idx, val, y.cpu().numpy(), grid, 3, cs)
+    print(f"frames decided in full: {full}/{X.shape[0]}", flush=True)
     # the two leading peaks near the two sources (within 20 degrees) in most frames
     ii = idx.cpu().numpy()
     hit = 0
@@ -75,10 +98,8 @@ def test_peaks_ties_and_limits(amd, torch, n, cos_sep):
     d = torch.from_numpy(grid.astype(np.float32)).cuda()
     idx, val = amd.peaks(buf[:, :Q], d, n, cos_sep)
     torch.cuda.synchronize()
-    ri, rv = oracle.peaks(y, grid.astype(np.float32), n, cos_sep)
-    assert np.array_equal(idx.cpu().numpy(), ri)
-    assert np.array_equal(val.cpu().numpy(), rv)
-    assert np.all(ri[4] == -1)
+    _check(idx, val, y, grid, n, np.float32(cos_sep))
+    assert np.all(idx.cpu().numpy()[4] == -1)
 
 
 def test_peaks_large_grid(amd, torch):
@@ -97,6 +118,5 @@ def test_peaks_large_grid(amd, torch):
     cs = np.float32(np.cos(np.deg2rad(15.0)))
     idx, val = amd.peaks(torch.from_numpy(y).cuda(), d, 8, cs)
     torch.cuda.synchronize()
-    ri, rv = oracle.peaks(y, grid.astype(np.float32), 8, cs)
-    assert np.array_equal(idx.cpu().numpy(), ri)
-    assert np.array_equal(val.cpu().numpy(), rv)
+    full = _check(idx, val, y, grid, 8, cs)
+    print(f"frames decided in full: {full}/{F}", flush=True)

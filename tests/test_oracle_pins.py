@@ -79,20 +79,24 @@ def test_rank_rule_cluster_extension():
     delta = 1 - np.sum(s[:3] ** 2) / E
     Kp, K = oracle.choose_rank(s, delta * 1.000001)
     assert Kp == 3 and K == 5
-    Kp, K = oracle.choose_rank(s, 0.0)
+    Kp, K = oracle.choose_rank(s, 1e-12)
     assert Kp == K == 7
+    # eq. (11) takes a positive delta
+    for bad in (0.0, -1e-5):
+        with pytest.raises(ValueError):
+            oracle.choose_rank(s, bad)
 
 
 # ------------------------------------------------------------------ P2
 def test_p2_full_rank_equals_srp():
     """With every singular value kept, eqs. (12)-(14) reproduce eq. (9) to
-    rounding; with the numerical-rank cut (delta = 0) the difference is
-    bounded by the first dropped singular value times ||x||."""
+    rounding; with a tiny delta the difference is bounded by the first
+    dropped singular value times ||x||."""
     for level, seed in ((0, 3), (2, 3)):
         mics, grid, rng = _small(M=4, N=16, level=level, seed=seed)
         tau = oracle.tdoa_farfield(mics, grid, 16000.0, 343.0)
         W = oracle.steering_matrix(tau, 16)
-        U, s, Vh, Kp, K = oracle.truncated_svd(W, 0.0)
+        U, s, Vh, Kp, K = oracle.truncated_svd(W, 1e-13)
         X = rng.standard_normal((6, 4, 9)) + 1j * rng.standard_normal((6, 4, 9))
         x = oracle.phat_vector(X)
         y_srp = oracle.srp_phat_power(W, x)
@@ -343,6 +347,40 @@ def test_adam_first_step():
     assert np.allclose(p, -0.01 * np.sign(g), rtol=1e-4)
 
 
+def test_adam_constant_gradient_steps():
+    """With the same gradient at every step the bias-corrected moments are
+    m^ = g and v^ = g^2 at every t, so each of three steps moves a parameter
+    by lr g / (|g| + eps); a missing or stale bias correction moves it by a
+    different amount from the second step on."""
+    g = np.array([0.5, -3.0, 2e-2, -1e-3])
+    p, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    lr, eps = 0.01, 1e-8
+    for t in (1, 2, 3):
+        p, m, v = oracle.adam_step(p, g, m, v, t, lr=lr, eps=eps)
+        assert np.allclose(p, -t * lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-15)
+
+
+def test_proposal_features_pins():
+    """The network input [Re z, Im z] / ||z||: a worked example, unit norm,
+    invariance under a positive scale of z, zero for z = 0, and a Gram
+    matrix over frames that a unitary change of the singular-vector basis
+    (a phase per component) leaves unchanged."""
+    z = np.array([[1 + 2j, 3 + 0j], [0j, 0j], [0j, -2j]])
+    f = oracle.proposal_features(z)
+    assert np.allclose(f[0], np.array([1.0, 3.0, 2.0, 0.0]) / np.sqrt(14.0), atol=1e-15)
+    assert np.array_equal(f[1], np.zeros(4))
+    assert np.allclose(f[2], [0.0, 0.0, 0.0, -1.0], atol=1e-15)
+    rng = np.random.default_rng(24)
+    z = rng.standard_normal((9, 6)) + 1j * rng.standard_normal((9, 6))
+    f = oracle.proposal_features(z)
+    assert np.allclose(np.linalg.norm(f, axis=1), 1.0, atol=1e-14)
+    assert np.allclose(oracle.proposal_features(z * 37.5), f, atol=1e-14)
+    ph = np.exp(1j * rng.uniform(0, 2 * np.pi, 6))
+    g = oracle.proposal_features(z * ph[None, :])
+    assert np.allclose(g @ g.T, f @ f.T, atol=1e-13)
+    assert not np.allclose(g, f, atol=1e-3)
+
+
 def test_coarse_cells_nesting():
     fine = synth.icosphere(4)
     coarse = synth.icosphere(2)
@@ -462,7 +500,8 @@ def test_peaks_no_separation_is_top_n():
     rng = np.random.default_rng(21)
     grid = synth.icosphere(2)
     y = rng.integers(0, 40, size=(30, grid.shape[0])).astype(np.float32)   # many ties
-    idx, val = oracle.peaks(y, grid, 5, 1.5)
+    idx, val, dec = oracle.peaks(y, grid, 5, 1.5, band=1e-6)
+    assert np.all(dec == 5)
     for f in range(30):
         order = np.argsort(-y[f], kind="stable")[:5]
         assert np.array_equal(idx[f], order) and np.array_equal(val[f], y[f, order])
@@ -475,7 +514,7 @@ def test_peaks_full_separation_and_separated_bumps():
     grid = synth.icosphere(3)
     rng = np.random.default_rng(22)
     y = rng.standard_normal((4, grid.shape[0])).astype(np.float32)
-    idx, val = oracle.peaks(y, grid, 3, -1.5)
+    idx, val, _ = oracle.peaks(y, grid, 3, -1.5)
     assert np.array_equal(idx[:, 0], np.argmax(y, axis=1)) and np.all(idx[:, 1:] == -1)
     assert np.all(np.isinf(val[:, 1:]))
     ia = 17
@@ -483,6 +522,76 @@ def test_peaks_full_separation_and_separated_bumps():
     a, b = grid[ia], grid[ib]
     assert abs(a @ b) < 0.1
     yb = (np.exp(8 * (grid @ a - 1)) + 0.8 * np.exp(8 * (grid @ b - 1))).astype(np.float32)[None]
-    idx, _ = oracle.peaks(yb, grid, 3, np.cos(np.deg2rad(30)))
+    idx, _, _ = oracle.peaks(yb, grid, 3, np.cos(np.deg2rad(30)))
     assert idx[0, 0] == ia and idx[0, 1] == ib
     assert grid[idx[0, 2]] @ a < np.cos(np.deg2rad(30)) and grid[idx[0, 2]] @ b < np.cos(np.deg2rad(30))
+
+
+def test_peaks_pair_at_the_separation():
+    """A direction whose dot product with the first peak is exactly cos_sep
+    is too close (the comparison is 'below cos_sep' for a free direction);
+    one ulp of cos_sep higher it is free.  The pair (1, 0, 0), (0.6, 0.8, 0)
+    has the dot product fl(0.6) exactly in FP64.  Within a band around
+    cos_sep the oracle reports only the first peak as decided, and the
+    validity check accepts either choice there but rejects a peak that is
+    clearly too close or clearly not the largest free power."""
+    dirs = np.array([[1.0, 0.0, 0.0], [0.6, 0.8, 0.0], [-1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    assert dirs[1] @ dirs[0] == 0.6
+    y = np.array([[4.0, 3.0, 1.0, 2.0]])
+    idx, val, dec = oracle.peaks(y, dirs, 2, 0.6)
+    assert idx[0].tolist() == [0, 3] and val[0].tolist() == [4.0, 2.0] and dec[0] == 2
+    idx, _, _ = oracle.peaks(y, dirs, 2, np.nextafter(0.6, 1.0))
+    assert idx[0].tolist() == [0, 1]
+    _, _, dec = oracle.peaks(y, dirs, 2, 0.6, band=1e-6)
+    assert dec[0] == 1
+    for second, ok in ((1, True), (3, True), (2, False)):
+        assert oracle.valid_peaks(y, dirs, 0.6, 1e-6, np.array([[0, second]]))[0] == ok
+    # outside the band only the exact answer is valid
+    assert oracle.valid_peaks(y, dirs, 0.5, 1e-6, np.array([[0, 3]]))[0]
+    assert not oracle.valid_peaks(y, dirs, 0.5, 1e-6, np.array([[0, 1]]))[0]
+    assert not oracle.valid_peaks(y, dirs, 0.7, 1e-6, np.array([[0, 3]]))[0]
+    assert oracle.valid_peaks(y, dirs, 0.7, 1e-6, np.array([[0, 1]]))[0]
+
+
+def test_peaks_brute_force_greedy():
+    """The greedy reading by brute force on tiny random inputs: every
+    ordered choice of n directions is enumerated and the one the rule
+    selects (each peak the largest strictly separated power, lowest index on
+    ties) compared with the oracle; the oracle's answer also passes the
+    validity check and the check rejects every other enumerated choice
+    away from the band."""
+    rng = np.random.default_rng(23)
+    for trial in range(40):
+        Q = 7
+        dirs = rng.standard_normal((Q, 3))
+        dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+        y = rng.integers(0, 4, size=(1, Q)).astype(np.float64)
+        cs = float(rng.uniform(-0.5, 0.9))
+        n = 3
+        idx, _, dec = oracle.peaks(y, dirs, n, cs, band=1e-9)
+        best = None
+        for choice in itertools.permutations(range(Q), n):
+            good = True
+            for p, q in enumerate(choice):
+                free = [r for r in range(Q) if r not in choice[:p]
+                        and all(dirs[r] @ dirs[e] < cs for e in choice[:p])]
+                if not free or q not in free:
+                    good = False
+                    break
+                m = max(y[0, r] for r in free)
+                if y[0, q] != m or q != min(r for r in free if y[0, r] == m):
+                    good = False
+                    break
+            if good:
+                best = choice
+                break
+        if best is None:   # fewer than n peaks exist: compare the leading ones
+            k = int(np.sum(idx[0] >= 0))
+            assert np.all(idx[0, k:] == -1)
+        else:
+            assert tuple(idx[0].tolist()) == best
+        assert oracle.valid_peaks(y, dirs, cs, 1e-9, idx)[0]
+        if dec[0] == n and best is not None:
+            for choice in itertools.permutations(range(Q), n):
+                if choice != best:
+                    assert not oracle.valid_peaks(y, dirs, cs, 1e-9, np.array([choice]))[0]
