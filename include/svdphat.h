@@ -154,6 +154,30 @@ int svdphat_locate(svdphat_plan* plan, const void* X, int64_t F,
                    void* stream);
 
 /*
+ * svdphat_locate_noalloc -- svdphat_locate (same kernels, same results, no
+ * y_opt) for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * calls no hipMalloc, hipFree or allocating library routine: its
+ * intermediate results live in a fixed device array of
+ * svdphat_noalloc_scratch_bytes() bytes (64 MiB) that the library holds on
+ * every GPU it runs on until the process ends; the caller still passes X and
+ * the outputs.  Every call on a GPU shares that GPU's array (the kernels
+ * clear what must start at zero), so calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.
+ * Errors: as svdphat_locate, and E_INVAL, before anything is enqueued,
+ * when F frames need more scratch than the array holds (at the
+ * 7-microphone, Q = 10242, K = 48 plan: about 4,800 frames with
+ * SVDPHAT_HILO and 16-bit operands, over 30,000 without); split such
+ * batches.
+ */
+int svdphat_locate_noalloc(svdphat_plan* plan, const void* X, int64_t F,
+                           int32_t precision, uint32_t mode, int32_t* doa,
+                           float* power, float* yhat, float* margin,
+                           void* stream);
+/* svdphat_noalloc_scratch_bytes -- size of the array above, in bytes. */
+int64_t svdphat_noalloc_scratch_bytes(void);
+
+/*
  * svdphat_srp_locate -- plain SRP-PHAT, eqs. (3), (9), (6), in FP32.
  *   X, F, stream as above; doa [F] class-lowest argmax, power [F] its Y,
  *   y_opt [F][Q] or NULL.  Needs a plan created with SVDPHAT_KEEP_W, else

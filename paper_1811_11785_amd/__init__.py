@@ -61,6 +61,9 @@ SIGNATURES = {
                                  C.c_void_p]),
     "svdphat_srp_locate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p]),
+    "svdphat_locate_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_uint32,
+                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "svdphat_noalloc_scratch_bytes": (C.c_int64, []),
     "svdphat_plan_destroy": (None, [C.c_void_p]),
     "svdphat_sync": (C.c_int, [C.c_void_p]),
     "svdphat_stft_frames": (C.c_int64, [C.c_int64, C.c_int32, C.c_int32]),
@@ -163,6 +166,15 @@ def svdphat_locate(plan, X, precision, mode, doa, power, yhat=None, margin=None,
                    stream=None):
     _check(lib().svdphat_locate(plan, _ptr(X), X.shape[0], precision, mode, _ptr(doa), _ptr(power),
                                 _ptr(yhat), _ptr(margin), _ptr(y_opt), _stream(stream)))
+
+
+def svdphat_locate_noalloc(plan, X, precision, mode, doa, power, yhat=None, margin=None, stream=None):
+    _check(lib().svdphat_locate_noalloc(plan, _ptr(X), X.shape[0], precision, mode, _ptr(doa), _ptr(power),
+                                        _ptr(yhat), _ptr(margin), _stream(stream)))
+
+
+def svdphat_noalloc_scratch_bytes() -> int:
+    return lib().svdphat_noalloc_scratch_bytes()
 
 
 def svdphat_srp_locate(plan, X, doa, power, y_opt=None, stream=None):

@@ -107,6 +107,31 @@ static void require_device() {
 
 void build_plan(svdphat_plan* p, const double* mics, const double* grid);
 
+// ------------------------------------------------ allocation-free locate
+// Intermediate results of svdphat_locate_noalloc live in this file-scope
+// device array: every GPU the library runs on holds its own copy until the
+// process ends.  In host code `scratch` names a host-side stand-in, so its
+// device address is looked up once per device (with that device current) and
+// only that address is ever passed to kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // device -> its copy of `scratch`
+
+void* scratch_ptr(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) return it->second;
+    void* ptr = nullptr;
+    SP_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    SP_REQUIRE(ptr != nullptr, SVDPHAT_E_DEVICE, "no device address for the scratch array");
+    g_scratch_ptr[device] = ptr;
+    return ptr;
+}
+}  // namespace
+
 // ------------------------------------------------------------ timing
 namespace {
 struct TimingTable {
@@ -277,6 +302,26 @@ int svdphat_locate(svdphat_plan* p, const void* X, int64_t F, int32_t precision,
         launch_locate(p, X, F, precision, mode, doa, power, yhat, margin, y_opt, (hipStream_t)stream);
     });
 }
+
+int svdphat_locate_noalloc(svdphat_plan* p, const void* X, int64_t F, int32_t precision, uint32_t mode,
+                           int32_t* doa, float* power, float* yhat, float* margin, void* stream) {
+    return guarded([&] {
+        SP_REQUIRE(p, SVDPHAT_E_INVAL, "NULL plan");
+        SP_REQUIRE(F >= 0 && F < ((int64_t)1 << 31), SVDPHAT_E_INVAL, "F out of range");
+        SP_REQUIRE(precision == SVDPHAT_FP32 || precision == SVDPHAT_BF16 || precision == SVDPHAT_FP16,
+                   SVDPHAT_E_INVAL, "unknown precision");
+        SP_REQUIRE((mode & ~(uint32_t)(SVDPHAT_RESCORE | SVDPHAT_HILO | SVDPHAT_HILO_ALL)) == 0, SVDPHAT_E_INVAL,
+                   "unknown mode bits");
+        if (F == 0) return;
+        SP_REQUIRE(X && doa && power, SVDPHAT_E_INVAL, "NULL X, doa or power");
+        SP_HIP(hipSetDevice(p->device));
+        void* ws = scratch_ptr(p->device);
+        launch_locate(p, X, F, precision, mode, doa, power, yhat, margin, nullptr, (hipStream_t)stream, ws,
+                      NOALLOC_SCRATCH_BYTES);
+    });
+}
+
+int64_t svdphat_noalloc_scratch_bytes(void) { return (int64_t)NOALLOC_SCRATCH_BYTES; }
 
 int svdphat_srp_locate(svdphat_plan* p, const void* X, int64_t F, int32_t* doa, float* power, float* y_opt,
                        void* stream) {

@@ -275,9 +275,11 @@ namespace svdphat {
 // Row stride (floats) of the frame-major tile maxima: tiles padded to 32.
 inline int pmax_stride(const svdphat_plan* p) { return round_up(p->ncls_pad / QTILE, 32); }
 // launchers
+// scratch: a caller-provided device buffer of scratch_bytes for the call's
+// intermediate results (nullptr: the plan's workspace of stream s)
 void launch_locate(svdphat_plan* p, const void* X, int64_t F, int prec, uint32_t mode,
                    int32_t* doa, float* power, float* yhat, float* margin, float* y_opt,
-                   hipStream_t s);
+                   hipStream_t s, void* scratch = nullptr, size_t scratch_bytes = 0);
 void launch_srp(svdphat_plan* p, const void* X, int64_t F, int32_t* doa, float* power,
                 float* y_opt, hipStream_t s);
 void build_w_fp32_frags(svdphat_plan* p);

@@ -1219,7 +1219,7 @@ void launch_final_list(const FinalArgs& fa, int M, bool dedup, hipStream_t s) {
 
 template <typename T>
 void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t mode, int32_t* doa, float* power,
-                float* yhat, float* margin, float* y_opt, hipStream_t s) {
+                float* yhat, float* margin, float* y_opt, hipStream_t s, void* scratch, size_t scratch_bytes) {
     const G1Layout& g = p->g1[prec];
     const int Rp = p->Rp;
     const int ntile = p->ncls_pad / QTILE;
@@ -1252,7 +1252,13 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     const size_t o_hc = hilo ? take(sizeof(int) * 64) : 0;
     const size_t o_y = y_opt ? take(sizeof(float) * Fc * p->ncls_pad) : 0;
     const size_t o_st = take(sizeof(unsigned long long) * 4);
-    char* w = (char*)ws_get(p, s, off);
+    // the caller's scratch buffer (checked before anything is enqueued), or
+    // the plan's workspace of this stream
+    if (scratch)
+        SP_REQUIRE(off <= scratch_bytes, SVDPHAT_E_INVAL,
+                   "this call needs " + std::to_string(off) + " bytes of scratch memory, more than the " +
+                       std::to_string(scratch_bytes) + " available: split the frames into smaller calls");
+    char* w = scratch ? (char*)scratch : (char*)ws_get(p, s, off);
     unsigned long long* stats = counting_on() ? (unsigned long long*)(w + o_st) : nullptr;
     if (stats) zero_async(stats, sizeof(unsigned long long) * 4, s);
     float* zpart = (float*)(w + o_zpart);
@@ -1593,11 +1599,12 @@ void tune_time(svdphat_plan* p, int64_t F, int nsplit_want, int fch, double* us_
 }
 
 void launch_locate(svdphat_plan* p, const void* X, int64_t F, int prec, uint32_t mode, int32_t* doa, float* power,
-                   float* yhat, float* margin, float* y_opt, hipStream_t s) {
+                   float* yhat, float* margin, float* y_opt, hipStream_t s, void* scratch, size_t scratch_bytes) {
     const float2* x = (const float2*)X;
-    if (prec == P_FP32) run_locate<float>(p, x, F, prec, mode, doa, power, yhat, margin, y_opt, s);
-    else if (prec == P_FP16) run_locate<_Float16>(p, x, F, prec, mode, doa, power, yhat, margin, y_opt, s);
-    else run_locate<__bf16>(p, x, F, prec, mode, doa, power, yhat, margin, y_opt, s);
+    if (prec == P_FP32) run_locate<float>(p, x, F, prec, mode, doa, power, yhat, margin, y_opt, s, scratch, scratch_bytes);
+    else if (prec == P_FP16)
+        run_locate<_Float16>(p, x, F, prec, mode, doa, power, yhat, margin, y_opt, s, scratch, scratch_bytes);
+    else run_locate<__bf16>(p, x, F, prec, mode, doa, power, yhat, margin, y_opt, s, scratch, scratch_bytes);
 }
 
 }  // namespace svdphat
