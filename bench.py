@@ -69,34 +69,58 @@ def _timed(fn, steps, torch):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(w, gold_doa, budget_s: float):
-    """The FP64 oracle timed on the host's cores on a bounded sample of the
-    same frames (its offline SVD is built first and timed separately)."""
-    import oracle
+def _cpu_model():
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count()
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, budget_s: float):
+    """The FP64 oracle timed on the host's cores on a bounded sample of the
+    same frames (its offline SVD is built first and timed separately): with
+    every core the BLAS uses, then on one core, and the plain SRP-PHAT oracle
+    on a few frames.  Returns (baseline dict, plan seconds, doa, margin) with
+    the oracle's answers for the frames it covered."""
+    import oracle
+    from threadpoolctl import threadpool_info, threadpool_limits
+    cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     t0 = time.perf_counter()
     log("oracle plan (FP64 SVD of W) ...")
     plan = oracle.make_plan(w["mics"], w["grid"], w["fs"], w["c"], w["N"], w["delta"])
     plan_s = time.perf_counter() - t0
-    log(f"oracle plan {plan_s:.1f} s; timing oracle.locate for {budget_s:.0f} s")
+    log(f"oracle plan {plan_s:.1f} s; timing oracle.locate for up to {budget_s:.0f} s")
     X = w["X"]
     done, chunk = 0, 256
     t0 = time.perf_counter()
-    doas = []
+    doas, margins = [], []
     while time.perf_counter() - t0 < budget_s and done < X.shape[0]:
         r = oracle.locate(plan, X[done:done + chunk])
         doas.append(r["doa"])
+        margins.append(r["margin"])
         done += r["doa"].shape[0]
     dt = time.perf_counter() - t0
-    doa = np.concatenate(doas)
-    return dict(value=done / dt, unit="frames/s", cores=int(cores), kind="oracle",
+    n1 = 256
+    with threadpool_limits(limits=1):
+        t1 = time.perf_counter()
+        oracle.locate(plan, X[:n1])
+        one_core = n1 / (time.perf_counter() - t1)
+    ns = 64
+    t1 = time.perf_counter()
+    oracle.srp_locate(plan, X[:ns])
+    srp_fps = ns / (time.perf_counter() - t1)
+    base = dict(value=done / dt, unit="frames/s", cores=int(cores), kind="oracle",
                 sample=f"first {done} of the {X.shape[0]} frames, FP64 numpy/LAPACK oracle.locate "
                        f"(PHAT, Z = S V^H X, Y = Re(U Z), argmax, row power); offline SVD "
-                       f"{plan_s:.1f} s excluded"), plan_s, doa
+                       f"{plan_s:.1f} s excluded",
+                one_core_fps=one_core, one_core_sample=f"first {n1} frames, BLAS limited to 1 thread",
+                srp_oracle_fps=srp_fps, srp_oracle_sample=f"first {ns} frames, oracle.srp_locate (eq. (9)), "
+                                                          f"{cores} threads",
+                cpu_model=_cpu_model(), os_cpu_count=os.cpu_count())
+    return base, plan_s, np.concatenate(doas), np.concatenate(margins)
 
 
 def main():
@@ -109,7 +133,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--workload", default="planar_q10242",
-                    help="planar_q10242 (default, the headline line), ragged256 or proposal_q40962")
+                    help="planar_q10242 (default, the headline line), cube_q10242, cube_q40962, ragged256 "
+                         "or proposal_q40962")
+    ap.add_argument("--batches", default="1,256,4096", help="batch sizes of the cube workloads")
     ap.add_argument("--train-frames", type=int, default=2_000_000, help="training pairs of the proposal")
     ap.add_argument("--train-epochs", type=int, default=1, help="passes over the proposal's training pairs")
     ap.add_argument("--arrays", type=int, default=256, help="arrays of the ragged workload")
@@ -133,6 +159,8 @@ def main():
         return bench_ragged(args, torch, amd, synth)
     if args.workload == "proposal_q40962":
         return bench_proposal(args, torch, amd, synth)
+    if args.workload in ("cube_q10242", "cube_q40962"):
+        return bench_cube(args, torch, amd, synth)
     if args.calib_copy_mb:
         n = args.calib_copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -257,9 +285,30 @@ def main():
         roof = dict(bound="hbm", achieved=algo / dur / 1e9, peak=HBM_PEAK_GBS, unit="GB/s", traffic=None)
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["kernel"] = dom
+    # both GEMMs against the dense FP16 MFMA peak (algorithmic flops:
+    # 2 x 2K x 2L per frame for GEMM1, 2 x classes x 2K for GEMM2)
+    mfma_fracs = {}
+    for k, fl in (("gemm1", 2.0 * K2 * 2 * L * F), ("gemm2", 2.0 * ncls * K2 * F)):
+        if k in kernels:
+            tf = fl / (kernels[k]["avg_us"] * 1e-6) / 1e12
+            mfma_fracs[k] = dict(tflops=tf, peak=MFMA_FP16_PEAK_TFLOPS, frac=tf / MFMA_FP16_PEAK_TFLOPS)
+
+    # reduced powers of every direction for the stored oracle rows, per form
+    # (the whole batch in one call, y_opt out)
+    gold = dict(np.load(os.path.join(ROOT, "tests", "golden", "planar_q10242_oracle.npz")))
+    rows = torch.from_numpy(gold["y_rows"]).to(dev)
+    yref = gold["y"].astype(np.float64)
+    yerr = {}
+    yopt = torch.empty((F, info["Q"]), dtype=torch.float32, device=dev)
+    for name, (prec, mode) in forms.items():
+        amd.svdphat_locate(h, X, prec, mode, doa, power, yhat, margin, yopt)
+        yv = yopt.index_select(0, rows).cpu().numpy().astype(np.float64)
+        e = np.max(np.abs(yv - yref), axis=1) / np.max(np.abs(yref), axis=1)
+        yerr[name] = dict(max=float(e.max()), mean=float(e.mean()), frames=int(len(e)))
+    del yopt
+    torch.cuda.synchronize()
 
     # accuracy against the stored FP64 oracle answers (first frames)
-    gold = dict(np.load(os.path.join(ROOT, "tests", "golden", "planar_q10242_oracle.npz")))
     n = min(int(gold["frames"]), F)
     judged = gold["margin"][:n] > 1e-5
     acc = {}
@@ -273,7 +322,16 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu, oracle_plan_s, _ = cpu_baseline(w, gold["doa"], args.cpu_budget)
+        cpu, oracle_plan_s, odoa, omargin = cpu_baseline(w, args.cpu_budget)
+        # every frame the oracle covered (all of them within the budget)
+        m = len(odoa)
+        jm = omargin > 1e-5
+        for name in forms:
+            d = results[name]["doa"][:m]
+            acc[name]["oracle_frames"] = m
+            acc[name]["match_all_frames"] = float(np.mean(d == odoa))
+            acc[name]["match_judged_all_frames"] = float(np.mean(d[jm] == odoa[jm]))
+            acc[name]["judged_share"] = float(np.mean(jm))
 
     head = results["fp16"]
     out = {
@@ -293,11 +351,13 @@ def main():
                    "K": info["K"], "n_classes": ncls, "N": info["N"], "frames_per_step": F,
                    "delta": w["delta"], "form": "FP16 MFMA, FP32 accumulate, FP32 rescoring, hi/lo fallback"},
         "roofline": roof,
+        "mfma_fracs": mfma_fracs,
         "cpu_baseline": cpu,
         "plain_fp32_srp_fps": srp_fps,
         "speedup_vs_plain_fp32": head["fps"] / srp_fps,
         "forms_fps": {k: v["fps"] for k, v in results.items()},
         "argmax_match": acc,
+        "y_error": yerr,
         "kernels_us": kernels,
         "kernels_srp_us": kernels_srp,
         "per_frame_counts": counts,
@@ -306,6 +366,133 @@ def main():
     }
     if cpu is not None:
         out["oracle_plan_s"] = oracle_plan_s
+    print(json.dumps(out))
+
+
+def bench_cube(args, torch, amd, synth):
+    """The 3-D 7-microphone array of Table 2 (two simultaneous white-noise
+    sources per 100-frame segment) at Q = 10242 or 40962, BF16 with FP32
+    rescoring, at several batch sizes.  Batch 1 is the streaming use: one
+    svdphat_locate call per frame, timed as a host loop of calls and as the
+    same calls captured once into a HIP graph and replayed (the launch
+    overhead of the host loop removed).  Accuracy against the stored FP64
+    oracle answers of the first frames."""
+    name = args.workload
+    frames = 40960
+    w = synth.workload(name, frames=frames)
+    t0 = time.perf_counter()
+    plan = amd.Plan(w["mics"], w["grid"], w["fs"], w["c"], w["N"], w["delta"])
+    plan_s = time.perf_counter() - t0
+    info = plan.info
+    log(f"{name}: plan {plan_s:.1f} s, K={info['K']}, classes={info['n_classes']}")
+    X = torch.from_numpy(w["X"]).cuda()
+    F = X.shape[0]
+    dev = X.device
+    doa = torch.empty(F, dtype=torch.int32, device=dev)
+    power = torch.empty(F, dtype=torch.float32, device=dev)
+    yhat = torch.empty(F, dtype=torch.float32, device=dev)
+    margin = torch.empty(F, dtype=torch.float32, device=dev)
+    h = plan.handle
+    prec, mode = amd.BF16, amd.RESCORE
+    gold = dict(np.load(os.path.join(ROOT, "tests", "golden", f"{name}_oracle.npz")))
+    ng = int(gold["frames"])
+    K2, L, ncls = 2 * info["K"], info["L"], info["n_classes"]
+    out = {"metric": f"frames/s, 3-D array, Q={info['Q']}, BF16 + FP32 rescoring", "unit": "frames/s",
+           "n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+           "data": "synthetic",
+           "config": {"workload": name, "array": "3-D 7-mic (Table 2)", "Q": info["Q"], "K": info["K"],
+                      "n_classes": ncls, "N": info["N"], "frames": F, "sources": 2},
+           "plan_build_s": plan_s, "batches": {}}
+    for B in [int(b) for b in args.batches.split(",")]:
+        if B == 1:
+            n1 = 2048
+            sl = [X[f:f + 1] for f in range(n1)]
+            outs = [(doa[f:f + 1], power[f:f + 1], yhat[f:f + 1], margin[f:f + 1]) for f in range(n1)]
+
+            def loop():
+                for f in range(n1):
+                    amd.svdphat_locate(h, sl[f], prec, mode, *outs[f])
+            _timed(loop, 1, torch)
+            dt = _timed(loop, 2, torch) / 2
+            host_fps = n1 / dt
+            # the same n1 calls captured once into a graph on a side stream
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                for f in range(n1):
+                    amd.svdphat_locate(h, sl[f], prec, mode, *outs[f], stream=s)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                for f in range(n1):
+                    amd.svdphat_locate(h, sl[f], prec, mode, *outs[f], stream=s)
+            g.replay()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 5
+            e0.record()
+            for _ in range(reps):
+                g.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            us = 1e3 * e0.elapsed_time(e1) / (reps * n1)
+            del g
+            # per-kernel durations (HIP events around each launch)
+            amd.svdphat_timing_reset()
+            amd.svdphat_timing_enable(True)
+            for f in range(256):
+                amd.svdphat_locate(h, sl[f], prec, mode, *outs[f])
+            amd.svdphat_timing_enable(False)
+            kt = amd.svdphat_timing_read()
+            amd.svdphat_timing_reset()
+            kern = {k: dict(avg_us=1e3 * v[0] / v[1], launches=v[1]) for k, v in kt.items()}
+            # bytes a frame reads if the FP32 operands are not cached: A (2K x 2L)
+            # and U (classes x 2K), and the frame
+            op_bytes = K2 * 2 * L * 4 + ncls * K2 * 4 + info["M"] * info["B"] * 8
+            r = dict(form="GEMV form, FP32 projections, exact FP32 argmax", frames=n1,
+                     host_loop_fps=host_fps, graph_fps=1e6 / us, graph_us_per_frame=us, kernels_us=kern,
+                     operand_bytes_per_frame=op_bytes,
+                     operand_GBps_graph=op_bytes / (us * 1e-6) / 1e9, hbm_peak_GBps=HBM_PEAK_GBS)
+            d = doa[:n1].cpu().numpy()
+            m = min(n1, ng)
+        else:
+            nb = F // B
+            def step():
+                for i in range(nb):
+                    amd.svdphat_locate(h, X[i * B:(i + 1) * B], prec, mode, doa[i * B:(i + 1) * B],
+                                       power[i * B:(i + 1) * B], yhat[i * B:(i + 1) * B],
+                                       margin[i * B:(i + 1) * B])
+            _timed(step, 1, torch)
+            ns = max(2, args.steps // 10)
+            dt = _timed(step, ns, torch)
+            fps = nb * B * ns / dt
+            amd.svdphat_timing_reset()
+            amd.svdphat_timing_enable(True)
+            step()
+            amd.svdphat_timing_enable(False)
+            kt = amd.svdphat_timing_read()
+            amd.svdphat_timing_reset()
+            kern = {k: dict(avg_us=1e3 * v[0] / v[1], launches=v[1]) for k, v in kt.items()}
+            flops = 2.0 * K2 * 2 * L + 2.0 * ncls * K2
+            g1 = kern.get("gemm1", {}).get("avg_us")
+            g2 = kern.get("gemm2", {}).get("avg_us")
+            r = dict(form="BF16 MFMA, FP32 accumulate, FP32 rescoring", fps=fps, ms_per_batch=1e3 * dt / (ns * nb),
+                     kernels_us=kern,
+                     gemm1_mfma_frac=(2.0 * K2 * 2 * L * B / (g1 * 1e-6) / 1e12 / MFMA_FP16_PEAK_TFLOPS) if g1 else None,
+                     gemm2_mfma_frac=(2.0 * ncls * K2 * B / (g2 * 1e-6) / 1e12 / MFMA_FP16_PEAK_TFLOPS) if g2 else None,
+                     mflop_per_frame=flops / 1e6)
+            d = doa[:nb * B].cpu().numpy()
+            m = min(nb * B, ng)
+        judged = gold["margin"][:m] > 1e-5
+        r["match_all"] = float(np.mean(d[:m] == gold["doa"][:m]))
+        r["match_judged"] = float(np.mean(d[:m][judged] == gold["doa"][:m][judged]))
+        r["oracle_frames"] = m
+        out["batches"][str(B)] = r
+        log(f"batch {B}: {json.dumps(r)[:300]}")
+    head = out["batches"].get("4096") or next(iter(out["batches"].values()))
+    out["value"] = head.get("fps", head.get("graph_fps"))
+    out["steps"] = args.steps
+    out["warmup"] = args.warmup
     print(json.dumps(out))
 
 

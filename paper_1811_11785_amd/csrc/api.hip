@@ -87,7 +87,7 @@ static void free_plan(svdphat_plan* p) {
         if (p->Alo[i]) (void)hipFree(p->Alo[i]);
         if (p->Ufr[i]) (void)hipFree(p->Ufr[i]);
     }
-    void* bufs[] = {p->U32T, p->d_tkappa, p->d_sig, p->d_rows, p->d_rep, p->d_rowof, p->d_tauN, p->d_tauN_all, p->d_tauM_all, p->d_rowcls, p->d_pi, p->d_pj, p->Wfr};
+    void* bufs[] = {p->U32T, p->A32T, p->d_tkappa, p->d_sig, p->d_rows, p->d_rep, p->d_rowof, p->d_tauN, p->d_tauN_all, p->d_tauM_all, p->d_rowcls, p->d_pi, p->d_pj, p->Wfr};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (auto& kv : p->ws)

@@ -226,6 +226,7 @@ struct svdphat_plan {
     void* Ufr[3] = {nullptr, nullptr, nullptr};  // GEMM2 operand per precision
     float uscale[3] = {1.f, 1.f, 1.f};           // exact power-of-two scale of U per precision
     float* U32T = nullptr;                       // [ntile][Rp/4][QTILE][4] FP32 rescoring rows
+    float* A32T = nullptr;                       // [B P 2][Rp] FP32 A = S V^H, transposed (GEMV form)
     float* d_tkappa = nullptr;                   // [ntile] largest ||U_q|| of each tile
     float* d_sig = nullptr;                      // [Rp] singular value of each stacked row of Z
     int32_t* d_rows = nullptr;                   // [ncls] direction index of row
@@ -283,6 +284,14 @@ void launch_locate(svdphat_plan* p, const void* X, int64_t F, int prec, uint32_t
 void launch_srp(svdphat_plan* p, const void* X, int64_t F, int32_t* doa, float* power,
                 float* y_opt, hipStream_t s);
 void build_w_fp32_frags(svdphat_plan* p);
+// small batches in GEMV form (frame1.hip): at most GV_MAX_FRAMES frames,
+// FP32 projections, exact FP32 argmax; scratch of gv_scratch_bytes()
+constexpr int GV_MAX_FRAMES = 16;
+bool gv_applicable(const svdphat_plan* p, int64_t F);
+int gv_score_groups(const svdphat_plan* p);
+size_t gv_scratch_bytes(const svdphat_plan* p, int64_t F);
+void launch_gv(svdphat_plan* p, const float2* X, int64_t F, int32_t* doa, float* power, float* yhat, float* margin,
+               void* ws, hipStream_t s);
 void* ws_get(svdphat_plan* p, hipStream_t s, size_t bytes);
 // zero `bytes` (a multiple of 4) of device memory on stream s with a kernel,
 // so that a caller capturing the stream into a graph records a kernel node

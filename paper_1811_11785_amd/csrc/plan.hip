@@ -426,6 +426,26 @@ void build_plan(svdphat_plan* p, const double* mics, const double* grid) {
         pack_A<__bf16>(p, p->g1[P_BF16], bh, bl, true);
         upload(bh, &p->A[P_BF16], bytes);
         upload(bl, &p->Alo[P_BF16], bytes);
+        // FP32 rows of A = S V^H transposed for the GEMV form of small
+        // batches: [(b P + p) 2 + ri][Rp], stacked as in pack_A
+        std::vector<float> at((size_t)B * P * 2 * p->Rp, 0.f);
+        for (int bin = 0; bin < B; ++bin)
+            for (int pp = 0; pp < P; ++pp) {
+                const int64_t c = (int64_t)bin * P + pp;
+                for (int kk = 0; kk < K; ++kk) {
+                    const double vr = p->V[(c * K + kk) * 2], vi = p->V[(c * K + kk) * 2 + 1];
+                    const double ar = p->sigma[kk] * vr, ai = -p->sigma[kk] * vi;
+                    float* re = &at[(size_t)(c * 2) * p->Rp];
+                    float* im = &at[(size_t)(c * 2 + 1) * p->Rp];
+                    re[kk] = (float)ar;
+                    re[K + kk] = (float)ai;
+                    im[kk] = (float)(-ai);
+                    im[K + kk] = (float)ar;
+                }
+            }
+        void* d = nullptr;
+        upload(at, &d, bytes);
+        p->A32T = (float*)d;
     }
     // stacked U rows (FP32) of the scored directions
     std::vector<float> Ust((size_t)p->ncls_pad * p->Rp, 0.f);

@@ -1601,6 +1601,16 @@ void tune_time(svdphat_plan* p, int64_t F, int nsplit_want, int fch, double* us_
 void launch_locate(svdphat_plan* p, const void* X, int64_t F, int prec, uint32_t mode, int32_t* doa, float* power,
                    float* yhat, float* margin, float* y_opt, hipStream_t s, void* scratch, size_t scratch_bytes) {
     const float2* x = (const float2*)X;
+    if (!y_opt && gv_applicable(p, F)) {
+        // a few frames: GEMV form in FP32 (frame1.hip), on the caller's
+        // scratch buffer or the plan's workspace of this stream
+        const size_t need = gv_scratch_bytes(p, F);
+        if (scratch)
+            SP_REQUIRE(need <= scratch_bytes, SVDPHAT_E_INVAL, "scratch memory too small for this call");
+        void* w = scratch ? scratch : ws_get(p, s, need);
+        launch_gv(p, x, F, doa, power, yhat, margin, w, s);
+        return;
+    }
     if (prec == P_FP32) run_locate<float>(p, x, F, prec, mode, doa, power, yhat, margin, y_opt, s, scratch, scratch_bytes);
     else if (prec == P_FP16)
         run_locate<_Float16>(p, x, F, prec, mode, doa, power, yhat, margin, y_opt, s, scratch, scratch_bytes);

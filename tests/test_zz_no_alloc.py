@@ -45,7 +45,7 @@ def test_noalloc_matches_locate(amd, torch, prec, mode):
     X = torch.from_numpy(X).cuda()
     m = amd.RESCORE | (amd.HILO if mode == "hilo" else 0)
     P = amd.PRECISIONS[prec]
-    for F in (1300, 301):
+    for F in (1300, 301, 9):
         Xf = X[:F].contiguous()
         ref = _outs(torch, F)
         got = _outs(torch, F)
