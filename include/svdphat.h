@@ -43,6 +43,7 @@ extern "C" {
 #define SVDPHAT_E_NUMERIC      -4  /* eigensolver failure or non-finite factors */
 #define SVDPHAT_E_NODEV        -5  /* no usable GPU */
 #define SVDPHAT_E_UNSUPPORTED  -6  /* request not supported by this plan */
+#define SVDPHAT_E_IO           -7  /* a file could not be opened, read or written */
 
 /* ---- plan flags ------------------------------------------------------ */
 #define SVDPHAT_KEEP_W    0x1u  /* also store W in FP32 for svdphat_srp_locate */
@@ -84,6 +85,7 @@ typedef struct svdphat_info {
     double fro2;        /* ||W||_F^2 (= Q * L exactly in exact arithmetic) */
     double u_rownorm_max; /* max_q ||U_q||_2 over the kept rank */
     int64_t device_bytes;
+    uint64_t input_hash;  /* svdphat_plan_input_hash of the plan's inputs */
 } svdphat_info;
 
 /*
@@ -128,6 +130,32 @@ int svdphat_plan_info(const svdphat_plan* plan, svdphat_info* out);
  */
 int svdphat_plan_export(const svdphat_plan* plan, double* sigma, double* U,
                         double* V, int32_t* class_rep);
+
+/*
+ * svdphat_plan_save / svdphat_plan_load -- Algorithm 1 computes its offline
+ * products once per array and grid (Section 3); these keep them.  save
+ * writes the plan's inputs (microphones, grid as given, fs, c, N, delta,
+ * flags) and its truncated SVD (sigma, U, V, K, K_paper) to `path` in a
+ * versioned little-endian binary with a 64-bit FNV-1a hash of the inputs and
+ * a checksum of the file.  load reads such a file and builds a plan on the
+ * current HIP device without refactorising W: only the host geometry and
+ * the packing of the device operands are repeated, so every result of the
+ * loaded plan is identical to the saved one's.  Synchronous.
+ *   path  host, NUL-terminated file name.  out: receives the plan (NULL on
+ *         failure; the caller destroys it with svdphat_plan_destroy).
+ * Errors: E_IO (the file cannot be opened, read or written), E_INVAL (NULL
+ * arguments, not a plan file, another version, damaged file: checksum,
+ * input hash or sizes), E_NODEV, E_NOMEM, E_DEVICE.
+ * svdphat_plan_input_hash -- the hash a saved file records, from the inputs
+ * of svdphat_plan_create (host arrays; no device needed), so a caller can
+ * match a saved plan to its problem; svdphat_plan_info reports it too.
+ */
+int svdphat_plan_save(const svdphat_plan* plan, const char* path);
+int svdphat_plan_load(const char* path, svdphat_plan** out);
+uint64_t svdphat_plan_input_hash(const double* mic_xyz_m, int32_t M,
+                                 const double* grid_xyz, int32_t Q, double fs,
+                                 double c, int32_t N, double delta,
+                                 uint32_t flags);
 
 /*
  * svdphat_locate -- Algorithm 1 online steps 1-4 (Section 3) with the
@@ -257,6 +285,13 @@ void svdphat_ragged_destroy(svdphat_ragged* ragged);
  * svdphat_proposal_grad  testing aid: mean loss and its gradient (same layout)
  *   for host features [F][2K] and labels [F].
  * svdphat_proposal_cells  host [Q]: cell of every fine direction.
+ * svdphat_proposal_save  writes the coarse directions, the FP32 parameters,
+ *   the Adam moments and the step count, with the fine plan's input hash,
+ *   to `path` (versioned little-endian binary with a checksum).
+ * svdphat_proposal_load  reads such a file into a new proposal over `fine`,
+ *   which must have the same input hash as the plan the file was saved with
+ *   (E_INVAL otherwise); training can continue from the saved state.
+ *   Errors of both: E_IO, E_INVAL (as for plans), E_NOMEM, E_DEVICE.
  * svdphat_proposal_features  testing aid: the network input of F device frames
  *   X, written to device f32 [F][2K] (the FP16 values the network reads,
  *   widened); synchronous.  The columns follow the plan's singular vectors,
@@ -287,6 +322,9 @@ int svdphat_proposal_grad(svdphat_proposal* proposal, const float* features,
                           float* loss_host);
 int svdphat_proposal_cells(const svdphat_proposal* proposal,
                            int32_t* cell_of_direction);
+int svdphat_proposal_save(const svdphat_proposal* proposal, const char* path);
+int svdphat_proposal_load(svdphat_plan* fine, const char* path,
+                          svdphat_proposal** out);
 int svdphat_proposal_features(svdphat_proposal* proposal, const void* X,
                               int64_t F, float* feat, void* stream);
 int svdphat_proposal_apply_grad(svdphat_proposal* proposal, const float* grad,

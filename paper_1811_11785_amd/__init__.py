@@ -19,7 +19,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsvdphat.so")
 
-OK, E_INVAL, E_NOMEM, E_DEVICE, E_NUMERIC, E_NODEV, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_NUMERIC, E_NODEV, E_UNSUPPORTED, E_IO = 0, -1, -2, -3, -4, -5, -6, -7
 KEEP_W, NO_DEDUP = 0x1, 0x2
 FP32, BF16, FP16 = 0, 1, 2
 RESCORE, HILO, HILO_ALL = 0x1, 0x2, 0x4
@@ -39,7 +39,7 @@ class Info(C.Structure):
                 ("K_paper", C.c_int32), ("N", C.c_int32), ("has_w", C.c_int32),
                 ("residual", C.c_double), ("sigma1", C.c_double), ("sigmaK", C.c_double),
                 ("fro2", C.c_double), ("u_rownorm_max", C.c_double),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("input_hash", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -55,6 +55,12 @@ SIGNATURES = {
                                       C.c_double, C.c_int32, C.c_double, C.c_uint32,
                                       C.POINTER(C.c_void_p)]),
     "svdphat_plan_info": (C.c_int, [C.c_void_p, C.POINTER(Info)]),
+    "svdphat_plan_save": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "svdphat_plan_load": (C.c_int, [C.c_char_p, C.POINTER(C.c_void_p)]),
+    "svdphat_plan_input_hash": (C.c_uint64, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_double,
+                                             C.c_double, C.c_int32, C.c_double, C.c_uint32]),
+    "svdphat_proposal_save": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "svdphat_proposal_load": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_void_p)]),
     "svdphat_plan_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "svdphat_locate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_uint32,
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -283,14 +289,32 @@ def svdphat_ragged_destroy(ragged):
 
 
 # ------------------------------------------------------------ convenience
+def svdphat_plan_input_hash(mics, grid, fs, c, N, delta, flags=0) -> int:
+    mics = np.ascontiguousarray(mics, dtype=np.float64)
+    grid = np.ascontiguousarray(grid, dtype=np.float64)
+    return lib().svdphat_plan_input_hash(mics.ctypes.data, mics.shape[0], grid.ctypes.data, grid.shape[0],
+                                         float(fs), float(c), int(N), float(delta), int(flags))
+
+
 class Plan:
     """Offline plan (Algorithm 1, offline) and online search on device tensors."""
 
     def __init__(self, mics, grid, fs=16000.0, c=343.0, N=512, delta=1e-5, keep_w=False,
-                 dedup=True):
-        flags = (KEEP_W if keep_w else 0) | (0 if dedup else NO_DEDUP)
-        self._h = svdphat_plan_create(mics, grid, fs, c, N, delta, flags)
+                 dedup=True, _handle=None):
+        if _handle is None:
+            flags = (KEEP_W if keep_w else 0) | (0 if dedup else NO_DEDUP)
+            _handle = svdphat_plan_create(mics, grid, fs, c, N, delta, flags)
+        self._h = _handle
         self.info = svdphat_plan_info(self._h)
+
+    def save(self, path):
+        _check(lib().svdphat_plan_save(self._h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path):
+        out = C.c_void_p()
+        _check(lib().svdphat_plan_load(os.fsencode(path), C.byref(out)))
+        return cls(None, None, _handle=out)
 
     @property
     def handle(self):
@@ -377,14 +401,30 @@ class Ragged:
 class Proposal:
     """Learned coarse-cell proposal over a fine plan (see svdphat.h)."""
 
-    def __init__(self, plan, coarse, hidden=256, seed=0):
+    def __init__(self, plan, coarse, hidden=256, seed=0, _handle=None):
         self.plan = plan
-        coarse = np.ascontiguousarray(coarse, dtype=np.float64)
-        self.C = coarse.shape[0]
+        if _handle is None:
+            coarse = np.ascontiguousarray(coarse, dtype=np.float64)
+            self.C = coarse.shape[0]
+            out = C.c_void_p()
+            _check(lib().svdphat_proposal_create(plan.handle, coarse.ctypes.data, self.C, hidden, seed,
+                                                 C.byref(out)))
+            self._h = out
+        else:
+            self._h = _handle
+            self.C = coarse
+
+    def save(self, path):
+        _check(lib().svdphat_proposal_save(self._h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, plan, path):
+        """A proposal saved over a plan with the same inputs as `plan`."""
         out = C.c_void_p()
-        _check(lib().svdphat_proposal_create(plan.handle, coarse.ctypes.data, self.C, hidden, seed,
-                                             C.byref(out)))
-        self._h = out
+        _check(lib().svdphat_proposal_load(plan.handle, os.fsencode(path), C.byref(out)))
+        obj = cls(plan, None, _handle=out)
+        obj.C = None
+        return obj
 
     def train_step(self, X, lr=1e-3, stream=None):
         loss = C.c_float()

@@ -105,7 +105,6 @@ static void require_device() {
     }
 }
 
-void build_plan(svdphat_plan* p, const double* mics, const double* grid);
 
 // ------------------------------------------------ allocation-free locate
 // Intermediate results of svdphat_locate_noalloc live in this file-scope
@@ -236,13 +235,35 @@ int svdphat_plan_create(const double* mic_xyz_m, int32_t M, const double* grid_x
         p->delta = delta;
         p->flags = flags;
         try {
-            build_plan(p, mic_xyz_m, grid_xyz);
+            build_plan(p, mic_xyz_m, grid_xyz, false);
         } catch (...) {
             free_plan(p);
             throw;
         }
         *out = p;
     });
+}
+
+int svdphat_plan_save(const svdphat_plan* p, const char* path) {
+    return guarded([&] {
+        SP_REQUIRE(p && path, SVDPHAT_E_INVAL, "NULL plan or path");
+        plan_save(p, path);
+    });
+}
+
+int svdphat_plan_load(const char* path, svdphat_plan** out) {
+    return guarded([&] {
+        SP_REQUIRE(out != nullptr, SVDPHAT_E_INVAL, "out is NULL");
+        *out = nullptr;
+        SP_REQUIRE(path != nullptr, SVDPHAT_E_INVAL, "NULL path");
+        *out = plan_load(path, free_plan);
+    });
+}
+
+uint64_t svdphat_plan_input_hash(const double* mic_xyz_m, int32_t M, const double* grid_xyz, int32_t Q, double fs,
+                                 double c, int32_t N, double delta, uint32_t flags) {
+    if (!mic_xyz_m || !grid_xyz || M < 0 || Q < 0) return 0;
+    return plan_input_hash(mic_xyz_m, M, grid_xyz, Q, fs, c, N, delta, flags);
 }
 
 int svdphat_plan_info(const svdphat_plan* p, svdphat_info* o) {
@@ -265,6 +286,8 @@ int svdphat_plan_info(const svdphat_plan* p, svdphat_info* o) {
         o->fro2 = p->fro2;
         o->u_rownorm_max = p->kappa;
         o->device_bytes = p->device_bytes;
+        o->input_hash = plan_input_hash(p->mics_in.data(), p->M, p->grid_in.data(), p->Q, p->fs, p->c, p->N,
+                                        p->delta, p->flags);
     });
 }
 
@@ -457,6 +480,25 @@ int svdphat_proposal_grad(svdphat_proposal* pr, const float* features, const int
         SP_HIP(hipSetDevice(pr->plan->device));
         const float l = proposal_grad(pr, features, labels, F, grad);
         if (loss_host) *loss_host = l;
+    });
+}
+
+int svdphat_proposal_save(const svdphat_proposal* pr, const char* path) {
+    return guarded([&] {
+        SP_REQUIRE(pr && path, SVDPHAT_E_INVAL, "NULL proposal or path");
+        SP_HIP(hipSetDevice(pr->plan->device));
+        proposal_save(pr, path);
+    });
+}
+
+int svdphat_proposal_load(svdphat_plan* fine, const char* path, svdphat_proposal** out) {
+    return guarded([&] {
+        SP_REQUIRE(out != nullptr, SVDPHAT_E_INVAL, "out is NULL");
+        *out = nullptr;
+        SP_REQUIRE(fine && path, SVDPHAT_E_INVAL, "NULL plan or path");
+        SP_REQUIRE(!(fine->flags & SVDPHAT_NO_DEDUP), SVDPHAT_E_UNSUPPORTED,
+                   "the proposal needs a plan with one scored row per class");
+        *out = proposal_load(fine, path);
     });
 }
 

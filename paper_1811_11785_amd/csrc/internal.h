@@ -180,6 +180,8 @@ void proposal_locate(svdphat_proposal* pr, const float2* X, int64_t F, int topk,
                      float* power, uint8_t* fell, hipStream_t s);
 int64_t proposal_nparams(const svdphat_proposal* pr);
 void proposal_params(svdphat_proposal* pr, float* host, bool set);
+// parameters, Adam moments (host layout of proposal_params) and step count
+void proposal_state(svdphat_proposal* pr, float* params, float* m, float* v, int64_t* step, bool set);
 float proposal_grad(svdphat_proposal* pr, const float* feat, const int32_t* lab, int64_t F, float* grad);
 void proposal_features(svdphat_proposal* pr, const float2* X, int64_t F, float* feat, hipStream_t s);
 void proposal_apply_grad(svdphat_proposal* pr, const float* grad, float lr);
@@ -209,6 +211,7 @@ struct svdphat_plan {
     std::vector<double> tau;     // [Q][P] delays in samples, eq. (2)
     std::vector<double> tauM;    // [Q][M] per-microphone delays in samples
     std::vector<double> grid;    // [Q][3] unit directions
+    std::vector<double> mics_in, grid_in;  // the inputs as given (M x 3, Q x 3)
     std::vector<int32_t> rep;    // [Q] class representative
     std::vector<int32_t> rows;   // [ncls] direction index of each scored row
     std::vector<double> sigma;   // all singular values, descending
@@ -252,6 +255,7 @@ struct svdphat_proposal {
     svdphat_plan* plan = nullptr;
     int C = 0, Cp = 0, H = 0, D = 0, D0 = 0;  // cells, padded cells, hidden, input (2K), padded input (Rp)
     std::vector<int32_t> cell_of_dir;         // [Q]
+    std::vector<double> coarse;               // [C][3] coarse directions as given
     int32_t* d_cell_of_dir = nullptr;         // [Q]
     int32_t* d_cell_start = nullptr;          // [C + 1] CSR over scored rows
     int32_t* d_cell_rows = nullptr;           // [ncls]
@@ -284,6 +288,17 @@ void launch_locate(svdphat_plan* p, const void* X, int64_t F, int prec, uint32_t
 void launch_srp(svdphat_plan* p, const void* X, int64_t F, int32_t* doa, float* power,
                 float* y_opt, hipStream_t s);
 void build_w_fp32_frags(svdphat_plan* p);
+// Algorithm 1 offline: geometry, classes, then (unless `factored`: sigma, U,
+// V, K, K_paper, fro2 and residual already set, e.g. from a saved plan) the
+// truncated SVD, then the packing of the device operands
+void build_plan(svdphat_plan* p, const double* mics, const double* grid, bool factored);
+// persistence (persist.cpp)
+void plan_save(const svdphat_plan* p, const char* path);
+svdphat_plan* plan_load(const char* path, void (*destroy)(svdphat_plan*));
+uint64_t plan_input_hash(const double* mics, int M, const double* grid, int Q, double fs, double c, int N,
+                         double delta, uint32_t flags);
+void proposal_save(const svdphat_proposal* pr, const char* path);
+svdphat_proposal* proposal_load(svdphat_plan* fine, const char* path);
 // small batches in GEMV form (frame1.hip): at most GV_MAX_FRAMES frames,
 // FP32 projections, exact FP32 argmax; scratch of gv_scratch_bytes()
 constexpr int GV_MAX_FRAMES = 16;

@@ -212,7 +212,7 @@ static void direction_classes(const std::vector<double>& tau, int Q, int P, doub
     }
 }
 
-void build_plan(svdphat_plan* p, const double* mics, const double* grid) {
+void build_plan(svdphat_plan* p, const double* mics, const double* grid, bool factored) {
     const int M = p->M, Q = p->Q, N = p->N;
     const int P = M * (M - 1) / 2, B = N / 2 + 1;
     const int64_t L = (int64_t)P * B;
@@ -288,8 +288,13 @@ void build_plan(svdphat_plan* p, const double* mics, const double* grid) {
     p->ncls = (int)p->rows.size();
     p->ncls_pad = round_up(p->ncls, 256);
 
-    // ---- eqs. (4), (8): W in FP64 on the device (column-major Q x L)
+    p->mics_in.assign(mics, mics + 3 * (size_t)M);
+    p->grid_in.assign(grid, grid + 3 * (size_t)Q);
     SP_HIP(hipSetDevice(p->device));
+    // the factors (sigma, U, V, K, K_paper, fro2, residual) of a saved plan
+    // are given; otherwise Algorithm 1 offline steps 1-2 compute them
+    if (!factored) {
+    // ---- eqs. (4), (8): W in FP64 on the device (column-major Q x L)
     RB rb;
     rb_check(rocblas_create_handle(&rb.h), "rocblas_create_handle");
     DevBuf<double> d_tau;
@@ -404,8 +409,10 @@ void build_plan(svdphat_plan* p, const double* mics, const double* grid) {
         if (!std::isfinite(v)) fail(SVDPHAT_E_NUMERIC, "non-finite U");
     for (double v : p->V)
         if (!std::isfinite(v)) fail(SVDPHAT_E_NUMERIC, "non-finite V");
+    }
 
     // ---- packing
+    const int K = p->K;
     p->R = 2 * K;
     p->Rp = round_up(p->R, 32);
     if (p->Rp > 1024) fail(SVDPHAT_E_UNSUPPORTED, "rank K above 512 is not supported");

@@ -639,6 +639,7 @@ void cast_weights(svdphat_proposal* pr, hipStream_t s) {
 void proposal_build(svdphat_proposal* pr, const double* coarse, int C, int H, uint64_t seed) {
     svdphat_plan* p = pr->plan;
     pr->C = C;
+    pr->coarse.assign(coarse, coarse + 3 * (size_t)C);
     pr->Cp = round_up(C, 64);
     pr->H = H;
     pr->D = 2 * p->K;
@@ -793,10 +794,12 @@ int64_t proposal_nparams(const svdphat_proposal* pr) {
     return H * D + H + H * H + H + C * H + C;
 }
 
-void proposal_params(svdphat_proposal* pr, float* host, bool set) {
+// one flat device array (parameters or an Adam moment) to or from the host
+// layout W1 [H][D], b1 [H], W2 [H][H], b2 [H], W3 [C][H], b3 [C]
+static void proposal_xfer(svdphat_proposal* pr, float* dev, float* host, bool set) {
     const int H = pr->H, D = pr->D, D0 = pr->D0, C = pr->C;
     std::vector<float> P(pr->nparam);
-    SP_HIP(hipMemcpy(P.data(), pr->P, sizeof(float) * pr->nparam, hipMemcpyDeviceToHost));
+    SP_HIP(hipMemcpy(P.data(), dev, sizeof(float) * pr->nparam, hipMemcpyDeviceToHost));
     int64_t h = 0;
     auto xfer = [&](int64_t dst, int rows, int cols, int ld) {
         for (int r = 0; r < rows; ++r)
@@ -811,11 +814,23 @@ void proposal_params(svdphat_proposal* pr, float* host, bool set) {
     xfer(pr->off[3], 1, H, H);
     xfer(pr->off[4], C, H, H);
     xfer(pr->off[5], 1, C, C);
+    if (set) SP_HIP(hipMemcpy(dev, P.data(), sizeof(float) * pr->nparam, hipMemcpyHostToDevice));
+}
+
+void proposal_params(svdphat_proposal* pr, float* host, bool set) {
+    proposal_xfer(pr, pr->P, host, set);
     if (set) {
-        SP_HIP(hipMemcpy(pr->P, P.data(), sizeof(float) * pr->nparam, hipMemcpyHostToDevice));
         cast_weights(pr, nullptr);
         SP_HIP(hipDeviceSynchronize());
     }
+}
+
+void proposal_state(svdphat_proposal* pr, float* params, float* m, float* v, int64_t* step, bool set) {
+    proposal_xfer(pr, pr->Mm, m, set);
+    proposal_xfer(pr, pr->Vv, v, set);
+    proposal_params(pr, params, set);
+    if (set) pr->step = *step;
+    else *step = pr->step;
 }
 
 // gradient of the mean cross-entropy for host features [F][D] and labels,
