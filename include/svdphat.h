@@ -65,6 +65,14 @@ extern "C" {
 #define SVDPHAT_HILO_ALL 0x4u /* the hi/lo pass for every frame, whatever
                                  its margin (implies SVDPHAT_HILO; with
                                  FP32 operands there is no hi/lo pass) */
+#define SVDPHAT_NORMALIZED 0x8u /* the search of eq. (15) (Section 3):
+                                 maximise Re{D^_q Z^} with D^_q = D_q /
+                                 ||D_q||, D_q = U_q S, i.e. minimise the
+                                 distance ||D^_q - Z^^H||_2 between unit
+                                 vectors, instead of Re{D_q Z} of eq. (14);
+                                 yhat, margin and y_opt then hold
+                                 Re{D_q Z} / ||D_q||, power stays the row
+                                 power of the chosen direction */
 
 typedef struct svdphat_plan svdphat_plan;
 
@@ -163,7 +171,8 @@ uint64_t svdphat_plan_input_hash(const double* mic_xyz_m, int32_t M,
  *   X          device, complex64 [F][M][N/2+1] STFT frames.
  *   F          number of frames, >= 0 (0 is a no-op).
  *   precision  SVDPHAT_FP32 | SVDPHAT_BF16 | SVDPHAT_FP16.
- *   mode       SVDPHAT_RESCORE | SVDPHAT_HILO | SVDPHAT_HILO_ALL.
+ *   mode       SVDPHAT_RESCORE | SVDPHAT_HILO | SVDPHAT_HILO_ALL |
+ *              SVDPHAT_NORMALIZED.
  *   doa        device, int32 [F]: class-lowest index of argmax_q Y_q.
  *   power      device, f32 [F]: Y at doa from the row of W (step 4, eq. (9)).
  *   yhat       device, f32 [F] or NULL: the reduced power Re{D_q Z} at doa.
@@ -204,6 +213,26 @@ int svdphat_locate_noalloc(svdphat_plan* plan, const void* X, int64_t F,
                            void* stream);
 /* svdphat_noalloc_scratch_bytes -- size of the array above, in bytes. */
 int64_t svdphat_noalloc_scratch_bytes(void);
+
+/*
+ * svdphat_locate_masked -- svdphat_locate on the cross-spectra of eq. (7)
+ * with a binary time-frequency mask applied: the paper names masks (and
+ * several sources) as future work in Section 5.  Every pair's x_{p,k} is set
+ * to 0 at the bins a frame's mask drops, for the search and for the row
+ * power of Algorithm 1 step 4 alike.
+ *   mask   device, uint8 [F][N/2+1]: nonzero keeps bin k of frame f, 0 drops
+ *          it (a frame with every bin dropped has every power 0 and returns
+ *          the lowest index, as a silent frame does).
+ *   The other arguments are those of svdphat_locate.  The masked frames are
+ *   written to a second workspace of the plan and stream (F (N/2+1) M 8
+ *   bytes), which is grown on demand like the first.
+ * Errors: as svdphat_locate; E_INVAL also for a NULL mask with F > 0.
+ */
+int svdphat_locate_masked(svdphat_plan* plan, const void* X, int64_t F,
+                          const uint8_t* mask, int32_t precision,
+                          uint32_t mode, int32_t* doa, float* power,
+                          float* yhat, float* margin, float* y_opt,
+                          void* stream);
 
 /*
  * svdphat_srp_locate -- plain SRP-PHAT, eqs. (3), (9), (6), in FP32.

@@ -29,7 +29,7 @@ from .svdphat import (  # noqa: F401
     mic_pairs, tdoa_farfield, steering_matrix, phat_vector, srp_phat_power,
     truncated_svd, choose_rank, svd_phat_power, direction_classes,
     argmax_with_margin, exact_power, OraclePlan, make_plan, locate,
-    srp_locate, dirichlet_power, stacked_projection,
+    srp_locate, dirichlet_power, stacked_projection, normalized_locate, apply_mask,
 )
 from .stft import stft, stft_frames, sine_window, dft_matrix  # noqa: F401
 from .rmse import doa_map, rmse_alpha  # noqa: F401

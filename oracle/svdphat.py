@@ -55,6 +55,17 @@ def phat_vector(X: np.ndarray) -> np.ndarray:
     return x.reshape(F, len(pairs) * B)
 
 
+def apply_mask(x: np.ndarray, mask, B: int) -> np.ndarray:
+    """Binary time-frequency mask (Section 5 names masks as future work):
+    x [F, P*B] of eq. (7) with every pair's value at bin k of frame f set to
+    0 where mask[f, k] == 0.  mask None leaves x unchanged."""
+    if mask is None:
+        return x
+    F = x.shape[0]
+    m = (np.asarray(mask)[:F] != 0).astype(x.real.dtype)
+    return (x.reshape(F, -1, B) * m[:, None, :]).reshape(F, -1)
+
+
 def srp_phat_power(W: np.ndarray, x: np.ndarray) -> np.ndarray:
     """SRP-PHAT powers, eq. (9): Y = Re{W X}, for a batch x [F, L] -> [F, Q]."""
     return np.real(x @ W.T)
@@ -197,12 +208,14 @@ def make_plan(mics, grid, fs, c, N, delta, keep_all=False) -> OraclePlan:
                       delta, tau, W, U, s, Vh, Kp, K, rep)
 
 
-def locate(plan: OraclePlan, X: np.ndarray, chunk: int = 256):
-    """Algorithm 1, online steps 1-4 with the brute-force search of eq. (14).
+def locate(plan: OraclePlan, X: np.ndarray, chunk: int = 256, mask=None):
+    """Algorithm 1, online steps 1-4 with the brute-force search of eq. (14),
+    on x masked by ``mask`` [F, N/2+1] (apply_mask) if given.
     Returns dict(doa, power, yhat, margin, y)."""
     out = {k: [] for k in ("doa", "power", "yhat", "margin", "y")}
+    B = plan.N // 2 + 1
     for a in range(0, X.shape[0], chunk):
-        x = phat_vector(X[a:a + chunk])
+        x = apply_mask(phat_vector(X[a:a + chunk]), None if mask is None else mask[a:a + chunk], B)
         y = svd_phat_power(plan.U, plan.s, plan.Vh, x)
         qbar, y1, m = argmax_with_margin(y, plan.rep)
         out["doa"].append(qbar)
@@ -214,17 +227,54 @@ def locate(plan: OraclePlan, X: np.ndarray, chunk: int = 256):
     return {k: np.concatenate(v) for k, v in out.items()}
 
 
-def srp_locate(plan: OraclePlan, X: np.ndarray, chunk: int = 64, W: np.ndarray | None = None):
-    """Plain SRP-PHAT, eqs. (3), (9) and (6).  Returns dict(doa, power,
-    margin, y)."""
+def srp_locate(plan: OraclePlan, X: np.ndarray, chunk: int = 64, W: np.ndarray | None = None, mask=None):
+    """Plain SRP-PHAT, eqs. (3), (9) and (6), on x masked by ``mask`` if
+    given.  Returns dict(doa, power, margin, y)."""
     W = plan.W if W is None else W
     out = {k: [] for k in ("doa", "power", "margin", "y")}
+    B = plan.N // 2 + 1
     for a in range(0, X.shape[0], chunk):
-        x = phat_vector(X[a:a + chunk])
+        x = apply_mask(phat_vector(X[a:a + chunk]), None if mask is None else mask[a:a + chunk], B)
         y = srp_phat_power(W, x)
         qbar, y1, m = argmax_with_margin(y, plan.rep)
         out["doa"].append(qbar)
         out["power"].append(y1)
         out["margin"].append(m)
         out["y"].append(y)
+    return {k: np.concatenate(v) for k, v in out.items()}
+
+
+def normalized_locate(plan: OraclePlan, X: np.ndarray, chunk: int = 256, mask=None):
+    """The search of eq. (15), Section 3: with D = U S (eq. (13)), unit rows
+    D^_q = D_q / ||D_q|| and the unit projection Z^ = Z / ||Z|| (Z = V^H X,
+    eq. (12)), q_bar minimises ||D^_q - Z^^H||^2 over the directions (lowest
+    index on exact ties, then the class representative), which equals
+    maximising 1 - ||D^_q - Z^^H||^2 / 2 = Re(D^_q . Z^).  For Z = 0 (a
+    silent frame) Z^ is undefined and every direction ties.  Returns
+    dict(doa, score, margin, yhat, power): score the normalised value at
+    q_bar, margin (s1 - s2) / |s1| to the best other class, yhat =
+    ||Z|| score = Re(D_q Z) / ||D_q|| at q_bar, power the row power of
+    Algorithm 1 online step 4."""
+    K = plan.K
+    D = plan.U * plan.s[:K][None, :]
+    Dn = D / np.linalg.norm(D, axis=1, keepdims=True)
+    out = {k: [] for k in ("doa", "score", "margin", "yhat", "power")}
+    B = plan.N // 2 + 1
+    for a in range(0, X.shape[0], chunk):
+        x = apply_mask(phat_vector(X[a:a + chunk]), None if mask is None else mask[a:a + chunk], B)
+        Z = x @ plan.Vh.T                              # [F, K] = (V^H X)^T
+        zn = np.linalg.norm(Z, axis=1)
+        Zh = Z / np.where(zn > 0, zn, 1.0)[:, None]
+        # squared distance between D^_q and the conjugate of Z^ (the row Z^^H)
+        d2 = np.stack([np.sum(np.abs(Dn - np.conj(z)[None, :]) ** 2, axis=1) for z in Zh])
+        score = 1.0 - 0.5 * d2
+        # Z = 0 (a silent or fully masked frame): Z^ is undefined and every
+        # direction is equally near; they tie exactly (lowest index wins)
+        score[zn == 0] = 0.5
+        qbar, s1, m = argmax_with_margin(score, plan.rep)
+        out["doa"].append(qbar)
+        out["score"].append(s1)
+        out["margin"].append(m)
+        out["yhat"].append(zn * s1)
+        out["power"].append(np.array([exact_power(plan.tau[q], plan.N, xv) for q, xv in zip(qbar, x)]))
     return {k: np.concatenate(v) for k, v in out.items()}

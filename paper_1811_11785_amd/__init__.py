@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libsvdphat.so")
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NUMERIC, E_NODEV, E_UNSUPPORTED, E_IO = 0, -1, -2, -3, -4, -5, -6, -7
 KEEP_W, NO_DEDUP = 0x1, 0x2
 FP32, BF16, FP16 = 0, 1, 2
-RESCORE, HILO, HILO_ALL = 0x1, 0x2, 0x4
+RESCORE, HILO, HILO_ALL, NORMALIZED = 0x1, 0x2, 0x4, 0x8
 RAGGED_TUNE = 0x1
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16}
 
@@ -67,6 +67,8 @@ SIGNATURES = {
                                  C.c_void_p]),
     "svdphat_srp_locate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p]),
+    "svdphat_locate_masked": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_uint32,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "svdphat_locate_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_uint32,
                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "svdphat_noalloc_scratch_bytes": (C.c_int64, []),
@@ -320,10 +322,13 @@ class Plan:
     def handle(self):
         return self._h
 
-    def locate(self, X, precision="fp32", rescore=True, hilo=False, want_y=False, stream=None, hilo_all=False):
+    def locate(self, X, precision="fp32", rescore=True, hilo=False, want_y=False, stream=None, hilo_all=False,
+               normalized=False, mask=None):
         """X: complex64 CUDA tensor [F, M, N/2+1].  Returns a dict of device
         tensors doa (int32), power, yhat, margin (f32) and y ([F, Q]) if asked.
-        hilo_all: the hi/lo pass for every frame (16-bit precisions)."""
+        hilo_all: the hi/lo pass for every frame (16-bit precisions);
+        normalized: the search of eq. (15) instead of eq. (14); mask: uint8
+        CUDA tensor [F, N/2+1], the binary time-frequency mask (0 drops a bin)."""
         import torch
         assert X.is_cuda and X.dtype == torch.complex64 and X.is_contiguous()
         F = X.shape[0]
@@ -333,8 +338,16 @@ class Plan:
         yhat = torch.empty(F, dtype=torch.float32, device=dev)
         margin = torch.empty(F, dtype=torch.float32, device=dev)
         y = torch.empty((F, self.info["Q"]), dtype=torch.float32, device=dev) if want_y else None
-        mode = (RESCORE if rescore else 0) | (HILO if hilo else 0) | (HILO_ALL if hilo_all else 0)
-        svdphat_locate(self._h, X, PRECISIONS[precision], mode, doa, power, yhat, margin, y, stream)
+        mode = ((RESCORE if rescore else 0) | (HILO if hilo else 0) | (HILO_ALL if hilo_all else 0)
+                | (NORMALIZED if normalized else 0))
+        if mask is None:
+            svdphat_locate(self._h, X, PRECISIONS[precision], mode, doa, power, yhat, margin, y, stream)
+        else:
+            assert mask.is_cuda and mask.dtype == torch.uint8 and mask.is_contiguous()
+            assert tuple(mask.shape) == (F, self.info["B"])
+            _check(lib().svdphat_locate_masked(self._h, _ptr(X), F, _ptr(mask), PRECISIONS[precision], mode,
+                                               _ptr(doa), _ptr(power), _ptr(yhat), _ptr(margin), _ptr(y),
+                                               _stream(stream)))
         out = dict(doa=doa, power=power, yhat=yhat, margin=margin)
         if want_y:
             out["y"] = y

@@ -35,9 +35,9 @@ void fail(int code, const std::string& msg) { throw Error{code, msg}; }
 // is by at least 1.5x, so the kept buffers add at most twice the largest).
 // Growing while the stream is being captured is refused: a capture must be
 // preceded by one eager call of at least its size on the same stream.
-void* ws_get(svdphat_plan* p, hipStream_t s, size_t bytes) {
+void* ws_get(svdphat_plan* p, hipStream_t s, size_t bytes, int slot) {
     std::lock_guard<std::mutex> lk(p->ws_mu);
-    Workspace& w = p->ws[(void*)s];
+    Workspace& w = p->ws[std::make_pair((void*)s, slot)];
     if (w.bytes < bytes) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         SP_HIP(hipStreamIsCapturing(s, &cs));
@@ -85,9 +85,10 @@ static void free_plan(svdphat_plan* p) {
     for (int i = 0; i < 3; ++i) {
         if (p->A[i]) (void)hipFree(p->A[i]);
         if (p->Alo[i]) (void)hipFree(p->Alo[i]);
-        if (p->Ufr[i]) (void)hipFree(p->Ufr[i]);
+        for (auto& sr : p->sr)
+            if (sr.Ufr[i]) (void)hipFree(sr.Ufr[i]);
     }
-    void* bufs[] = {p->U32T, p->A32T, p->d_tkappa, p->d_sig, p->d_rows, p->d_rep, p->d_rowof, p->d_tauN, p->d_tauN_all, p->d_tauM_all, p->d_rowcls, p->d_pi, p->d_pj, p->Wfr};
+    void* bufs[] = {p->sr[0].U32T, p->sr[1].U32T, p->A32T, p->sr[0].tkappa, p->sr[1].tkappa, p->d_sig, p->d_rows, p->d_rep, p->d_rowof, p->d_tauN, p->d_tauN_all, p->d_tauM_all, p->d_rowcls, p->d_pi, p->d_pj, p->Wfr};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (auto& kv : p->ws)
@@ -317,8 +318,8 @@ int svdphat_locate(svdphat_plan* p, const void* X, int64_t F, int32_t precision,
         SP_REQUIRE(F >= 0 && F < ((int64_t)1 << 31), SVDPHAT_E_INVAL, "F out of range");
         SP_REQUIRE(precision == SVDPHAT_FP32 || precision == SVDPHAT_BF16 || precision == SVDPHAT_FP16,
                    SVDPHAT_E_INVAL, "unknown precision");
-        SP_REQUIRE((mode & ~(uint32_t)(SVDPHAT_RESCORE | SVDPHAT_HILO | SVDPHAT_HILO_ALL)) == 0, SVDPHAT_E_INVAL,
-                   "unknown mode bits");
+        SP_REQUIRE((mode & ~(uint32_t)(SVDPHAT_RESCORE | SVDPHAT_HILO | SVDPHAT_HILO_ALL | SVDPHAT_NORMALIZED)) == 0,
+                   SVDPHAT_E_INVAL, "unknown mode bits");
         if (F == 0) return;
         SP_REQUIRE(X && doa && power, SVDPHAT_E_INVAL, "NULL X, doa or power");
         SP_HIP(hipSetDevice(p->device));
@@ -333,8 +334,8 @@ int svdphat_locate_noalloc(svdphat_plan* p, const void* X, int64_t F, int32_t pr
         SP_REQUIRE(F >= 0 && F < ((int64_t)1 << 31), SVDPHAT_E_INVAL, "F out of range");
         SP_REQUIRE(precision == SVDPHAT_FP32 || precision == SVDPHAT_BF16 || precision == SVDPHAT_FP16,
                    SVDPHAT_E_INVAL, "unknown precision");
-        SP_REQUIRE((mode & ~(uint32_t)(SVDPHAT_RESCORE | SVDPHAT_HILO | SVDPHAT_HILO_ALL)) == 0, SVDPHAT_E_INVAL,
-                   "unknown mode bits");
+        SP_REQUIRE((mode & ~(uint32_t)(SVDPHAT_RESCORE | SVDPHAT_HILO | SVDPHAT_HILO_ALL | SVDPHAT_NORMALIZED)) == 0,
+                   SVDPHAT_E_INVAL, "unknown mode bits");
         if (F == 0) return;
         SP_REQUIRE(X && doa && power, SVDPHAT_E_INVAL, "NULL X, doa or power");
         SP_HIP(hipSetDevice(p->device));
@@ -345,6 +346,28 @@ int svdphat_locate_noalloc(svdphat_plan* p, const void* X, int64_t F, int32_t pr
 }
 
 int64_t svdphat_noalloc_scratch_bytes(void) { return (int64_t)NOALLOC_SCRATCH_BYTES; }
+
+int svdphat_locate_masked(svdphat_plan* p, const void* X, int64_t F, const uint8_t* mask, int32_t precision,
+                          uint32_t mode, int32_t* doa, float* power, float* yhat, float* margin, float* y_opt,
+                          void* stream) {
+    return guarded([&] {
+        SP_REQUIRE(p, SVDPHAT_E_INVAL, "NULL plan");
+        SP_REQUIRE(F >= 0 && F < ((int64_t)1 << 31), SVDPHAT_E_INVAL, "F out of range");
+        SP_REQUIRE(precision == SVDPHAT_FP32 || precision == SVDPHAT_BF16 || precision == SVDPHAT_FP16,
+                   SVDPHAT_E_INVAL, "unknown precision");
+        SP_REQUIRE((mode & ~(uint32_t)(SVDPHAT_RESCORE | SVDPHAT_HILO | SVDPHAT_HILO_ALL | SVDPHAT_NORMALIZED)) == 0,
+                   SVDPHAT_E_INVAL, "unknown mode bits");
+        if (F == 0) return;
+        SP_REQUIRE(X && mask && doa && power, SVDPHAT_E_INVAL, "NULL X, mask, doa or power");
+        SP_HIP(hipSetDevice(p->device));
+        const hipStream_t s = (hipStream_t)stream;
+        // the masked frames live in the stream's second workspace slot for the
+        // whole call (the power of Algorithm 1 step 4 reads them last)
+        float2* xm = (float2*)ws_get(p, s, (size_t)F * p->M * p->B * sizeof(float2), 1);
+        launch_mask(p, (const float2*)X, F, mask, xm, s);
+        launch_locate(p, xm, F, precision, mode, doa, power, yhat, margin, y_opt, s);
+    });
+}
 
 int svdphat_srp_locate(svdphat_plan* p, const void* X, int64_t F, int32_t* doa, float* power, float* y_opt,
                        void* stream) {

@@ -288,8 +288,8 @@ size_t gv_scratch_bytes(const svdphat_plan* p, int64_t F) {
            (size_t)F * ng * 16;
 }
 
-void launch_gv(svdphat_plan* p, const float2* X, int64_t F, int32_t* doa, float* power, float* yhat, float* margin,
-               void* ws, hipStream_t s) {
+void launch_gv(svdphat_plan* p, const ScoreRows& sr, const float2* X, int64_t F, int32_t* doa, float* power,
+               float* yhat, float* margin, void* ws, hipStream_t s) {
     const int nsl = cdiv(p->B, GV_BINS);
     const int ng = gv_score_groups(p);
     char* w = (char*)ws;
@@ -318,7 +318,7 @@ void launch_gv(svdphat_plan* p, const float2* X, int64_t F, int32_t* doa, float*
     SP_HIP(hipGetLastError());
     kt.end();
     kt.begin("gv_score");
-    SP_GV(k_gv_score, gs, 256, z, p->Rp, p->U32T, p->ncls, p->d_rowcls, res)
+    SP_GV(k_gv_score, gs, 256, z, p->Rp, sr.U32T, p->ncls, p->d_rowcls, res)
 #undef SP_GV
     SP_HIP(hipGetLastError());
     kt.end();

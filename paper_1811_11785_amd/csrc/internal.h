@@ -5,6 +5,7 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <map>
 #include <mutex>
@@ -194,6 +195,15 @@ void back_list_fp16(svdphat_plan* p, const float2* X, int64_t Fmax, const int* f
                     float* pmax, int32_t* doa, float* power, float* margin, hipStream_t s);
 void tune_time(svdphat_plan* p, int64_t F, int nsplit, int fch, double* us_g1, double* us_g2, hipStream_t s);
 
+// Device tables of one set of scored rows (see pack_rows in plan.hip).
+struct ScoreRows {
+    void* Ufr[3] = {nullptr, nullptr, nullptr};  // GEMM2 operand per precision
+    float uscale[3] = {1.f, 1.f, 1.f};           // exact power-of-two scale per precision
+    float* U32T = nullptr;                       // [ntile][Rp/4][QTILE][4] FP32 rescoring rows
+    float* tkappa = nullptr;                     // [ntile] largest row norm of each tile
+    float usig_max = 0.f;                        // max ||row sigma|| over the rows
+};
+
 struct Workspace {
     int64_t cap_frames = 0;
     void* buf = nullptr;
@@ -226,11 +236,8 @@ struct svdphat_plan {
     // device operands (all owned)
     void* A[3] = {nullptr, nullptr, nullptr};    // GEMM1 operand per precision
     void* Alo[3] = {nullptr, nullptr, nullptr};  // low parts (16-bit only)
-    void* Ufr[3] = {nullptr, nullptr, nullptr};  // GEMM2 operand per precision
-    float uscale[3] = {1.f, 1.f, 1.f};           // exact power-of-two scale of U per precision
-    float* U32T = nullptr;                       // [ntile][Rp/4][QTILE][4] FP32 rescoring rows
+    svdphat::ScoreRows sr[2];                    // scored rows: [0] U (eq. (14)), [1] U / ||U sigma|| (eq. (15))
     float* A32T = nullptr;                       // [B P 2][Rp] FP32 A = S V^H, transposed (GEMV form)
-    float* d_tkappa = nullptr;                   // [ntile] largest ||U_q|| of each tile
     float* d_sig = nullptr;                      // [Rp] singular value of each stacked row of Z
     int32_t* d_rows = nullptr;                   // [ncls] direction index of row
     int32_t* d_rep = nullptr;                    // [Q]
@@ -239,14 +246,13 @@ struct svdphat_plan {
     float* d_tauN_all = nullptr;                 // [Q][P] tau / N
     float* d_tauM_all = nullptr;                 // [Q][M] per-microphone tau / N
     int32_t* d_rowcls = nullptr;                 // [ncls_pad] class of each scored row
-    float usig_max = 0.f;                        // max ||U_q sigma|| over scored rows
     int8_t* d_pi = nullptr;                      // [P] first mic of pair
     int8_t* d_pj = nullptr;                      // [P] second mic of pair
     float* Wfr = nullptr;                        // plain form operand (KEEP_W)
     int Wrows_pad = 0, Wks = 0;                  // rows padded to 128, k-steps of 4
 
     std::mutex ws_mu;
-    std::map<void*, svdphat::Workspace> ws;  // per stream
+    std::map<std::pair<void*, int>, svdphat::Workspace> ws;  // per (stream, slot)
     std::vector<void*> ws_retired;           // grown-out workspaces (freed with the plan)
 };
 
@@ -305,9 +311,12 @@ constexpr int GV_MAX_FRAMES = 16;
 bool gv_applicable(const svdphat_plan* p, int64_t F);
 int gv_score_groups(const svdphat_plan* p);
 size_t gv_scratch_bytes(const svdphat_plan* p, int64_t F);
-void launch_gv(svdphat_plan* p, const float2* X, int64_t F, int32_t* doa, float* power, float* yhat, float* margin,
-               void* ws, hipStream_t s);
-void* ws_get(svdphat_plan* p, hipStream_t s, size_t bytes);
+void launch_gv(svdphat_plan* p, const ScoreRows& sr, const float2* X, int64_t F, int32_t* doa, float* power,
+               float* yhat, float* margin, void* ws, hipStream_t s);
+// the plan's workspace `slot` of stream s, grown to at least `bytes`
+void* ws_get(svdphat_plan* p, hipStream_t s, size_t bytes, int slot = 0);
+// binary time-frequency mask (mask.hip): xm = X where mask[f][b] != 0, else 0
+void launch_mask(const svdphat_plan* p, const float2* X, int64_t F, const uint8_t* mask, float2* xm, hipStream_t s);
 // zero `bytes` (a multiple of 4) of device memory on stream s with a kernel,
 // so that a caller capturing the stream into a graph records a kernel node
 void zero_async(void* p, size_t bytes, hipStream_t s);

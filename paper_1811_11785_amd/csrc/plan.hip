@@ -212,6 +212,53 @@ static void direction_classes(const std::vector<double>& tau, int Q, int P, doub
     }
 }
 
+// Device tables of one set of scored rows (stacked [Re, -Im] rows of U, or
+// of U / ||U sigma|| for eq. (15)): GEMM2 operands in the three precisions
+// (FP16 scaled by a power of two so that the largest entry lands near 2^14),
+// the FP32 rescoring copy per 64-row tile [tile][k/4][QTILE][4], each tile's
+// largest row norm and the largest ||row sigma||.
+static void pack_rows(svdphat_plan* p, const std::vector<float>& rows, const std::vector<float>& sg, float umax,
+                      svdphat::ScoreRows& out, int64_t& bytes) {
+    std::vector<float> u32;
+    pack_U<float>(p, rows, 1.f, u32);
+    upload(u32, &out.Ufr[P_FP32], bytes);
+    out.uscale[P_FP32] = 1.f;
+    float sc = 1.f;
+    if (umax > 0.f) sc = std::ldexp(1.f, (int)std::floor(std::log2(16384.0 / umax)));
+    std::vector<_Float16> u16;
+    pack_U<_Float16>(p, rows, sc, u16);
+    upload(u16, &out.Ufr[P_FP16], bytes);
+    out.uscale[P_FP16] = sc;
+    std::vector<__bf16> ub;
+    pack_U<__bf16>(p, rows, 1.f, ub);
+    upload(ub, &out.Ufr[P_BF16], bytes);
+    out.uscale[P_BF16] = 1.f;
+    const int ntile = p->ncls_pad / QTILE;
+    std::vector<float> t((size_t)ntile * p->Rp * QTILE, 0.f);
+    for (int r = 0; r < p->ncls; ++r)
+        for (int k = 0; k < p->Rp; ++k)
+            t[(((size_t)(r / QTILE) * (p->Rp / 4) + k / 4) * QTILE + r % QTILE) * 4 + k % 4] = rows[(size_t)r * p->Rp + k];
+    void* d = nullptr;
+    upload(t, &d, bytes);
+    out.U32T = (float*)d;
+    std::vector<float> tk(ntile, 0.f);
+    double us = 0.0;
+    for (int r = 0; r < p->ncls; ++r) {
+        double nrm = 0.0, ns = 0.0;
+        for (int k = 0; k < p->Rp; ++k) {
+            const double v = rows[(size_t)r * p->Rp + k];
+            const double vs = v * sg[k];
+            nrm += v * v;
+            ns += vs * vs;
+        }
+        tk[r / QTILE] = std::max(tk[r / QTILE], (float)(std::sqrt(nrm) * (1.0 + 1e-6)));
+        us = std::max(us, std::sqrt(ns));
+    }
+    upload(tk, &d, bytes);
+    out.tkappa = (float*)d;
+    out.usig_max = (float)(us * (1.0 + 1e-6));
+}
+
 void build_plan(svdphat_plan* p, const double* mics, const double* grid, bool factored) {
     const int M = p->M, Q = p->Q, N = p->N;
     const int P = M * (M - 1) / 2, B = N / 2 + 1;
@@ -471,59 +518,36 @@ void build_plan(svdphat_plan* p, const double* mics, const double* grid, bool fa
         kappa = std::max(kappa, std::sqrt(nrm));
     }
     p->kappa = kappa;
+    // singular value of each stacked row of Z (rows k and K + k: s_k)
+    std::vector<float> sg(p->Rp, 0.f);
+    for (int k = 0; k < K; ++k) sg[k] = sg[K + k] = (float)p->sigma[k];
     {
-        std::vector<float> u32;
-        pack_U<float>(p, Ust, 1.f, u32);
-        upload(u32, &p->Ufr[P_FP32], bytes);
-        p->uscale[P_FP32] = 1.f;
-        // FP16: exact power-of-two scale so that max |U| lands near 2^14
-        float sc = 1.f;
-        if (umax > 0.f) sc = std::ldexp(1.f, (int)std::floor(std::log2(16384.0 / umax)));
-        std::vector<_Float16> u16;
-        pack_U<_Float16>(p, Ust, sc, u16);
-        upload(u16, &p->Ufr[P_FP16], bytes);
-        p->uscale[P_FP16] = sc;
-        std::vector<__bf16> ub;
-        pack_U<__bf16>(p, Ust, 1.f, ub);
-        upload(ub, &p->Ufr[P_BF16], bytes);
-        p->uscale[P_BF16] = 1.f;
-        // FP32 rescoring rows, per tile [tile][k/4][QTILE][4]: a lane (row)
-        // reads four consecutive k in one 16-byte piece, and a wave's pieces
-        // for one k/4 are contiguous
-        const int ntile = p->ncls_pad / QTILE;
-        std::vector<float> t((size_t)ntile * p->Rp * QTILE, 0.f);
-        for (int r = 0; r < p->ncls; ++r)
-            for (int k = 0; k < p->Rp; ++k)
-                t[(((size_t)(r / QTILE) * (p->Rp / 4) + k / 4) * QTILE + r % QTILE) * 4 + k % 4] =
-                    Ust[(size_t)r * p->Rp + k];
         void* d = nullptr;
-        upload(t, &d, bytes);
-        p->U32T = (float*)d;
-        // largest row norm of each tile (rounding bound of its rows)
-        std::vector<float> tk(ntile, 0.f);
-        for (int r = 0; r < p->ncls; ++r) {
-            double nrm = 0.0;
-            for (int k = 0; k < p->Rp; ++k) nrm += (double)Ust[(size_t)r * p->Rp + k] * Ust[(size_t)r * p->Rp + k];
-            tk[r / QTILE] = std::max(tk[r / QTILE], (float)(std::sqrt(nrm) * (1.0 + 1e-6)));
-        }
-        upload(tk, &d, bytes);
-        p->d_tkappa = (float*)d;
-        // singular value of each stacked row of Z (rows k and K + k: s_k)
-        std::vector<float> sg(p->Rp, 0.f);
-        for (int k = 0; k < K; ++k) sg[k] = sg[K + k] = (float)p->sigma[k];
         upload(sg, &d, bytes);
         p->d_sig = (float*)d;
-        // largest ||U_q sigma|| over the scored rows (bound of the hi/lo test)
-        double us = 0.0;
+    }
+    pack_rows(p, Ust, sg, umax, p->sr[0], bytes);
+    // eq. (15): the same search over the rows D_q / ||D_q|| (D_q = U_q S,
+    // ||D_q|| = ||U_q sigma|| from the FP64 factors)
+    {
+        std::vector<float> Un(Ust.size(), 0.f);
+        float unmax = 0.f;
         for (int r = 0; r < p->ncls; ++r) {
+            const int q = p->rows[r];
             double nrm = 0.0;
-            for (int k = 0; k < p->Rp; ++k) {
-                const double v = (double)Ust[(size_t)r * p->Rp + k] * sg[k];
-                nrm += v * v;
+            for (int kk = 0; kk < K; ++kk) {
+                const double ur = p->U[((size_t)q * K + kk) * 2], ui = p->U[((size_t)q * K + kk) * 2 + 1];
+                nrm += (ur * ur + ui * ui) * p->sigma[kk] * p->sigma[kk];
             }
-            us = std::max(us, std::sqrt(nrm));
+            const double inv = nrm > 0.0 ? 1.0 / std::sqrt(nrm) : 0.0;
+            for (int kk = 0; kk < K; ++kk) {
+                const double ur = p->U[((size_t)q * K + kk) * 2], ui = p->U[((size_t)q * K + kk) * 2 + 1];
+                Un[(size_t)r * p->Rp + kk] = (float)(ur * inv);
+                Un[(size_t)r * p->Rp + K + kk] = (float)(-ui * inv);
+                unmax = std::max(unmax, std::max(std::fabs((float)(ur * inv)), std::fabs((float)(ui * inv))));
+            }
         }
-        p->usig_max = (float)(us * (1.0 + 1e-6));
+        pack_rows(p, Un, sg, unmax, p->sr[1], bytes);
     }
     {
         std::vector<int32_t> rows(p->rows);

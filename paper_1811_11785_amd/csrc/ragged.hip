@@ -197,12 +197,12 @@ void ragged_build(svdphat_ragged* r, uint32_t flags, const char* cache_path) {
         d.zfrag = w + of[i].zf;
         d.zsc = (float*)(w + of[i].sc);
         d.zn = (float*)(w + of[i].zn);
-        d.U = p->Ufr[P_FP16];
+        d.U = p->sr[0].Ufr[P_FP16];
         d.KSn = p->Rp / Mf<_Float16>::KSTEP;
         d.ncls = p->ncls;
         d.ntile = p->ncls_pad / QTILE;
         d.fch = r->fch[i];
-        d.uinv = 1.f / p->uscale[P_FP16];
+        d.uinv = 1.f / p->sr[0].uscale[P_FP16];
         d.pmax = (float*)(w + of[i].pm);
         d.pstride = pmax_stride(p);
         FinalArgs& fa = d.fin;
@@ -219,15 +219,15 @@ void ragged_build(svdphat_ragged* r, uint32_t flags, const char* cache_path) {
         const double u = std::ldexp(1.0, -11);
         fa.ecoef = (float)((2.0 * u + u * u + 2.0 * p->Rp * std::ldexp(1.0, -24)) * 1.01);
         fa.rescore = 1;
-        fa.U32T = p->U32T;
-        fa.tkappa = p->d_tkappa;
+        fa.U32T = p->sr[0].U32T;
+        fa.tkappa = p->sr[0].tkappa;
         fa.sig = p->d_sig;
         fa.rows = p->d_rows;
         fa.rep = p->d_rep;
         fa.tauN = p->d_tauN_all;
         fa.tauM = p->d_tauM_all;
         fa.rowcls = p->d_rowcls;
-        fa.usig_max = p->usig_max;
+        fa.usig_max = p->sr[0].usig_max;
         fa.hilo_k = 4.f;
         fa.u = (float)u;
         r->h_desc[i] = d;

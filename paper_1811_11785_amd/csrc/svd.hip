@@ -1119,15 +1119,15 @@ int g2_frames(int ntile, int64_t F) {
 }
 
 template <typename T>
-void launch_g2(svdphat_plan* p, int prec, const T* zfrag, int64_t F, const float* zsc, float* pmax,
-               int64_t pstride, float* ycls, hipStream_t s) {
+void launch_g2(svdphat_plan* p, const ScoreRows& sr, int prec, const T* zfrag, int64_t F, const float* zsc,
+               float* pmax, int64_t pstride, float* ycls, hipStream_t s) {
     constexpr int KS = Mf<T>::KSTEP;
     const int KSn = p->Rp / KS;
     const int ntile = p->ncls_pad / QTILE;
     const int fch = g2_frames(ntile, F);
     dim3 grid(cdiv(ntile, 4), (unsigned)((F + fch - 1) / fch));
-    const float uinv = 1.f / p->uscale[prec];
-    const T* U = (const T*)p->Ufr[prec];
+    const float uinv = 1.f / sr.uscale[prec];
+    const T* U = (const T*)sr.Ufr[prec];
     if (ycls) {
         // every reduced power as well (debugging output): general form
         k_gemm2<T, 0, true><<<grid, 256, 0, s>>>(U, KSn, zfrag, F, fch, p->ncls, ntile, zsc, uinv, pmax, pstride, ycls,
@@ -1298,7 +1298,9 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     SP_HIP(hipGetLastError());
     kt.end();
     kt.begin("gemm2");
-    launch_g2<T>(p, prec, zfrag, F, zsc, pmax, ntp, ycls, s);
+    // eq. (14) searches the rows of U, eq. (15) the rows of U / ||U sigma||
+    const ScoreRows& sr = p->sr[(mode & SVDPHAT_NORMALIZED) ? 1 : 0];
+    launch_g2<T>(p, sr, prec, zfrag, F, zsc, pmax, ntp, ycls, s);
     SP_HIP(hipGetLastError());
     kt.end();
     if (y_opt) {
@@ -1329,15 +1331,15 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     fa.Rp = Rp;
     fa.ecoef = (float)(lin * 1.01);
     fa.rescore = (mode & SVDPHAT_RESCORE) ? 1 : 0;
-    fa.U32T = p->U32T;
-    fa.tkappa = p->d_tkappa;
+    fa.U32T = sr.U32T;
+    fa.tkappa = sr.tkappa;
     fa.sig = p->d_sig;
     fa.rows = p->d_rows;
     fa.rep = p->d_rep;
     fa.tauN = p->d_tauN_all;
     fa.tauM = p->d_tauM_all;
     fa.rowcls = p->d_rowcls;
-    fa.usig_max = p->usig_max;
+    fa.usig_max = sr.usig_max;
     fa.nfr = F;
     fa.doa = doa;
     fa.power = nullptr;  // k_power below, after the hi/lo pass
@@ -1431,9 +1433,9 @@ void back_list_fp16(svdphat_plan* p, const float2* X, int64_t Fmax, const int* f
     const int ntile = p->ncls_pad / QTILE;
     const int fch = 256;
     dim3 grid(cdiv(ntile, 4), (unsigned)((Fmax + fch - 1) / fch));
-    const float uinv = 1.f / p->uscale[P_FP16];
+    const float uinv = 1.f / p->sr[0].uscale[P_FP16];
 #define SP_G2L(N)                                                                                             \
-    k_gemm2_list<N><<<grid, 256, 0, s>>>((const _Float16*)p->Ufr[P_FP16], KSn, zfrag, Fmax, fch, p->ncls, ntile, zsc, \
+    k_gemm2_list<N><<<grid, 256, 0, s>>>((const _Float16*)p->sr[0].Ufr[P_FP16], KSn, zfrag, Fmax, fch, p->ncls, ntile, zsc, \
                                          uinv, pmax, pstride, flist, fcount)
     switch (KSn) {
         case 1: SP_G2L(1); break;
@@ -1461,15 +1463,15 @@ void back_list_fp16(svdphat_plan* p, const float2* X, int64_t Fmax, const int* f
     const double u = std::ldexp(1.0, -11);
     fa.ecoef = (float)((2.0 * u + u * u + 2.0 * p->Rp * std::ldexp(1.0, -24)) * 1.01);
     fa.rescore = 1;
-    fa.U32T = p->U32T;
-    fa.tkappa = p->d_tkappa;
+    fa.U32T = p->sr[0].U32T;
+    fa.tkappa = p->sr[0].tkappa;
     fa.sig = p->d_sig;
     fa.rows = p->d_rows;
     fa.rep = p->d_rep;
     fa.tauN = p->d_tauN_all;
     fa.tauM = p->d_tauM_all;
     fa.rowcls = p->d_rowcls;
-    fa.usig_max = p->usig_max;
+    fa.usig_max = p->sr[0].usig_max;
     fa.nfr = Fmax;
     fa.flist = flist;
     fa.fcount = fcount;
@@ -1573,7 +1575,7 @@ void tune_time(svdphat_plan* p, int64_t F, int nsplit_want, int fch, double* us_
     dim3 grid(cdiv(ntile, 4), (unsigned)((F + fch - 1) / fch));
     for (int it = 0; it < reps; ++it) {
 #define SP_G2T(N)                                                                                            \
-    k_gemm2<_Float16, N><<<grid, 256, 0, s>>>((const _Float16*)p->Ufr[P_FP16], KSn, (const _Float16*)(w + o_zf), F, \
+    k_gemm2<_Float16, N><<<grid, 256, 0, s>>>((const _Float16*)p->sr[0].Ufr[P_FP16], KSn, (const _Float16*)(w + o_zf), F, \
                                               fch, p->ncls, ntile, (const float*)(w + o_sc), 1.f,                   \
                                               (float*)(w + o_pm), pmax_stride(p), nullptr, 0)
         switch (KSn) {
@@ -1608,7 +1610,7 @@ void launch_locate(svdphat_plan* p, const void* X, int64_t F, int prec, uint32_t
         if (scratch)
             SP_REQUIRE(need <= scratch_bytes, SVDPHAT_E_INVAL, "scratch memory too small for this call");
         void* w = scratch ? scratch : ws_get(p, s, need);
-        launch_gv(p, x, F, doa, power, yhat, margin, w, s);
+        launch_gv(p, p->sr[(mode & SVDPHAT_NORMALIZED) ? 1 : 0], x, F, doa, power, yhat, margin, w, s);
         return;
     }
     if (prec == P_FP32) run_locate<float>(p, x, F, prec, mode, doa, power, yhat, margin, y_opt, s, scratch, scratch_bytes);

@@ -2,6 +2,9 @@
 workloads, and the oracle's powers of every direction for a few sampled
 frames.  Calls only the input generators and the oracle.
 
+For each, the same frames are also searched with the normalised form of
+eq. (15) (nn_* fields).
+
 Workloads:
   planar_q10242  planar 7-mic array of Table 2, icosphere level 5 (10242
                  directions), N = 512, delta = 1e-5, one source per segment;
@@ -40,6 +43,7 @@ def make(name: str):
     X = w["X"][:frames]
     r = oracle.locate(plan, X)
     s = oracle.srp_locate(plan, X)
+    nn = oracle.normalized_locate(plan, X)
     np.savez_compressed(
         os.path.join(HERE, f"{name}_oracle.npz"),
         frames=np.int64(frames), K=np.int64(plan.K), K_paper=np.int64(plan.K_paper),
@@ -47,7 +51,8 @@ def make(name: str):
         sigma=plan.s[:plan.K + 8], doa=r["doa"].astype(np.int32),
         margin=r["margin"].astype(np.float64), power=r["power"], yhat=r["yhat"],
         srp_doa=s["doa"].astype(np.int32), srp_margin=s["margin"], srp_power=s["power"],
-        y_rows=rows, y=r["y"][rows].astype(np.float32), srp_y=s["y"][rows].astype(np.float32))
+        y_rows=rows, y=r["y"][rows].astype(np.float32), srp_y=s["y"][rows].astype(np.float32),
+        nn_doa=nn["doa"].astype(np.int32), nn_margin=nn["margin"], nn_yhat=nn["yhat"], nn_power=nn["power"])
     print(name, "K", plan.K, "residual", plan.residual, flush=True)
 
 

@@ -595,3 +595,113 @@ def test_peaks_brute_force_greedy():
             for choice in itertools.permutations(range(Q), n):
                 if choice != best:
                     assert not oracle.valid_peaks(y, dirs, cs, 1e-9, np.array([choice]))[0]
+
+
+# ------------------------------------------------ eq. (15), normalised search
+def _nn_case(seed=31, M=4, N=16, level=2, delta=1e-3, F=12):
+    mics, grid, rng = _small(M=M, N=N, level=level, seed=seed)
+    plan = oracle.make_plan(mics, grid, 16000.0, 343.0, N, delta)
+    X = rng.standard_normal((F, M, N // 2 + 1)) + 1j * rng.standard_normal((F, M, N // 2 + 1))
+    return plan, X
+
+
+def test_eq15_identity_and_brute_force():
+    """For unit rows D^_q and the unit projection Z^, 1 - ||D^_q - Z^^H||^2 / 2
+    equals Re(sum_k D^_qk Z^_k) (the product of eq. (14), no conjugate),
+    checked with explicit loops over directions and components; the oracle's
+    answer is the arg-max of y_q / ||D_q|| from the reduced powers of eqs.
+    (12)-(14), a different route to the same number."""
+    plan, X = _nn_case()
+    K = plan.K
+    D = plan.U * plan.s[:K][None, :]
+    x = oracle.phat_vector(X)
+    r = oracle.normalized_locate(plan, X)
+    y = oracle.svd_phat_power(plan.U, plan.s, plan.Vh, x)
+    rn = np.linalg.norm(D, axis=1)
+    for f in range(X.shape[0]):
+        Z = plan.Vh @ x[f]
+        zn = math.sqrt(sum(abs(v) ** 2 for v in Z))
+        best, bq = -2.0, -1
+        for q in range(D.shape[0]):
+            dn = [D[q, k] / rn[q] for k in range(K)]
+            zh = [Z[k] / zn for k in range(K)]
+            dist2 = sum(abs(dn[k] - zh[k].conjugate()) ** 2 for k in range(K))
+            dot = sum(dn[k] * zh[k] for k in range(K)).real
+            assert abs((1.0 - 0.5 * dist2) - dot) < 1e-12
+            if dot > best + 1e-12:
+                best, bq = dot, q
+        assert plan.rep[bq] == r["doa"][f]
+        assert abs(r["score"][f] - best) < 1e-12
+        qn = int(np.argmax(y[f] / rn))
+        assert plan.rep[qn] == r["doa"][f]
+        assert abs(r["yhat"][f] - y[f, qn] / rn[qn]) < 1e-9 * max(1.0, abs(r["yhat"][f]))
+
+
+def test_eq15_full_rank_equals_srp():
+    """At full rank ||D_q||^2 = ||W_q||^2 = L for every direction (unit-modulus
+    entries of eq. (4)), so eq. (15) picks the direction of eq. (9)."""
+    mics, grid, rng = _small(M=4, N=16, level=0, seed=3)
+    plan = oracle.make_plan(mics, grid, 16000.0, 343.0, 16, 1e-13)
+    assert plan.K == min(plan.W.shape)
+    D = plan.U * plan.s[:plan.K][None, :]
+    assert np.allclose(np.sum(np.abs(D) ** 2, axis=1), plan.W.shape[1], rtol=1e-12)
+    X = rng.standard_normal((20, 4, 9)) + 1j * rng.standard_normal((20, 4, 9))
+    r = oracle.normalized_locate(plan, X)
+    s = oracle.srp_locate(plan, X)
+    judged = s["margin"] > 1e-9
+    assert np.array_equal(r["doa"][judged], s["doa"][judged])
+    # and a truncated plan's row norms differ, so eq. (15) is not eq. (14)
+    plan2, X2 = _nn_case(delta=1e-1, F=40)
+    D2 = plan2.U * plan2.s[:plan2.K][None, :]
+    assert np.ptp(np.linalg.norm(D2, axis=1)) > 1e-3
+
+
+# ------------------------------------------------ binary time-frequency mask
+def test_mask_pins():
+    """The mask of ones changes nothing; dropping bins equals silencing them
+    in X (eq. (3) gives 0 for a silent bin); and for a noiseless plane wave
+    with only bins k0..k1 kept, SRP-PHAT is the band-limited Dirichlet sum
+    sum_p sum_{k=k0}^{k1} cos(k theta_p) = sum_p (D(k1) - D(k0 - 1)), with
+    D(n) = 1/2 + sin((n + 1/2) t) / (2 sin(t / 2))."""
+    N, fs, c = 64, 16000.0, 343.0
+    mics = synth.geometry("2d")
+    grid = synth.icosphere(2)
+    plan = oracle.make_plan(mics, grid, fs, c, N, 1e-5)
+    rng = np.random.default_rng(33)
+    B = N // 2 + 1
+    X = synth.plane_wave_fd(mics, synth.random_direction(rng), 6, N, fs, c, rng, snr_db=5.0)
+    ones = np.ones((6, B), np.uint8)
+    a, b = oracle.locate(plan, X), oracle.locate(plan, X, mask=ones)
+    assert np.array_equal(a["y"], b["y"]) and np.array_equal(a["power"], b["power"])
+    m = rng.integers(0, 2, size=(6, B)).astype(np.uint8)
+    Xz = X * m[:, None, :]
+    c1, c2 = oracle.locate(plan, X, mask=m), oracle.locate(plan, Xz)
+    assert np.allclose(c1["y"], c2["y"], atol=1e-12) and np.allclose(c1["power"], c2["power"], atol=1e-12)
+    # band-limited Dirichlet sum for a noiseless off-grid plane wave
+    u = synth.random_direction(rng)
+    Xp = synth.plane_wave_fd(mics, u, 1, N, fs, c, rng)
+    k0, k1 = 5, 21
+    band = np.zeros((1, B), np.uint8)
+    band[0, k0:k1 + 1] = 1
+    s = oracle.srp_locate(plan, Xp, mask=band)
+    tau = plan.tau
+    src = oracle.tdoa_farfield(mics, u[None, :], fs, c)[0]
+    th = 2 * np.pi * (tau - src[None, :]) / N
+    th = np.mod(th + np.pi, 2 * np.pi) - np.pi
+
+    def dsum(n, t):
+        small = np.abs(t) < 1e-12
+        st = np.where(small, 1.0, t)
+        return np.where(small, n + 1.0, 0.5 + np.sin((n + 0.5) * st) / (2 * np.sin(st / 2)))
+    want = (dsum(k1, th) - dsum(k0 - 1, th)).sum(axis=1)
+    assert np.max(np.abs(s["y"][0] - want)) < 1e-9 * plan.W.shape[1]
+
+
+def test_eq15_silent_frame_ties():
+    """A frame with every bin silent has Z = 0: every direction ties in
+    eq. (15) and the lowest index is returned, as for eq. (14)."""
+    plan, X = _nn_case(F=3)
+    X[1] = 0
+    r = oracle.normalized_locate(plan, X)
+    assert r["doa"][1] == 0 and r["yhat"][1] == 0.0 and r["margin"][1] == 0.0
+    assert oracle.locate(plan, X)["doa"][1] == 0
