@@ -267,6 +267,8 @@ int svdphat_srp_locate(svdphat_plan* plan, const void* X, int64_t F,
  *   X, doa, power  host arrays of n device pointers: STFT frames
  *                  complex64 [F_i][M_i][N_i/2+1], int32 [F_i], f32 [F_i].
  *   F              host, n frame counts, 0 <= F_i <= max_frames_i.
+ *   precision      SVDPHAT_FP16 (the batch's kernels run FP16 MFMA with FP32
+ *                  rescoring); other values give E_UNSUPPORTED.
  *   Copies the per-array descriptors and launches the graph on `stream`;
  *   returns without waiting.
  * svdphat_ragged_info -- how many shapes were tuned now / taken from the cache.
@@ -279,7 +281,8 @@ int svdphat_ragged_create(svdphat_plan* const* plans, int32_t n,
                           const char* tune_cache, svdphat_ragged** out);
 int svdphat_ragged_locate(svdphat_ragged* ragged, const void* const* X,
                           const int64_t* F, int32_t* const* doa,
-                          float* const* power, void* stream);
+                          float* const* power, int32_t precision,
+                          void* stream);
 int svdphat_ragged_info(const svdphat_ragged* ragged, int64_t* tuned,
                         int64_t* from_cache);
 void svdphat_ragged_destroy(svdphat_ragged* ragged);

@@ -82,7 +82,7 @@ SIGNATURES = {
     "svdphat_ragged_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_int64),
                                         C.c_uint32, C.c_char_p, C.POINTER(C.c_void_p)]),
     "svdphat_ragged_locate": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
-                                        C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p]),
+                                        C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32, C.c_void_p]),
     "svdphat_ragged_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "svdphat_ragged_destroy": (None, [C.c_void_p]),
     "svdphat_proposal_create": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_uint64,
@@ -271,13 +271,13 @@ def svdphat_ragged_create(plans, max_frames, flags=0, tune_cache=None):
     return out
 
 
-def svdphat_ragged_locate(ragged, Xs, doas, powers, stream=None):
+def svdphat_ragged_locate(ragged, Xs, doas, powers, stream=None, precision=FP16):
     n = len(Xs)
     X = (C.c_void_p * n)(*[x.data_ptr() if x.shape[0] else None for x in Xs])
     F = (C.c_int64 * n)(*[x.shape[0] for x in Xs])
     D = (C.c_void_p * n)(*[d.data_ptr() if d.numel() else None for d in doas])
     P = (C.c_void_p * n)(*[p.data_ptr() if p.numel() else None for p in powers])
-    _check(lib().svdphat_ragged_locate(ragged, X, F, D, P, _stream(stream)))
+    _check(lib().svdphat_ragged_locate(ragged, X, F, D, P, precision, _stream(stream)))
 
 
 def svdphat_ragged_info(ragged):

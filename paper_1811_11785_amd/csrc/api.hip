@@ -412,9 +412,11 @@ int svdphat_ragged_create(svdphat_plan* const* plans, int32_t n, const int64_t* 
 }
 
 int svdphat_ragged_locate(svdphat_ragged* r, const void* const* X, const int64_t* F, int32_t* const* doa,
-                          float* const* power, void* stream) {
+                          float* const* power, int32_t precision, void* stream) {
     return guarded([&] {
         SP_REQUIRE(r && X && F && doa && power, SVDPHAT_E_INVAL, "NULL argument");
+        SP_REQUIRE(precision == SVDPHAT_FP16, SVDPHAT_E_UNSUPPORTED,
+                   "ragged batches run FP16 MFMA with FP32 rescoring only");
         ragged_locate(r, X, F, doa, power, (hipStream_t)stream);
     });
 }

@@ -141,3 +141,49 @@ def test_ragged_rejects(amd, torch, batch):
         amd.Ragged([nd], [8])
     assert e.value.code == amd.E_UNSUPPORTED
     nd.close()
+    # only FP16 (with FP32 rescoring) runs in a ragged batch
+    rg = amd.Ragged(d["plans"][:2], [8, 8])
+    doas = [torch.empty(1, dtype=torch.int32, device="cuda") for _ in range(2)]
+    pows = [torch.empty(1, dtype=torch.float32, device="cuda") for _ in range(2)]
+    with pytest.raises(amd.SvdphatError) as e:
+        amd.svdphat_ragged_locate(rg._h, [x[:1] for x in d["Xs"][:2]], doas, pows, precision=amd.BF16)
+    assert e.value.code == amd.E_UNSUPPORTED
+    rg.close()
+
+
+def test_ragged_c4_shapes(amd, torch):
+    """Shapes at the ends of the 256-array workload in one batch: 16
+    microphones over 20 cm (P = 120, L = 30840, K in the hundreds), 4
+    microphones over 5 cm with Q = 10242, and a mid-size array, all at
+    N = 512; sampled frames of each against its FP64 oracle."""
+    print("ragged C4 shapes", flush=True)
+    rng = np.random.default_rng(11785950)
+    specs = [(16, 0.20, 3, 1e-5, 300), (4, 0.05, 5, 1e-3, 256), (11, 0.12, 3, 1e-5, 97)]
+    plans, Xs, refs = [], [], []
+    for M, ap, level, delta, F in specs:
+        mics = synth.random_array(M, ap, rng)
+        grid = synth.icosphere(level)
+        X = np.concatenate([synth.plane_wave_fd(mics, synth.random_direction(rng), 25, 512, 16000.0, 343.0, rng,
+                                                snr_db=rng.uniform(0, 20)) for _ in range(-(-F // 25))])[:F]
+        X = X.astype(np.complex64)
+        rp = oracle.make_plan(mics, grid, 16000.0, 343.0, 512, delta)
+        sample = np.unique(np.concatenate([[0, 1, F - 1], np.arange(0, F, 7)]))
+        refs.append((rp, sample, oracle.locate(rp, X[sample])))
+        plans.append(amd.Plan(mics, grid, 16000.0, 343.0, 512, delta))
+        Xs.append(torch.from_numpy(X).cuda())
+    Ks = [p.info["K"] for p in plans]
+    print(f"  K = {Ks}, Q = {[p.info['Q'] for p in plans]}", flush=True)
+    assert max(Ks) >= 200 and [r[0].K for r in refs] == Ks
+    rg = amd.Ragged(plans, [x.shape[0] for x in Xs])
+    doas, pows = rg.locate(Xs)
+    torch.cuda.synchronize()
+    for (rp, sample, ref), d, pw in zip(refs, doas, pows):
+        d, pw = d.cpu().numpy()[sample], pw.cpu().numpy()[sample]
+        judged = ref["margin"] > MARGIN_TOL
+        assert np.array_equal(d[judged], ref["doa"][judged])
+        same = d == ref["doa"]
+        L = rp.W.shape[1]
+        assert np.all(np.abs(pw[same] - ref["power"][same]) <= 1e-5 * L + 2e-5 * np.abs(ref["power"][same]))
+    rg.close()
+    for p in plans:
+        p.close()
