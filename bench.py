@@ -602,6 +602,20 @@ def bench_proposal(args, torch, amd, synth):
     kt = amd.svdphat_timing_read()
     amd.svdphat_timing_reset()
     kernels = {k: dict(avg_us=1e3 * v[0] / v[1], launches=v[1]) for k, v in kt.items()}
+    # rows rescored per confident frame (the kernel's own count) against the
+    # full search, which scores every direction class and rescores tiles
+    amd.svdphat_timing_enable(False, counts=True)
+    prop_step()
+    full_step()
+    torch.cuda.synchronize()
+    amd.svdphat_timing_enable(False)
+    cnt = amd.svdphat_timing_read()
+    amd.svdphat_timing_reset()
+    rows, conf_frames = cnt.get("count:proposal_rows_rescored", (0.0, 0))
+    tiles, _ = cnt.get("count:final_tiles_rescored", (0.0, 0))
+    work = {"rows_rescored_per_confident_frame": rows / max(conf_frames, 1),
+            "full_search_classes_scored_per_frame": plan.info["n_classes"],
+            "full_search_fp32_rows_rescored_per_frame": 64.0 * tiles / F}
     out = {
         "metric": "frames/s, learned proposal vs full search (planar, Q=40962)",
         "value": F * args.steps / dtp, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
@@ -616,7 +630,7 @@ def bench_proposal(args, torch, amd, synth):
         "fallback_rate": float(pfell.mean()),
         "miss_rate_confident_frames": float(np.mean(pdoa[~pfell] != full[~pfell])) if (~pfell).any() else 0.0,
         "final_loss": float(np.mean(losses[-10:])), "train_s": train_s, "plan_build_s": plan_s,
-        "kernels_us": kernels,
+        "kernels_us": kernels, "work": work,
     }
     print(json.dumps(out))
 

@@ -279,7 +279,7 @@ struct svdphat_proposal {
     void* ws = nullptr;
     size_t ws_bytes = 0;
     std::vector<void*> ws_retired;  // grown-out workspaces (freed with the proposal)
-    int* d_count = nullptr;  // [4]
+    int* d_count = nullptr;  // [8]: fallback count, then two 64-bit event counters
 };
 
 namespace svdphat {

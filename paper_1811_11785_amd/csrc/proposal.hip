@@ -292,7 +292,8 @@ __global__ __launch_bounds__(256) void k_propose(const float* __restrict__ logit
                                                  const float2* __restrict__ X, int M, int P, int B,
                                                  const float* __restrict__ tauM, int64_t F, int32_t* __restrict__ doa,
                                                  float* __restrict__ power, uint8_t* __restrict__ fell,
-                                                 int* __restrict__ flist, int* __restrict__ fcount) {
+                                                 int* __restrict__ flist, int* __restrict__ fcount,
+                                                 unsigned long long* __restrict__ stats) {
     __shared__ __align__(16) float zs[4][1024];
     __shared__ int rlist[4][RLIST];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -330,6 +331,7 @@ __global__ __launch_bounds__(256) void k_propose(const float* __restrict__ logit
     // 64 at a time (one row per lane), so the passes are few and full
     int* rl = rlist[wave];
     int nl = 0;
+    int scored = 0;  // rows rescored for this frame
     auto flush = [&]() {
         wave_sync();
         for (int i0 = 0; i0 < nl; i0 += 64) {
@@ -395,6 +397,7 @@ __global__ __launch_bounds__(256) void k_propose(const float* __restrict__ logit
             if (nl + n > RLIST) flush();
             for (int k = lane; k < n; k += 64) rl[nl + k] = crows[i + k];
             nl += n;
+            scored += n;
         }
     }
     flush();
@@ -407,6 +410,10 @@ __global__ __launch_bounds__(256) void k_propose(const float* __restrict__ logit
         });
         by = __uint_as_float(w[0]);
         bq = (int)w[1];
+    }
+    if (stats && lane == 0) {
+        atomicAdd(&stats[0], (unsigned long long)scored);
+        atomicAdd(&stats[1], 1ull);
     }
     if (bq < 0 || bq == 0x7fffffff) {
         // no scored direction in any proposed cell (empty cells): full search
@@ -727,7 +734,7 @@ void proposal_build(svdphat_proposal* pr, const double* coarse, int C, int H, ui
         SP_HIP(hipMalloc((void**)&pr->Wh[l], wsz[l] * sizeof(_Float16)));
         SP_HIP(hipMalloc((void**)&pr->Wt[l], wsz[l] * sizeof(_Float16)));
     }
-    SP_HIP(hipMalloc((void**)&pr->d_count, 4 * sizeof(int)));
+    SP_HIP(hipMalloc((void**)&pr->d_count, 8 * sizeof(int)));
     cast_weights(pr, nullptr);
     SP_HIP(hipDeviceSynchronize());
 }
@@ -765,16 +772,19 @@ void proposal_locate(svdphat_proposal* pr, const float2* X, int64_t F, int topk,
     k_features<<<dim3((unsigned)((F * p->Rp + 255) / 256)), 256, 0, s>>>(o.z32, o.zn, F, p->Rp, o.feat);
     forward(pr, o, F, s);
     kt.end();
-    zero_async(pr->d_count, sizeof(int), s);
+    // event counts (instrumentation): rows rescored and frames that took the
+    // proposal, in d_count[2..5] as two 64-bit counters
+    unsigned long long* stats = counting_on() ? reinterpret_cast<unsigned long long*>(pr->d_count + 2) : nullptr;
+    zero_async(pr->d_count, (stats ? 6 : 1) * sizeof(int), s);
     kt.begin("prop_rescore");
     if (p->M <= 8)
         k_propose<8><<<dim3((unsigned)((F + 3) / 4)), 256, 0, s>>>(
             o.logits, pr->Cp, pr->C, topk, conf_min, o.z32, p->Rp, pr->d_U32R, pr->d_cell_start, pr->d_cell_rows,
-            p->d_rows, X, p->M, p->P, p->B, p->d_tauM_all, F, doa, power, fell, o.flist, pr->d_count);
+            p->d_rows, X, p->M, p->P, p->B, p->d_tauM_all, F, doa, power, fell, o.flist, pr->d_count, stats);
     else
         k_propose<16><<<dim3((unsigned)((F + 3) / 4)), 256, 0, s>>>(
             o.logits, pr->Cp, pr->C, topk, conf_min, o.z32, p->Rp, pr->d_U32R, pr->d_cell_start, pr->d_cell_rows,
-            p->d_rows, X, p->M, p->P, p->B, p->d_tauM_all, F, doa, power, fell, o.flist, pr->d_count);
+            p->d_rows, X, p->M, p->P, p->B, p->d_tauM_all, F, doa, power, fell, o.flist, pr->d_count, stats);
     SP_HIP(hipGetLastError());
     kt.end();
     // low-confidence frames: the full search on the listed frames only
@@ -785,6 +795,16 @@ void proposal_locate(svdphat_proposal* pr, const float2* X, int64_t F, int topk,
     back_list_fp16(p, X, F, o.flist, pr->d_count, o.zgfrag, o.zgsc, o.zg32, o.zn, o.pmax, doa, power, nullptr, s);
     kt.end();
     kt.flush();
+    if (stats) {
+        unsigned long long h[2] = {0, 0};
+        int fc = 0;
+        SP_HIP(hipMemcpyAsync(h, stats, sizeof(h), hipMemcpyDeviceToHost, s));
+        SP_HIP(hipMemcpyAsync(&fc, pr->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+        SP_HIP(hipStreamSynchronize(s));
+        // rows rescored per frame that took the proposal; frames that fell back
+        timing_count("count:proposal_rows_rescored", (double)h[0], (int64_t)h[1]);
+        timing_count("count:proposal_fell_back", (double)fc, F);
+    }
 }
 
 // host parameters in the layout W1 [H][D], b1 [H], W2 [H][H], b2 [H],

@@ -180,6 +180,26 @@ def test_training_and_proposal_search(amd, torch, small):
     print(f"proposal agreement {agree:.4f}, fell back {fell.mean():.3f}, "
           f"misses on judged frames vs oracle {miss:.4f}")
     assert miss <= 0.05
+    # what the proposal saves: the rows rescored per confident frame (the
+    # scored directions of its topk cells) against the full search's one row
+    # per distinct direction class, counted by the kernel itself
+    amd.svdphat_timing_reset()
+    amd.svdphat_timing_enable(False, counts=True)
+    again = prop.locate(X, topk=4, conf_min=0.5)
+    torch.cuda.synchronize()
+    amd.svdphat_timing_enable(False)
+    cnt = amd.svdphat_timing_read()
+    amd.svdphat_timing_reset()
+    assert torch.equal(again["doa"], out["doa"])
+    rows, frames = cnt["count:proposal_rows_rescored"]
+    fb, nf = cnt["count:proposal_fell_back"]
+    assert frames == np.count_nonzero(~fell) and fb == np.count_nonzero(fell) and nf == X.shape[0]
+    cells = prop.cells()
+    ncls = plan.info["n_classes"]
+    biggest = np.sort(np.bincount(cells))[-4:].sum()
+    per = rows / frames
+    print(f"rows rescored per confident frame {per:.1f} of {ncls} direction classes", flush=True)
+    assert per <= biggest and per < 0.1 * ncls
     prop.close()
 
 
