@@ -291,8 +291,8 @@ void svdphat_ragged_destroy(svdphat_ragged* ragged);
  * Learned proposal.  Section 3 replaces the O(Q) scan of eq. (14) by a k-d
  * tree search; here a small network proposes where to look instead: an MLP
  * maps the normalised projection f = [Re Z; Im Z] / ||Z|| (Z of eq. (12))
- * through f -> GELU(W1 f + b1) -> GELU(W2 . + b2) -> W3 . + b3 (exact erf
- * GELU, `hidden` units) to C coarse cells of the direction grid (the cell of
+ * through f -> GELU(W1 f + b1) -> GELU(W2 . + b2) -> W3 . + b3 (GELU with
+ * erf to 1.5e-7, `hidden` units) to C coarse cells of the direction grid (the cell of
  * a direction is its nearest coarse direction, ties within 1e-12 to the lowest
  * cell).  The scored directions of the topk most probable cells are rescored
  * exactly in FP32; frames whose top probability is below conf_min take the

@@ -59,6 +59,7 @@ enum Prec { P_FP32 = 0, P_BF16 = 1, P_FP16 = 2 };
 inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
 inline int64_t round_up64(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+inline int64_t cdiv64(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Rows of the reduced search are scored in tiles of this many directions;
 // the per-tile maximum is the unit of the candidate set that is rescored.
@@ -263,9 +264,9 @@ struct svdphat_proposal {
     std::vector<int32_t> cell_of_dir;         // [Q]
     std::vector<double> coarse;               // [C][3] coarse directions as given
     int32_t* d_cell_of_dir = nullptr;         // [Q]
-    int32_t* d_cell_start = nullptr;          // [C + 1] CSR over scored rows
-    int32_t* d_cell_rows = nullptr;           // [ncls]
-    float* d_U32R = nullptr;                  // [ncls][Rp] FP32 rows, row-major
+    int32_t* d_cell_start = nullptr;          // [C + 1] CSR over the scored rows in cell order
+    int32_t* d_cell_dir = nullptr;            // [ncls] direction of each row in cell order
+    float* d_U32C = nullptr;                  // [ncls][Rp] FP32 stacked U rows in cell order
     // parameters: FP32 master, Adam moments, FP16 copies and transposes
     int64_t off[6] = {0, 0, 0, 0, 0, 0};     // W1 b1 W2 b2 W3 b3 inside the flat arrays
     int64_t nparam = 0;

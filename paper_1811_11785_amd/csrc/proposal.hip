@@ -9,7 +9,8 @@
 // kernels (forward, backward, weight gradients), FP32 master weights and Adam.
 //
 // Network: f (2K) -> GELU(W1 f + b1) (H) -> GELU(W2 . + b2) (H) -> W3 . + b3
-// (C), exact erf GELU, softmax cross-entropy.
+// (C), GELU(v) = v (1 + erf(v / sqrt 2)) / 2 with erf to 1.5e-7, softmax
+// cross-entropy.
 #include "device.h"
 
 #include <cstring>
@@ -25,11 +26,28 @@ constexpr int GPAD = 8;
 
 enum { EPI_GELU = 0, EPI_BIAS = 1, EPI_DGELU = 2, EPI_F32 = 3 };
 
-constexpr int RLIST = 1024;  // rows listed per wave before a rescoring pass
-
-__device__ __forceinline__ float gelu_f(float v) { return 0.5f * v * (1.f + erff(v * 0.70710678118654752f)); }
+// erf by formula 7.1.26 of Abramowitz and Stegun's Handbook of Mathematical
+// Functions (absolute error at most 1.5e-7), without branches; ex receives
+// exp(-x^2), which GELU' needs as well
+__device__ __forceinline__ float erf_as(float x, float& ex) {
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.f));
+    float q = fmaf(1.061405429f, t, -1.453152027f);
+    q = fmaf(q, t, 1.421413741f);
+    q = fmaf(q, t, -0.284496736f);
+    q = fmaf(q, t, 0.254829592f);
+    ex = __expf(-ax * ax);
+    return copysignf(fmaf(-q * t, ex, 1.f), x);
+}
+__device__ __forceinline__ float gelu_f(float v) {
+    float e;
+    return 0.5f * v * (1.f + erf_as(v * 0.70710678118654752f, e));
+}
+// GELU'(v) = (1 + erf(v / sqrt 2)) / 2 + v exp(-v^2 / 2) / sqrt(2 pi)
 __device__ __forceinline__ float gelu_d(float v) {
-    return 0.5f * (1.f + erff(v * 0.70710678118654752f)) + v * 0.39894228040143268f * __expf(-0.5f * v * v);
+    float e;
+    const float er = erf_as(v * 0.70710678118654752f, e);
+    return 0.5f * (1.f + er) + v * 0.39894228040143268f * e;
 }
 
 // C(m, n) = sum_k A(m, k) B(n, k) for m < M, n < N, k in [kbeg, kend), f16
@@ -280,158 +298,484 @@ __global__ void k_cast_w(const float* __restrict__ W, int rows, int cols, _Float
     wt[(int64_t)c * ldt + r] = (_Float16)W[i];
 }
 
-// Inference, one wave per frame: softmax top probability; if below conf_min
-// the frame is queued for the full search; otherwise the scored directions
-// of the topk most probable cells are rescored in FP32 (U rows . z) and the
-// best one's power is taken from its row of W.
-template <int MAXM>
-__global__ __launch_bounds__(256) void k_propose(const float* __restrict__ logits, int ld, int C, int topk,
-                                                 float conf_min, const float* __restrict__ z32, int Rp,
-                                                 const float* __restrict__ U32R, const int32_t* __restrict__ cstart,
-                                                 const int32_t* __restrict__ crows, const int32_t* __restrict__ rows,
-                                                 const float2* __restrict__ X, int M, int P, int B,
-                                                 const float* __restrict__ tauM, int64_t F, int32_t* __restrict__ doa,
-                                                 float* __restrict__ power, uint8_t* __restrict__ fell,
-                                                 int* __restrict__ flist, int* __restrict__ fcount,
-                                                 unsigned long long* __restrict__ stats) {
-    __shared__ __align__(16) float zs[4][1024];
-    __shared__ int rlist[4][RLIST];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t f = (int64_t)blockIdx.x * 4 + wave;
-    if (f >= F) return;
-    const float* l = logits + f * ld;
-    // logits of this frame's cells, up to 1024 cells in registers
-    float lv[16];
-    float mx = -INFINITY;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int c = lane + 64 * j;
-        lv[j] = c < C ? l[c] : -INFINITY;
-        mx = fmaxf(mx, lv[j]);
-    }
-    mx = wave_max(mx);
-    float se = 0.f;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) se += lv[j] > -INFINITY ? __expf(lv[j] - mx) : 0.f;
-    se = wave_sum(se);
-    const float p1 = 1.f / se;
-    if (p1 < conf_min) {
-        if (lane == 0) {
-            fell[f] = 1;
-            const int k = atomicAdd(fcount, 1);
-            flist[k] = (int)f;
+// ------------------------------------------------------------- inference
+// Inference runs in stages:
+//   k_mlp_infer   the forward pass of FT frames per workgroup, activations in
+//                 LDS, FP32 logits out;
+//   k_select      per frame the softmax top probability (below conf_min: the
+//                 full search) and the topk most probable cells that hold
+//                 scored rows, each entered in its cell's pair list;
+//   k_cell_scan   list offsets per cell, the rescoring work items (a cell
+//                 and up to PT of its frames) and the list of frames for the
+//                 full search, in frame order;
+//   k_scatter     the pair lists (the frames of each cell);
+//   k_rescore     per work item the cell's scored rows against its frames'
+//                 z in FP32 on MFMA (rows staged once for the item), the best
+//                 (y, lowest direction) per frame into a 64-bit atomic max;
+//   k_prop_final  direction and row power (Algorithm 1 step 4) per frame.
+// Grouping the pairs by cell reads each cell's rows once per PT frames
+// instead of once per frame.
+
+constexpr int PT = 64;       // frames per rescoring item
+constexpr int SEL_FPW = 2;   // frames per wave in the selection
+
+// The forward pass for inference: features f = z / ||z|| (f16), GELU(W1 f +
+// b1), GELU(W2 . + b2), W3 . + b3, for FT frames per workgroup of 4 waves.
+// Activations stay in LDS in two buffers ([FT][max(D0, H) + 8] and [FT][H +
+// 8] halves); the weights are read as B fragments from their f16 copies
+// (L2-resident), two k-steps ahead of their MFMAs.  The arithmetic is that
+// of the training path (f16 operands, FP32 accumulation, bias and GELU in
+// FP32, f16 hidden activations).  Writes FP32 logits [F][Cp].
+template <int FT>
+__global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ z32, const float* __restrict__ zn,
+                                                   int64_t F, int D0, int H, int Cp,
+                                                   const _Float16* __restrict__ W1, const float* __restrict__ b1,
+                                                   const _Float16* __restrict__ W2, const float* __restrict__ b2,
+                                                   const _Float16* __restrict__ W3, const float* __restrict__ b3,
+                                                   float* __restrict__ logits) {
+    constexpr int RB = FT / 16;
+    extern __shared__ __align__(16) char smem[];
+    const int L0 = max(D0, H) + 8, L1 = H + 8;
+    _Float16* buf0 = reinterpret_cast<_Float16*>(smem);
+    _Float16* buf1 = buf0 + FT * L0;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t f0 = (int64_t)blockIdx.x * FT;
+    // features (frames past F: 0)
+    const int q4 = D0 / 4;
+    for (int i = tid; i < FT * q4; i += 256) {
+        const int r = i / q4, c = 4 * (i - r * q4);
+        const int64_t f = f0 + r;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        float n = 0.f;
+        if (f < F) {
+            v = *reinterpret_cast<const float4*>(z32 + f * D0 + c);
+            n = zn[f];
         }
-        return;
+        _Float16* d = buf0 + r * L0 + c;
+        d[0] = (_Float16)(n > 0.f ? v.x / n : 0.f);
+        d[1] = (_Float16)(n > 0.f ? v.y / n : 0.f);
+        d[2] = (_Float16)(n > 0.f ? v.z / n : 0.f);
+        d[3] = (_Float16)(n > 0.f ? v.w / n : 0.f);
     }
-    float* zw = zs[wave];
-    for (int r = lane; r < Rp; r += 64) zw[r] = z32[f * Rp + r];
-    float by = -INFINITY;
-    int bq = 0x7fffffff;
-    // the scored rows of the chosen cells are listed first, then rescored
-    // 64 at a time (one row per lane), so the passes are few and full
-    int* rl = rlist[wave];
-    int nl = 0;
-    int scored = 0;  // rows rescored for this frame
-    auto flush = [&]() {
-        wave_sync();
-        for (int i0 = 0; i0 < nl; i0 += 64) {
-            const int i = i0 + lane;
-            if (i < nl) {
-                const int row = rl[i];
-                // the row in 16-byte pieces, one 128-byte line (8 pieces) per
-                // batch, so each lane's line is read in one go
-                const float* u = U32R + (int64_t)row * Rp;
-                float acc[4] = {0.f, 0.f, 0.f, 0.f};
-                for (int r0 = 0; r0 < Rp; r0 += 32) {
-                    float4 pv[8];
+    __syncthreads();
+    // out(m, n) = sum_k in(m, k) W(n, k) for the FT rows and n < N, in
+    // groups of 64 columns (wave w: groups w, w + 4, ...); epi(acc, group)
+    auto layer = [&](const _Float16* in, int ldi, int K, const _Float16* __restrict__ W, int N, auto&& epi) {
+        for (int g = wave; g * 64 < N; g += 4) {
+            f4 acc[RB][4];
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) pv[k] = *reinterpret_cast<const float4*>(u + r0 + 4 * k);
+            for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const float4 zz = *reinterpret_cast<const float4*>(zw + r0 + 4 * k);
-                        acc[0] = fmaf(pv[k].x, zz.x, acc[0]);
-                        acc[1] = fmaf(pv[k].y, zz.y, acc[1]);
-                        acc[2] = fmaf(pv[k].z, zz.z, acc[2]);
-                        acc[3] = fmaf(pv[k].w, zz.w, acc[3]);
+                for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
+            const _Float16* wp = W + (int64_t)(g * 64 + (lane & 15)) * K + 8 * (lane >> 4);
+            // B fragments two k-steps ahead (k-steps past the end reload the
+            // last one)
+            h8 b1[4], b2[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                b1[cb] = *reinterpret_cast<const h8*>(wp + (int64_t)cb * 16 * K);
+                b2[cb] = *reinterpret_cast<const h8*>(wp + (int64_t)cb * 16 * K + min(32, K - 32));
+            }
+            for (int k0 = 0; k0 < K; k0 += 32) {
+                h8 b[4];
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    b[cb] = b1[cb];
+                    b1[cb] = b2[cb];
+                }
+                const int kn = min(k0 + 64, K - 32);
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) b2[cb] = *reinterpret_cast<const h8*>(wp + (int64_t)cb * 16 * K + kn);
+                h8 a[RB];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+                    a[rb] = *reinterpret_cast<const h8*>(in + (rb * 16 + (lane & 15)) * ldi + k0 + 8 * (lane >> 4));
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = mfma(a[rb], b[cb], acc[rb][cb]);
+            }
+            epi(acc, g);
+        }
+    };
+    // hidden epilogue: GELU(acc + bias) in f16 into out [FT][ldo]
+    // (D layout: lane holds rows 4 (lane / 16) + e of column lane % 16)
+    auto hidden = [&](const float* __restrict__ bias, _Float16* out, int ldo) {
+        return [=](f4 (&acc)[RB][4], int g) {
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                const int n = g * 64 + cb * 16 + (lane & 15);
+                const float bv = bias[n];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        out[(rb * 16 + 4 * (lane >> 4) + e) * ldo + n] = (_Float16)gelu_f(acc[rb][cb][e] + bv);
+            }
+        };
+    };
+    layer(buf0, L0, D0, W1, H, hidden(b1, buf1, L1));
+    __syncthreads();
+    layer(buf1, L1, H, W2, H, hidden(b2, buf0, L0));
+    __syncthreads();
+    layer(buf0, L0, H, W3, Cp, [&](f4 (&acc)[RB][4], int g) {
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const int n = g * 64 + cb * 16 + (lane & 15);
+            const float bv = b3[n];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t f = f0 + rb * 16 + 4 * (lane >> 4) + e;
+                    // (streamed past the caches: read once, by the selection)
+                    if (f < F) __builtin_nontemporal_store(acc[rb][cb][e] + bv, logits + f * Cp + n);
+                }
+        }
+    });
+}
+
+// LDS bytes of k_mlp_infer for FT frames
+inline size_t mlp_infer_lds(int FT, int D0, int H) {
+    return (size_t)FT * (std::max(D0, H) + 8 + H + 8) * sizeof(_Float16);
+}
+
+// Selection, one wave per frame, SEL_FPW frames per wave (C <= 1024).  A
+// frame whose top probability is below conf_min, or whose topk cells hold
+// no scored row, takes the full search (fell = 1, ntop = 0).  Otherwise its
+// ntop cells with rows (in order of probability, lowest index on ties) go to
+// cand[f topk + t], with their slot in the cell's pair list in slot[..]:
+// a slot in a workgroup histogram (LDS) plus the workgroup's base, one
+// global add per cell the workgroup names.  stats (optional): rows to be
+// rescored and frames that take the proposal.
+__global__ __launch_bounds__(256) void k_select(const float* __restrict__ logits, int ld, int C, int topk,
+                                                float conf_min, const int32_t* __restrict__ cstart, int64_t F,
+                                                uint8_t* __restrict__ fell, int32_t* __restrict__ ntop,
+                                                int32_t* __restrict__ cand, int32_t* __restrict__ slot,
+                                                int* __restrict__ ccount, unsigned long long* __restrict__ best,
+                                                unsigned long long* __restrict__ stats) {
+    __shared__ int hist[1024];
+    __shared__ int base[1024];
+    __shared__ int cnr[1024];  // scored rows of each cell
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int c = tid; c < C; c += 256) {
+        hist[c] = 0;
+        cnr[c] = cstart[c + 1] - cstart[c];
+    }
+    __syncthreads();
+    const int64_t fw = ((int64_t)blockIdx.x * 4 + wave) * SEL_FPW;
+    int nsel[SEL_FPW];
+    unsigned long long rows_sum = 0, nconf = 0;
+    // logits of a frame's cells, up to 1024 in registers (lane + 64 j)
+    // (frame index clamped into range, so that the loads need no branch)
+    float lv[16];
+    auto load = [&](float (&v)[16], int64_t f) {
+        const float* l = logits + min(f, F - 1) * ld;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = __builtin_nontemporal_load(l + min(lane + 64 * j, C - 1));
+    };
+#pragma unroll
+    for (int i = 0; i < SEL_FPW; ++i) {
+        nsel[i] = 0;
+        const int64_t f = fw + i;
+        load(lv, f);
+        if (f < F) {
+            float mx = -INFINITY;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (lane + 64 * j >= C) lv[j] = -INFINITY;
+                mx = fmaxf(mx, lv[j]);
+            }
+            mx = wave_max(mx);
+            float se = 0.f;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) se += lv[j] > -INFINITY ? __expf(lv[j] - mx) : 0.f;
+            se = wave_sum(se);
+            int n = 0;
+            unsigned long long rs = 0;
+            if (1.f / se >= conf_min) {
+                // cells ranked by one 32-bit key: the logit's order-preserving
+                // bits to 13 mantissa bits, then the lowest index (key 0: none)
+                uint32_t key[16];
+                uint32_t km = 0;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const uint32_t b = __float_as_uint(lv[j]);
+                    const uint32_t o = b ^ ((uint32_t)((int32_t)b >> 31) | 0x80000000u);
+                    key[j] = lv[j] > -INFINITY ? ((o & ~0x3FFu) | (uint32_t)(1023 - (lane + 64 * j))) : 0u;
+                    km = max(km, key[j]);
+                }
+                for (int t = 0; t < topk; ++t) {
+                    uint32_t w[1] = {km};
+                    wave_reduce(w, [](uint32_t (&x)[1], const uint32_t (&o)[1]) { x[0] = max(x[0], o[0]); });
+                    const uint32_t kw = __builtin_amdgcn_readfirstlane(w[0]);
+                    if (kw == 0u) break;
+                    const int c = 1023 - (int)(kw & 0x3FFu);
+                    km = 0;
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) {
+                        key[j] = key[j] == kw ? 0u : key[j];
+                        km = max(km, key[j]);
+                    }
+                    const int nr = cnr[c];
+                    if (nr == 0) continue;  // an empty cell: nothing to rescore
+                    rs += (unsigned long long)nr;
+                    if (lane == 0) {
+                        cand[f * topk + n] = c;
+                        slot[f * topk + n] = atomicAdd(&hist[c], 1);
+                    }
+                    ++n;
+                }
+            }
+            nsel[i] = n;
+            if (n > 0) {
+                rows_sum += rs;
+                nconf += 1;
+            }
+            if (lane == 0) {
+                fell[f] = n == 0 ? 1 : 0;
+                ntop[f] = n;
+                best[f] = 0ull;
+            }
+        }
+    }
+    __syncthreads();
+    for (int c = tid; c < C; c += 256)
+        if (hist[c] > 0) base[c] = atomicAdd(&ccount[c], hist[c]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < SEL_FPW; ++i) {
+        const int64_t f = fw + i;
+        for (int t = lane; t < nsel[i]; t += 64) {
+            const int64_t e = f * topk + t;
+            slot[e] += base[cand[e]];
+        }
+    }
+    if (stats && lane == 0 && nconf > 0) {
+        atomicAdd(&stats[0], rows_sum);
+        atomicAdd(&stats[1], nconf);
+    }
+}
+
+// Exclusive prefix sum over the 1024 threads of the workgroup (total in
+// *tot): a scan within each wave, then over the 16 wave totals; every
+// thread must call it.  sw: 16 ints of LDS.
+__device__ __forceinline__ int block_exscan1024(int v, int* sw, int* tot) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) sw[wave] = x;
+    __syncthreads();
+    int below = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+        const int t = sw[w];
+        below += w < wave ? t : 0;
+        all += t;
+    }
+    *tot = all;
+    __syncthreads();  // (sw free for the next scan)
+    return below + x - v;
+}
+
+// One workgroup of 1024 threads: cell list offsets, rescoring items and the
+// full-search frame list in frame order (fell set).
+__global__ __launch_bounds__(1024) void k_cell_scan(const int* __restrict__ ccount, int C, int* __restrict__ cpos,
+                                                    int4* __restrict__ items, int* __restrict__ nitems,
+                                                    const uint8_t* __restrict__ fell, int64_t F,
+                                                    int* __restrict__ flist, int* __restrict__ fcount) {
+    __shared__ int sa[16];
+    const int t = threadIdx.x;
+    const int cnt = t < C ? ccount[t] : 0;
+    const int nch = (cnt + PT - 1) / PT;
+    int tot_pairs = 0, tot_items = 0;
+    const int pa = block_exscan1024(cnt, sa, &tot_pairs);
+    const int pb = block_exscan1024(nch, sa, &tot_items);
+    if (t < C) {
+        cpos[t] = pa;
+        for (int j = 0; j < nch; ++j) items[pb + j] = int4{t, pa + j * PT, min(PT, cnt - j * PT), 0};
+    }
+    if (t == 0) *nitems = tot_items;
+    int run = 0;
+    for (int64_t f0 = 0; f0 < F; f0 += 4096) {
+        int k = 0;
+        uint8_t fl[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t f = f0 + 4 * t + j;
+            fl[j] = f < F ? fell[f] : 0;
+            k += fl[j] ? 1 : 0;
+        }
+        int tot = 0;
+        int o = run + block_exscan1024(k, sa, &tot);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (fl[j]) flist[o++] = (int)(f0 + 4 * t + j);
+        run += tot;
+    }
+    if (t == 0) *fcount = run;
+}
+
+// The pair lists: frame f at cpos[cell] + slot for each of its entries.
+__global__ void k_scatter(const int32_t* __restrict__ ntop, const int32_t* __restrict__ cand,
+                          const int32_t* __restrict__ slot, const int* __restrict__ cpos, int64_t F, int topk,
+                          int32_t* __restrict__ pairs) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= F * topk) return;
+    const int64_t f = e / topk;
+    if (e - f * topk >= ntop[f]) return;
+    pairs[cpos[cand[e]] + slot[e]] = (int)f;
+}
+
+// 64-bit key of (y, direction q): larger y first, then lower q
+__device__ __forceinline__ unsigned long long yq_key(float y, int q) {
+    uint32_t u = __float_as_uint(y);
+    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return ((unsigned long long)u << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)q);
+}
+
+// Rescoring, one workgroup per item (cell c, up to PT frames): the cell's
+// scored rows (FP32, cell-ordered copy of U) in chunks of 64 rows against the
+// frames' z in FP32 on 16x16x4 MFMA.  The frames' z and the chunk's rows go
+// through LDS ([PT + 64][KC + 4] floats, the reduction axis in chunks of KC),
+// each thread issuing four 16-byte loads before their four stores.  Per
+// frame the best (y, lowest q) over the cell goes into best[f] (64-bit atomic
+// max, so the order of items does not matter).
+__global__ __launch_bounds__(256) void k_rescore(const int4* __restrict__ items, const int* __restrict__ nitems,
+                                                 const int32_t* __restrict__ pairs, const float* __restrict__ z32,
+                                                 int Rp, int KC, const float* __restrict__ U32C,
+                                                 const int32_t* __restrict__ cstart, const int32_t* __restrict__ cdir,
+                                                 unsigned long long* __restrict__ best) {
+    if ((int)blockIdx.x >= *nitems) return;
+    extern __shared__ __align__(16) char smem[];
+    const int LD = KC + 4;
+    float* zs = reinterpret_cast<float*>(smem);  // rows 0 .. PT-1: z; PT .. PT+63: U
+    const float* us = zs + PT * LD;
+    __shared__ int frm[PT];
+    __shared__ int qd[64];
+    __shared__ unsigned long long kb[PT];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int4 w = items[blockIdx.x];
+    const int c = w.x, p0 = w.y, n = w.z;
+    const int r0 = cstart[c], nr = cstart[c + 1] - r0;
+    if (tid < PT) {
+        frm[tid] = tid < n ? pairs[p0 + tid] : -1;
+        kb[tid] = 0ull;
+    }
+    const int nfb = (n + 15) / 16;
+    for (int rc = 0; rc < nr; rc += 64) {
+        const int nrc = min(64, nr - rc);
+        const int nrb = (nrc + 15) / 16, ntile = nrb * nfb;
+        const int nt = ntile > wave ? (ntile - wave + 3) / 4 : 0;  // tiles of this wave: wave, wave + 4, ...
+        f4 acc[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < Rp; k0 += KC) {
+            const int kn = min(KC, Rp - k0), q4 = kn / 4, tot = (PT + 64) * q4;
+            __syncthreads();  // (frm ready; the previous chunk's reads of LDS done)
+            if (k0 == 0 && tid < 64) qd[tid] = tid < nrc ? cdir[r0 + rc + tid] : 0;
+            for (int i0 = 0; i0 < tot; i0 += 1024) {
+                float4 v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = min(i0 + tid + 256 * u, tot - 1);
+                    const int j = i / q4, cc = 4 * (i - j * q4);
+                    const float* src = j < PT ? z32 + (int64_t)max(frm[j], 0) * Rp + k0 + cc
+                                              : U32C + (int64_t)(r0 + rc + min(j - PT, nrc - 1)) * Rp + k0 + cc;
+                    v[u] = *reinterpret_cast<const float4*>(src);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = i0 + tid + 256 * u;
+                    if (i < tot) {
+                        const int j = i / q4, cc = 4 * (i - j * q4);
+                        const bool ok = j < PT ? frm[j] >= 0 : j - PT < nrc;
+                        const float4 x = v[u];
+                        *reinterpret_cast<float4*>(zs + j * LD + cc) =
+                            make_float4(ok ? x.x : 0.f, ok ? x.y : 0.f, ok ? x.z : 0.f, ok ? x.w : 0.f);
                     }
                 }
-                const float y = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-                const int q = rows[row];
-                if (better(y, q, by, bq)) {
-                    by = y;
-                    bq = q;
-                }
+            }
+            __syncthreads();
+            // the wave's tiles, their MFMAs interleaved (independent accumulators)
+            const float* ua[4];
+            const float* zb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int tile = min(wave + 4 * i, ntile - 1);
+                const int rb = tile / nfb, fb = tile - rb * nfb;
+                ua[i] = us + (rb * 16 + (lane & 15)) * LD + (lane >> 4);
+                zb[i] = zs + (fb * 16 + (lane & 15)) * LD + (lane >> 4);
+            }
+            if (nt == 4) {
+                for (int k = 0; k < kn; k += 4)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc[i] = mfma(ua[i][k], zb[i][k], acc[i]);
+            } else if (nt == 3) {
+                for (int k = 0; k < kn; k += 4)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) acc[i] = mfma(ua[i][k], zb[i][k], acc[i]);
+            } else if (nt == 2) {
+                for (int k = 0; k < kn; k += 4)
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) acc[i] = mfma(ua[i][k], zb[i][k], acc[i]);
+            } else if (nt == 1) {
+                for (int k = 0; k < kn; k += 4) acc[0] = mfma(ua[0][k], zb[0][k], acc[0]);
             }
         }
-        wave_sync();
-        nl = 0;
-    };
-    for (int t = 0; t < topk; ++t) {
-        // next most probable cell (lowest index on ties)
-        float v = -INFINITY;
-        int c = 0x7fffffff;
+        // per frame: best over the chunk's rows (D layout: lane holds rows
+        // 4 (lane / 16) + e of frame column lane % 16)
+        auto epi = [&](const f4& av, int i) {
+            const int tile = min(wave + 4 * i, ntile - 1);
+            const bool live = wave + 4 * i < ntile;
+            const int rb = tile / nfb, fb = tile - rb * nfb;
+            unsigned long long k = 0ull;
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
-            if (better(lv[j], lane + 64 * j, v, c)) {
-                v = lv[j];
-                c = lane + 64 * j;
+            for (int e = 0; e < 4; ++e) {
+                const int row = rb * 16 + 4 * (lane >> 4) + e;
+                const unsigned long long ke = yq_key(av[e], qd[min(row, 63)]);
+                k = (live && row < nrc && ke > k) ? ke : k;
             }
-        {
-            uint32_t w[2] = {__float_as_uint(v), (uint32_t)c};
-            wave_reduce(w, [](uint32_t (&x)[2], const uint32_t (&o)[2]) {
-                const bool ob = better(__uint_as_float(o[0]), (int)o[1], __uint_as_float(x[0]), (int)x[1]);
-                x[0] = blend(x[0], o[0], ob);
-                x[1] = blend(x[1], o[1], ob);
-            });
-            v = __uint_as_float(w[0]);
-            c = (int)w[1];
-        }
-        if (c >= C || v == -INFINITY) break;
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-            if (lane + 64 * j == c) lv[j] = -INFINITY;
-        const int b = cstart[c], e = cstart[c + 1];
-        if (nl + (e - b) > RLIST) flush();
-        for (int i = b; i < e; i += RLIST) {  // (a cell larger than the list: in pieces)
-            const int n = min(e - i, RLIST);
-            if (nl + n > RLIST) flush();
-            for (int k = lane; k < n; k += 64) rl[nl + k] = crows[i + k];
-            nl += n;
-            scored += n;
-        }
+            const unsigned long long k16 = (unsigned long long)__shfl_xor((long long)k, 16);
+            k = k16 > k ? k16 : k;
+            const unsigned long long k32 = (unsigned long long)__shfl_xor((long long)k, 32);
+            k = k32 > k ? k32 : k;
+            const int j = fb * 16 + lane;
+            if (live && lane < 16 && j < n) atomicMax(&kb[j], k);
+        };
+        epi(acc[0], 0);
+        epi(acc[1], 1);
+        epi(acc[2], 2);
+        epi(acc[3], 3);
     }
-    flush();
-    {
-        uint32_t w[2] = {__float_as_uint(by), (uint32_t)bq};
-        wave_reduce(w, [](uint32_t (&x)[2], const uint32_t (&o)[2]) {
-            const bool ob = better(__uint_as_float(o[0]), (int)o[1], __uint_as_float(x[0]), (int)x[1]);
-            x[0] = blend(x[0], o[0], ob);
-            x[1] = blend(x[1], o[1], ob);
-        });
-        by = __uint_as_float(w[0]);
-        bq = (int)w[1];
-    }
-    if (stats && lane == 0) {
-        atomicAdd(&stats[0], (unsigned long long)scored);
-        atomicAdd(&stats[1], 1ull);
-    }
-    if (bq < 0 || bq == 0x7fffffff) {
-        // no scored direction in any proposed cell (empty cells): full search
-        if (lane == 0) {
-            fell[f] = 1;
-            const int k = atomicAdd(fcount, 1);
-            flist[k] = (int)f;
-        }
-        return;
-    }
+    __syncthreads();
+    if (tid < n) atomicMax(&best[frm[tid]], kb[tid]);
+}
+
+// Direction and row power (Algorithm 1 step 4) of the frames that took the
+// proposal, one wave per frame.
+template <int MAXM>
+__global__ __launch_bounds__(256) void k_prop_final(const uint8_t* __restrict__ fell,
+                                                    const unsigned long long* __restrict__ best,
+                                                    const float2* __restrict__ X, int M, int B,
+                                                    const float* __restrict__ tauM, int64_t F,
+                                                    int32_t* __restrict__ doa, float* __restrict__ power) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t f = (int64_t)blockIdx.x * 4 + wave;
+    if (f >= F || __builtin_amdgcn_readfirstlane(fell[f])) return;
+    const unsigned long long k = best[f];
+    const int q = __builtin_amdgcn_readfirstlane((int)(0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFull)));
     float t[MAXM];
 #pragma unroll
-    for (int m = 0; m < MAXM; ++m) t[m] = m < M ? tauM[(int64_t)bq * M + m] : 0.f;
+    for (int m = 0; m < MAXM; ++m) t[m] = m < M ? tauM[(int64_t)q * M + m] : 0.f;
     const float acc = power_ds<MAXM>(X + f * M * B, M, B, t, lane);
     if (lane == 0) {
-        doa[f] = bq;
+        doa[f] = q;
         power[f] = acc;
-        fell[f] = 0;
     }
 }
 
@@ -491,12 +835,17 @@ struct PW {  // workspace carve-up for F frames
     _Float16 *zfrag, *feat, *h1, *h2, *dlog, *d2, *d1, *zgfrag;
     int32_t *lab, *doa, *flist;
     float* pw;
-    int64_t Fc;
+    // inference: selection, pair lists, rescoring items, best keys
+    int32_t *ntop, *cand, *slot, *pairs;
+    int *ccount, *cpos, *nitems;
+    int4* items;
+    unsigned long long* best;
+    int64_t Fc, nitem_max;
 };
 
 constexpr int WSPLIT = 8;  // split-K partials of the weight gradients
 
-PW carve(svdphat_proposal* pr, int64_t F, hipStream_t s) {
+PW carve(svdphat_proposal* pr, int64_t F, hipStream_t s, int topk = 0) {
     svdphat_plan* p = pr->plan;
     const int64_t Fc = round_up64(std::max<int64_t>(F, 1), 64);
     const int H = pr->H, Cp = pr->Cp, D0 = pr->D0, Rp = p->Rp;
@@ -521,6 +870,11 @@ PW carve(svdphat_proposal* pr, int64_t F, hipStream_t s) {
     const size_t o_g4 = take(sizeof(float) * WSPLIT * Cp * H), o_g5 = take(sizeof(float) * Cp);
     const size_t o_pm = take(sizeof(float) * pmax_stride(p) * Fc), o_zg = take(sizeof(float) * Fc * Rp);
     const size_t o_zgf = take(sizeof(_Float16) * Fc * Rp), o_zgs = take(sizeof(float) * Fc);
+    const int64_t npair = std::max<int64_t>(1, F * topk), nitem = (npair + PT - 1) / PT + pr->C;
+    const size_t o_nt = take(sizeof(int32_t) * Fc), o_cd = take(sizeof(int32_t) * npair);
+    const size_t o_sl = take(sizeof(int32_t) * npair), o_pr = take(sizeof(int32_t) * npair);
+    const size_t o_cc = take(sizeof(int) * (pr->C + 1)), o_cp = take(sizeof(int) * pr->C);
+    const size_t o_it = take(sizeof(int4) * nitem), o_bs = take(sizeof(unsigned long long) * Fc);
     if (pr->ws_bytes < off) {
         // a grown-out buffer is kept until the proposal is destroyed (a graph
         // captured earlier may reference it); no growth during a capture
@@ -570,6 +924,16 @@ PW carve(svdphat_proposal* pr, int64_t F, hipStream_t s) {
     o.zg32 = (float*)(w + o_zg);
     o.zgfrag = (_Float16*)(w + o_zgf);
     o.zgsc = (float*)(w + o_zgs);
+    o.ntop = (int32_t*)(w + o_nt);
+    o.cand = (int32_t*)(w + o_cd);
+    o.slot = (int32_t*)(w + o_sl);
+    o.pairs = (int32_t*)(w + o_pr);
+    o.ccount = (int*)(w + o_cc);
+    o.nitems = o.ccount + pr->C;  // (cleared with the counts; written by the scan)
+    o.cpos = (int*)(w + o_cp);
+    o.items = (int4*)(w + o_it);
+    o.best = (unsigned long long*)(w + o_bs);
+    o.nitem_max = nitem;
     return o;
 }
 
@@ -692,18 +1056,21 @@ void proposal_build(svdphat_proposal* pr, const double* coarse, int C, int H, ui
     std::vector<int32_t> fillp(start.begin(), start.end() - 1);
     for (int r = 0; r < p->ncls; ++r) rowsc[fillp[pr->cell_of_dir[p->rows[r]]]++] = r;
     up(start.data(), sizeof(int32_t) * (C + 1), (void**)&pr->d_cell_start);
-    up(rowsc.data(), sizeof(int32_t) * p->ncls, (void**)&pr->d_cell_rows);
-    // FP32 stacked U rows, row-major [ncls][Rp]
+    // FP32 stacked U rows in cell order, row-major [ncls][Rp], and the
+    // direction of each
     std::vector<float> ur((size_t)p->ncls * p->Rp, 0.f);
+    std::vector<int32_t> dirc(p->ncls);
     const int K = p->K;
-    for (int r = 0; r < p->ncls; ++r) {
-        const int q = p->rows[r];
+    for (int i = 0; i < p->ncls; ++i) {
+        const int q = p->rows[rowsc[i]];
+        dirc[i] = q;
         for (int k = 0; k < K; ++k) {
-            ur[(size_t)r * p->Rp + k] = (float)p->U[((size_t)q * K + k) * 2];
-            ur[(size_t)r * p->Rp + K + k] = (float)(-p->U[((size_t)q * K + k) * 2 + 1]);
+            ur[(size_t)i * p->Rp + k] = (float)p->U[((size_t)q * K + k) * 2];
+            ur[(size_t)i * p->Rp + K + k] = (float)(-p->U[((size_t)q * K + k) * 2 + 1]);
         }
     }
-    up(ur.data(), sizeof(float) * ur.size(), (void**)&pr->d_U32R);
+    up(ur.data(), sizeof(float) * ur.size(), (void**)&pr->d_U32C);
+    up(dirc.data(), sizeof(int32_t) * p->ncls, (void**)&pr->d_cell_dir);
     // parameters: W ~ N(0, 2 / fan_in) (real inputs), biases 0; padded
     // input columns and padded cells stay 0
     const int D0 = pr->D0, Cp = pr->Cp, D = pr->D;
@@ -763,33 +1130,74 @@ float proposal_train_step(svdphat_proposal* pr, const float2* X, int64_t F, floa
 void proposal_locate(svdphat_proposal* pr, const float2* X, int64_t F, int topk, float conf_min, int32_t* doa,
                      float* power, uint8_t* fell, hipStream_t s) {
     svdphat_plan* p = pr->plan;
-    PW o = carve(pr, F, s);
+    PW o = carve(pr, F, s, topk);
+    const int H = pr->H, D0 = pr->D0, Cp = pr->Cp, C = pr->C, Rp = p->Rp;
     KernelTimer kt(s);
     kt.begin("prop_front");
     front_fp16(p, X, F, o.zpart, o.z32, o.zfrag, o.zsc, o.zn, s);
     kt.end();
+    // the forward pass: fused, with as many frames per workgroup as two
+    // workgroups' activations fit a CU's LDS (else layer by layer)
     kt.begin("prop_mlp");
-    k_features<<<dim3((unsigned)((F * p->Rp + 255) / 256)), 256, 0, s>>>(o.z32, o.zn, F, p->Rp, o.feat);
-    forward(pr, o, F, s);
+    const size_t lds_cap = 80 * 1024;
+    const int ft = mlp_infer_lds(64, D0, H) <= lds_cap ? 64 : mlp_infer_lds(32, D0, H) <= lds_cap ? 32
+                   : mlp_infer_lds(16, D0, H) <= 2 * lds_cap ? 16 : 0;
+    const float* P = pr->P;
+    if (ft == 64)
+        k_mlp_infer<64><<<dim3((unsigned)cdiv64(F, 64)), 256, mlp_infer_lds(64, D0, H), s>>>(
+            o.z32, o.zn, F, D0, H, Cp, pr->Wh[0], P + pr->off[1], pr->Wh[1], P + pr->off[3], pr->Wh[2],
+            P + pr->off[5], o.logits);
+    else if (ft == 32)
+        k_mlp_infer<32><<<dim3((unsigned)cdiv64(F, 32)), 256, mlp_infer_lds(32, D0, H), s>>>(
+            o.z32, o.zn, F, D0, H, Cp, pr->Wh[0], P + pr->off[1], pr->Wh[1], P + pr->off[3], pr->Wh[2],
+            P + pr->off[5], o.logits);
+    else if (ft == 16)
+        k_mlp_infer<16><<<dim3((unsigned)cdiv64(F, 16)), 256, mlp_infer_lds(16, D0, H), s>>>(
+            o.z32, o.zn, F, D0, H, Cp, pr->Wh[0], P + pr->off[1], pr->Wh[1], P + pr->off[3], pr->Wh[2],
+            P + pr->off[5], o.logits);
+    else {
+        k_features<<<dim3((unsigned)((F * Rp + 255) / 256)), 256, 0, s>>>(o.z32, o.zn, F, Rp, o.feat);
+        forward(pr, o, F, s);
+    }
+    SP_HIP(hipGetLastError());
     kt.end();
-    // event counts (instrumentation): rows rescored and frames that took the
-    // proposal, in d_count[2..5] as two 64-bit counters
+    // selection, pair lists, work items and the full-search list; event
+    // counts (instrumentation) in d_count[2..5] as two 64-bit counters:
+    // rows rescored, frames that take the proposal
     unsigned long long* stats = counting_on() ? reinterpret_cast<unsigned long long*>(pr->d_count + 2) : nullptr;
-    zero_async(pr->d_count, (stats ? 6 : 1) * sizeof(int), s);
+    if (stats) zero_async(stats, 2 * sizeof(unsigned long long), s);
+    kt.begin("prop_select");
+    zero_async(o.ccount, sizeof(int) * (C + 1), s);
+    const int64_t nwave = cdiv64(F, SEL_FPW);
+    k_select<<<dim3((unsigned)cdiv64(nwave, 4)), 256, 0, s>>>(o.logits, Cp, C, topk, conf_min, pr->d_cell_start, F,
+                                                            fell, o.ntop, o.cand, o.slot, o.ccount, o.best, stats);
+    SP_HIP(hipGetLastError());
+    k_cell_scan<<<dim3(1), 1024, 0, s>>>(o.ccount, C, o.cpos, o.items, o.nitems, fell, F, o.flist, pr->d_count);
+    SP_HIP(hipGetLastError());
+    const int64_t ne = F * topk;
+    k_scatter<<<dim3((unsigned)cdiv64(ne, 256)), 256, 0, s>>>(o.ntop, o.cand, o.slot, o.cpos, F, topk, o.pairs);
+    SP_HIP(hipGetLastError());
+    kt.end();
+    // rescoring of each cell's rows against its frames (grid: the most
+    // items there can be; the rest exit at once)
     kt.begin("prop_rescore");
+    const int KC = std::min(Rp, 128);
+    const size_t lds = (size_t)(PT + 64) * (KC + 4) * sizeof(float);
+    k_rescore<<<dim3((unsigned)o.nitem_max), 256, lds, s>>>(o.items, o.nitems, o.pairs, o.z32, Rp, KC, pr->d_U32C,
+                                                            pr->d_cell_start, pr->d_cell_dir, o.best);
+    SP_HIP(hipGetLastError());
+    kt.end();
+    kt.begin("prop_power");
+    const dim3 gf((unsigned)cdiv64(F, 4));
     if (p->M <= 8)
-        k_propose<8><<<dim3((unsigned)((F + 3) / 4)), 256, 0, s>>>(
-            o.logits, pr->Cp, pr->C, topk, conf_min, o.z32, p->Rp, pr->d_U32R, pr->d_cell_start, pr->d_cell_rows,
-            p->d_rows, X, p->M, p->P, p->B, p->d_tauM_all, F, doa, power, fell, o.flist, pr->d_count, stats);
+        k_prop_final<8><<<gf, 256, 0, s>>>(fell, o.best, X, p->M, p->B, p->d_tauM_all, F, doa, power);
     else
-        k_propose<16><<<dim3((unsigned)((F + 3) / 4)), 256, 0, s>>>(
-            o.logits, pr->Cp, pr->C, topk, conf_min, o.z32, p->Rp, pr->d_U32R, pr->d_cell_start, pr->d_cell_rows,
-            p->d_rows, X, p->M, p->P, p->B, p->d_tauM_all, F, doa, power, fell, o.flist, pr->d_count, stats);
+        k_prop_final<16><<<gf, 256, 0, s>>>(fell, o.best, X, p->M, p->B, p->d_tauM_all, F, doa, power);
     SP_HIP(hipGetLastError());
     kt.end();
     // low-confidence frames: the full search on the listed frames only
     kt.begin("prop_fallback");
-    k_gather_z<<<dim3((unsigned)(o.Fc / 4)), 256, 0, s>>>(o.flist, pr->d_count, o.z32, p->Rp, o.zg32, o.zgfrag,
+    k_gather_z<<<dim3((unsigned)(o.Fc / 4)), 256, 0, s>>>(o.flist, pr->d_count, o.z32, Rp, o.zg32, o.zgfrag,
                                                           o.zgsc);
     SP_HIP(hipGetLastError());
     back_list_fp16(p, X, F, o.flist, pr->d_count, o.zgfrag, o.zgsc, o.zg32, o.zn, o.pmax, doa, power, nullptr, s);
@@ -930,7 +1338,7 @@ void proposal_apply_grad(svdphat_proposal* pr, const float* grad, float lr) {
 
 void proposal_free(svdphat_proposal* pr) {
     if (!pr) return;
-    void* bufs[] = {pr->d_cell_of_dir, pr->d_cell_start, pr->d_cell_rows, pr->d_U32R, pr->P, pr->Mm, pr->Vv,
+    void* bufs[] = {pr->d_cell_of_dir, pr->d_cell_start, pr->d_cell_dir, pr->d_U32C, pr->P, pr->Mm, pr->Vv,
                     pr->ws, pr->d_count, pr->Wh[0], pr->Wh[1], pr->Wh[2], pr->Wt[0], pr->Wt[1], pr->Wt[2]};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
