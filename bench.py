@@ -202,6 +202,26 @@ def main():
         d = doa.cpu().numpy()
         results[name]["doa"] = d
         log(f"{name}: {results[name]['fps']:.4g} frames/s ({results[name]['ms_per_step']:.3f} ms/step)")
+    # the normalised search of eq. (15), and a binary time-frequency mask
+    # (each bin of each frame kept with probability 0.7), both in the FP16
+    # form with rescoring and hi/lo
+    prec, mode = forms["fp16"]
+    extra = {}
+    g = torch.Generator(device=dev)
+    g.manual_seed(11785)
+    tfmask = (torch.rand((F, info["B"]), generator=g, device=dev) < 0.7).to(torch.uint8)
+    masked = lambda: amd._check(amd.lib().svdphat_locate_masked(
+        h, amd._ptr(X), F, amd._ptr(tfmask), prec, mode, amd._ptr(doa), amd._ptr(power), amd._ptr(yhat),
+        amd._ptr(margin), None, amd._stream(None)))
+    for name, step in (("fp16_eq15", svd_step(prec, mode | amd.NORMALIZED)), ("fp16_masked", masked)):
+        ns = max(3, args.steps // 5)
+        _timed(step, 2, torch)
+        dt = _timed(step, ns, torch)
+        extra[name] = dict(fps=F * ns / dt, ms_per_step=1e3 * dt / ns)
+        if name == "fp16_eq15":
+            extra[name]["same_direction_as_eq14"] = float(np.mean(doa.cpu().numpy() == results["fp16"]["doa"]))
+        log(f"{name}: {extra[name]['fps']:.4g} frames/s ({extra[name]['ms_per_step']:.3f} ms/step)")
+    del tfmask
     # plain FP32 SRP-PHAT on the same batch
     srp = lambda: amd.svdphat_srp_locate(h, X, doa, power)
     _timed(srp, 1, torch)
@@ -356,6 +376,7 @@ def main():
         "plain_fp32_srp_fps": srp_fps,
         "speedup_vs_plain_fp32": head["fps"] / srp_fps,
         "forms_fps": {k: v["fps"] for k, v in results.items()},
+        "eq15_and_mask": extra,
         "argmax_match": acc,
         "y_error": yerr,
         "kernels_us": kernels,

@@ -247,14 +247,22 @@ __global__ __launch_bounds__(256) void k_xent(const float* __restrict__ logits, 
     if (lane == 0) loss[f] = -(l[y] - mx - __logf(se));
 }
 
-// Column sums over frames of an f16 matrix [F][ld] (bias gradients).
+// Column sums over frames of an f16 matrix [F][ld] (bias gradients), in
+// gridDim.y partial sums over equal runs of frames: out[part][n] (the Adam
+// step adds the partials in order).
 __global__ void k_colsum(const _Float16* __restrict__ d, int64_t F, int N, int ld, float* __restrict__ out) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
+    const int64_t per = (F + gridDim.y - 1) / gridDim.y;
+    const int64_t fb = (int64_t)blockIdx.y * per, fe = min(F, fb + per);
     float s = 0.f;
-    for (int64_t f = 0; f < F; ++f) s += (float)d[f * ld + n];
-    out[n] = s;
+    for (int64_t f = fb; f < fe; ++f) s += (float)d[f * ld + n];
+    out[(int64_t)blockIdx.y * N + n] = s;
 }
+
+// partial sums of a bias gradient over F frames (runs of at least 128)
+constexpr int BSPLIT = 64;
+inline int bias_parts(int64_t F) { return (int)std::max<int64_t>(1, std::min<int64_t>(BSPLIT, (F + 127) / 128)); }
 
 struct AdamSeg {
     int64_t off;       // offset in the flat parameter arrays
@@ -865,9 +873,9 @@ PW carve(svdphat_proposal* pr, int64_t F, hipStream_t s, int topk = 0) {
     const size_t o_d2 = take(sizeof(_Float16) * Fc * H), o_d1 = take(sizeof(_Float16) * Fc * H);
     const size_t o_ls = take(sizeof(float) * Fc), o_lab = take(sizeof(int32_t) * Fc), o_doa = take(sizeof(int32_t) * Fc);
     const size_t o_pw = take(sizeof(float) * Fc), o_fl = take(sizeof(int32_t) * Fc);
-    const size_t o_g0 = take(sizeof(float) * WSPLIT * H * D0), o_g1 = take(sizeof(float) * H);
-    const size_t o_g2 = take(sizeof(float) * WSPLIT * H * H), o_g3 = take(sizeof(float) * H);
-    const size_t o_g4 = take(sizeof(float) * WSPLIT * Cp * H), o_g5 = take(sizeof(float) * Cp);
+    const size_t o_g0 = take(sizeof(float) * WSPLIT * H * D0), o_g1 = take(sizeof(float) * BSPLIT * H);
+    const size_t o_g2 = take(sizeof(float) * WSPLIT * H * H), o_g3 = take(sizeof(float) * BSPLIT * H);
+    const size_t o_g4 = take(sizeof(float) * WSPLIT * Cp * H), o_g5 = take(sizeof(float) * BSPLIT * Cp);
     const size_t o_pm = take(sizeof(float) * pmax_stride(p) * Fc), o_zg = take(sizeof(float) * Fc * Rp);
     const size_t o_zgf = take(sizeof(_Float16) * Fc * Rp), o_zgs = take(sizeof(float) * Fc);
     const int64_t npair = std::max<int64_t>(1, F * topk), nitem = (npair + PT - 1) / PT + pr->C;
@@ -956,17 +964,18 @@ void backward(svdphat_proposal* pr, const PW& o, int64_t F, hipStream_t s) {
     // layer 3: dW3[c][h] = sum_f dlog[f][c] h2[f][h]; db3; dh2 = dlog W3, da2 = dh2 GELU'(a2)
     zero(o.g[4], (size_t)WSPLIT * Cp * H);
     mlp_gemm<true, true, EPI_F32>(o.dlog, Cp, o.h2, H, Cp, H, (int)F, ks, nullptr, nullptr, o.g[4], nullptr, H, s);
-    k_colsum<<<dim3(cdiv(Cp, 256)), 256, 0, s>>>(o.dlog, F, Cp, Cp, o.g[5]);
+    const int bp = bias_parts(F);
+    k_colsum<<<dim3(cdiv(Cp, 256), bp), 256, 0, s>>>(o.dlog, F, Cp, Cp, o.g[5]);
     mlp_gemm<false, false, EPI_DGELU>(o.dlog, Cp, pr->Wt[2], Cp, (int)F, H, Cp, 1, nullptr, o.a2, nullptr, o.d2, H, s);
     // layer 2
     zero(o.g[2], (size_t)WSPLIT * H * H);
     mlp_gemm<true, true, EPI_F32>(o.d2, H, o.h1, H, H, H, (int)F, ks, nullptr, nullptr, o.g[2], nullptr, H, s);
-    k_colsum<<<dim3(cdiv(H, 256)), 256, 0, s>>>(o.d2, F, H, H, o.g[3]);
+    k_colsum<<<dim3(cdiv(H, 256), bp), 256, 0, s>>>(o.d2, F, H, H, o.g[3]);
     mlp_gemm<false, false, EPI_DGELU>(o.d2, H, pr->Wt[1], H, (int)F, H, H, 1, nullptr, o.a1, nullptr, o.d1, H, s);
     // layer 1
     zero(o.g[0], (size_t)WSPLIT * H * D0);
     mlp_gemm<true, true, EPI_F32>(o.d1, H, o.feat, D0, H, D0, (int)F, ks, nullptr, nullptr, o.g[0], nullptr, D0, s);
-    k_colsum<<<dim3(cdiv(H, 256)), 256, 0, s>>>(o.d1, F, H, H, o.g[1]);
+    k_colsum<<<dim3(cdiv(H, 256), bp), 256, 0, s>>>(o.d1, F, H, H, o.g[1]);
     SP_HIP(hipGetLastError());
 }
 
@@ -976,13 +985,14 @@ void adam(svdphat_proposal* pr, const PW& o, int64_t F, float lr, hipStream_t s,
     const float b1 = 0.9f, b2 = 0.999f;
     const float c1 = 1.f - std::pow(b1, (float)pr->step), c2 = 1.f - std::pow(b2, (float)pr->step);
     const int ks = std::max(1, std::min(WSPLIT, (int)((F + 255) / 256)));
+    const int bp = bias_parts(F);
     AdamSeg seg[6] = {
         {pr->off[0], H, D0, ks, o.g[0], pr->Wh[0], pr->Wt[0], D0, H},
-        {pr->off[1], H, 1, 1, o.g[1], nullptr, nullptr, 0, 0},
+        {pr->off[1], H, 1, bp, o.g[1], nullptr, nullptr, 0, 0},
         {pr->off[2], H, H, ks, o.g[2], pr->Wh[1], pr->Wt[1], H, H},
-        {pr->off[3], H, 1, 1, o.g[3], nullptr, nullptr, 0, 0},
+        {pr->off[3], H, 1, bp, o.g[3], nullptr, nullptr, 0, 0},
         {pr->off[4], Cp, H, ks, o.g[4], pr->Wh[2], pr->Wt[2], H, Cp},
-        {pr->off[5], Cp, 1, 1, o.g[5], nullptr, nullptr, 0, 0},
+        {pr->off[5], Cp, 1, bp, o.g[5], nullptr, nullptr, 0, 0},
     };
     for (auto& sg : seg) {
         const int64_t n = (int64_t)sg.rows * sg.cols;
@@ -1290,11 +1300,12 @@ float proposal_grad(svdphat_proposal* pr, const float* feat, const int32_t* lab,
     };
     int64_t h = 0;
     fetch(o.g[0], H, D, H, D0, ks, h);
-    fetch(o.g[1], 1, H, 1, H, 1, h);
+    const int bp = bias_parts(F);
+    fetch(o.g[1], 1, H, 1, H, bp, h);
     fetch(o.g[2], H, H, H, H, ks, h);
-    fetch(o.g[3], 1, H, 1, H, 1, h);
+    fetch(o.g[3], 1, H, 1, H, bp, h);
     fetch(o.g[4], C, H, Cp, H, ks, h);
-    fetch(o.g[5], 1, C, 1, Cp, 1, h);
+    fetch(o.g[5], 1, C, 1, Cp, bp, h);
     std::vector<float> loss(F);
     SP_HIP(hipMemcpy(loss.data(), o.loss, sizeof(float) * F, hipMemcpyDeviceToHost));
     double sum = 0.0;
