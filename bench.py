@@ -137,7 +137,7 @@ def main():
                          "or proposal_q40962")
     ap.add_argument("--batches", default="1,256,4096", help="batch sizes of the cube workloads")
     ap.add_argument("--train-frames", type=int, default=2_000_000, help="training pairs of the proposal")
-    ap.add_argument("--train-epochs", type=int, default=1, help="passes over the proposal's training pairs")
+    ap.add_argument("--train-epochs", type=int, default=20, help="passes over the proposal's training pairs")
     ap.add_argument("--arrays", type=int, default=256, help="arrays of the ragged workload")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MB (a known-size reference "
