@@ -555,6 +555,20 @@ def bench_ragged(args, torch, amd, synth):
     single_fps = Ftot * ns / dts
     agree = float(np.mean(np.concatenate([a == d.cpu().numpy() for a, d in zip(rdoa, doas)])))
     Ks = [p.info["K"] for p in plans]
+    # roofline of the whole step: every array's STFT frames read once against
+    # HBM, and the two products' arithmetic (GEMM1: 2 Rp 2L per frame, GEMM2:
+    # 2 classes Rp per frame, Rp = 2K padded to 32) against FP16 MFMA
+    step_s = dt / args.steps
+    in_bytes = sum(x.numel() * x.element_size() for x in Xs)
+    flops = 0.0
+    for p, x in zip(plans, Xs):
+        rp = -(-2 * p.info["K"] // 32) * 32
+        flops += x.shape[0] * (2.0 * rp * 2 * p.info["L"] + 2.0 * p.info["n_classes"] * rp)
+    roof = {"bound": "hbm", "achieved": in_bytes / step_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": in_bytes / step_s / 1e9 / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": in_bytes,
+            "kernel": "whole step (graph of grouped stages)"}
+    mfma = {"tflops": flops / step_s / 1e12, "peak": 2500.0, "frac": flops / step_s / 1e12 / 2500.0,
+            "flops_per_step": flops}
     out = {
         "metric": "frames/s, ragged batch of arrays in one graph launch",
         "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -565,7 +579,7 @@ def bench_ragged(args, torch, amd, synth):
                    "K_range": [min(Ks), max(Ks)], "Q_levels": sorted(grids)},
         "single_call_fps": single_fps, "speedup_vs_single_calls": fps / single_fps,
         "doa_agreement_with_single_calls": agree, "tuned_shapes": tuned, "cached_shapes": cached,
-        "plan_build_s": plan_s, "ragged_build_s": tune_s,
+        "plan_build_s": plan_s, "ragged_build_s": tune_s, "roofline": roof, "mfma": mfma,
     }
     print(json.dumps(out))
 
