@@ -674,7 +674,7 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
     const int64_t f = a.flist ? (int64_t)a.flist[pos] : pos;
     const float* pm = a.pmax + f * a.pstride;
 
-    // ---- round 1: frame maximum over tiles, the tile holding it and that
+    // ---- stage 1: frame maximum over tiles, the tile holding it and that
     // tile's bound (carried through the reduction), z into LDS
     float ym = -INFINITY, km = 0.f;
     int tm = 0x7fffffff;
@@ -764,7 +764,7 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
     wave_sync();
     const float thr = a.rescore ? ym - km * ef : ym;
 
-    // ---- round 2: rescore the candidate tiles in FP32: best (y1, q1, r1,
+    // ---- stage 2: rescore the candidate tiles in FP32: best (y1, q1, r1,
     // class c1) and runner-up (y2, q2, r2)
     float y1 = -INFINITY, y2 = -INFINITY, ncmax = -INFINITY;
     int q1 = 0x7fffffff, q2 = 0x7fffffff, r1 = -1, r2 = -1, c1 = 0;
@@ -910,7 +910,7 @@ __device__ __forceinline__ void final_body(int bx, const FinalArgs& a) {
     }
     if (!HILO && a.hlist && !a.flist && a.hilo_all) redo = true;
 
-    // ---- round 3 (when the power is not left to k_power): Algorithm 1
+    // ---- stage 3 (when the power is not left to k_power): Algorithm 1
     // online step 4, the power of the chosen direction from its row of W
     // (delay-and-sum form)
     // (MAXM = 0: no power here, which keeps the register count and so the
