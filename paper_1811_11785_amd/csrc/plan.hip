@@ -74,7 +74,7 @@ template <typename T>
 float from_t(T v) { return (float)v; }
 
 // Chunk layout of the GEMM1 reduction axis for one element type.  The x
-// tile of 64 frames x CW values must fit in 64 KB of LDS; among the bin
+// tile of 64 frames x CW values must fit its LDS budget; among the bin
 // counts that fit, prefer little padding, then bigger chunks.
 G1Layout make_layout(int P, int B, int M, int esize, int kstep, int nRB, int epl) {
     G1Layout g;
@@ -88,7 +88,10 @@ G1Layout make_layout(int P, int B, int M, int esize, int kstep, int nRB, int epl
         g.elems = (int64_t)g.nch * g.ks_chunk * nRB * 64 * epl;
         return g;
     }
-    const int budget = 65536 / (64 * esize) - 8;  // CW + pad per frame row
+    // CW + pad per frame row: 64 KB of x tile, or 124 KB above 8
+    // microphones (120 pairs per bin at 16: two bins per chunk would leave
+    // half of the workgroup's threads idle while the tile is formed)
+    const int budget = (M <= 8 ? 65536 : 126976) / (64 * esize) - 8;
     const int max_bb = (M <= 8 ? G1_MAX_ITEMS8 : G1_MAX_ITEMS16) / 64;
     double best = -1.0;
     for (int bb = 1; bb <= std::min(B, max_bb); ++bb) {

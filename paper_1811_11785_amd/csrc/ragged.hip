@@ -11,6 +11,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <array>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -233,9 +234,17 @@ void ragged_build(svdphat_ragged* r, uint32_t flags, const char* cache_path) {
         r->h_desc[i] = d;
     }
 
-    // work lists, one per (stage, class)
+    // work lists, one per (stage, class).  GEMM1's items are dealt to the
+    // eight XCDs (workgroup b of a launch runs on XCD b mod 8): an array's
+    // items in A-region order ((split, row group) major, frame tile minor)
+    // are cut into up to eight contiguous parts, each queued for one XCD
+    // (a rotating start balances the queues), so that each XCD reads its
+    // part of A into its own L2 and serves every frame tile from there;
+    // the queues are interleaved, shorter ones padded with empty items.
     std::map<std::pair<int, int>, std::vector<int4>> lists;
     std::map<std::pair<int, int>, size_t> lds;
+    std::map<std::pair<int, int>, std::array<std::vector<int4>, 8>> xq;
+    std::map<std::pair<int, int>, int> xrot;
     for (int i = 0; i < n; ++i) {
         const svdphat_plan* p = r->plans[i];
         const G1Layout& g = p->g1[P_FP16];
@@ -245,9 +254,19 @@ void ragged_build(svdphat_ragged* r, uint32_t flags, const char* cache_path) {
         const int NRB = g1_nrb_class(nRB);
         const int big = p->M > 8 ? 1 : 0;
         const auto k1 = std::make_pair(0, NRB * 2 + big);
-        for (int64_t ft = 0; ft < Fc / 64; ++ft)
+        {
+            std::vector<int4> it;
             for (int sp = 0; sp < r->nsplit[i]; ++sp)
-                for (int rg = 0; rg < cdiv(nRB, NRB); ++rg) lists[k1].push_back(int4{i, (int)ft, sp, rg});
+                for (int rg = 0; rg < cdiv(nRB, NRB); ++rg)
+                    for (int64_t ft = 0; ft < Fc / 64; ++ft) it.push_back(int4{i, (int)ft, sp, rg});
+            auto& q = xq[k1];
+            int& o = xrot[k1];
+            const size_t ni = it.size();
+            const int parts = (int)std::min<size_t>(8, ni);
+            for (int j = 0; j < parts; ++j)
+                for (size_t t = j * ni / parts; t < (j + 1) * ni / parts; ++t) q[(o + j) % 8].push_back(it[t]);
+            o = (o + parts) % 8;
+        }
         lds[k1] = std::max(lds[k1], g1_lds_bytes(NRB, g.CW));
         for (int64_t bx = 0; bx < Fc / 4; ++bx) lists[{1, 0}].push_back(int4{i, (int)bx, 0, 0});
         const int ntile = p->ncls_pad / QTILE;
@@ -257,6 +276,13 @@ void ragged_build(svdphat_ragged* r, uint32_t flags, const char* cache_path) {
             for (int64_t by = 0; by < (F + r->fch[i] - 1) / r->fch[i]; ++by)
                 lists[{2, ureg}].push_back(int4{i, bx, (int)by, 0});
         for (int64_t bx = 0; bx < (F + 3) / 4; ++bx) lists[{3, big}].push_back(int4{i, (int)bx, 0, 0});
+    }
+    for (auto& kv : xq) {
+        size_t len = 0;
+        for (auto& v : kv.second) len = std::max(len, v.size());
+        auto& L = lists[kv.first];
+        for (size_t k = 0; k < len; ++k)
+            for (int x = 0; x < 8; ++x) L.push_back(k < kv.second[x].size() ? kv.second[x][k] : int4{-1, 0, 0, 0});
     }
     for (auto& kv : lists) {
         GroupLaunch gl;

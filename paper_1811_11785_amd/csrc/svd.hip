@@ -1005,6 +1005,7 @@ void launch_power(const svdphat_plan* p, const float2* X, const int32_t* doa, in
 template <int NRB, int MAXM, int IPT>
 __global__ __launch_bounds__(256) void k_gemm1_grouped(const RDesc* __restrict__ d, const int4* __restrict__ work) {
     const int4 w = work[blockIdx.x];
+    if (w.x < 0) return;  // padding of the XCD queues
     const RDesc& a = d[w.x];
     gemm1_body<_Float16, 64, NRB, MAXM, IPT, false>(w.y, w.z, w.w, a.X, a.F, a.M, a.P, a.B,
                                                     (const _Float16*)a.A, nullptr, a.nRB, a.BB, a.CW, a.nch, a.cps,
