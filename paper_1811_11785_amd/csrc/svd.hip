@@ -132,6 +132,15 @@ __device__ __forceinline__ void gemm1_body(int bx, int by, int bz, const float2*
             const int fl = it / BB, bl = bofs[k];
             VP* dst = reinterpret_cast<VP*>(xs + fl * ldx + bl * twoP);
             VP* dlo = reinterpret_cast<VP*>(xl + fl * ldx + bl * twoP);
+            // pair (i, j), i < j < M, goes to slot i M - i (i + 1) / 2 + j - i - 1
+            // of the bin's run; pairs with j >= M go to the row's padding past
+            // the tile (columns CW .. ldx - 1, never read), so the unrolled
+            // loops below carry no branch per pair
+            VP* pad = reinterpret_cast<VP*>(xs + fl * ldx + CW);
+            VP* padl = reinterpret_cast<VP*>(xl + fl * ldx + CW);
+            auto slot = [&](VP* base, VP* sink, int i, int j) {
+                return j < M ? base + (i * M - i * (i + 1) / 2 + j - i - 1) : sink;
+            };
             float re[MAXM], im[MAXM];
 #pragma unroll
             for (int m = 0; m < MAXM; ++m) {
@@ -148,30 +157,24 @@ __device__ __forceinline__ void gemm1_body(int bx, int by, int bz, const float2*
                     a[m] = h2{(_Float16)re[m], (_Float16)im[m]};
                     c[m] = h2{(_Float16)im[m], (_Float16)(-re[m])};
                 }
-                int p = 0;
 #pragma unroll
                 for (int i = 0; i < MAXM; ++i)
 #pragma unroll
-                    for (int j = i + 1; j < MAXM; ++j)
-                        if (j < M) {
-                            const h2 rj = h2{a[j].x, a[j].x}, ij = h2{a[j].y, a[j].y};
-                            dst[p] = a[i] * rj + c[i] * ij;
-                            ++p;
-                        }
+                    for (int j = i + 1; j < MAXM; ++j) {
+                        const h2 rj = h2{a[j].x, a[j].x}, ij = h2{a[j].y, a[j].y};
+                        *slot(dst, pad, i, j) = a[i] * rj + c[i] * ij;
+                    }
             } else {
-                int p = 0;
 #pragma unroll
                 for (int i = 0; i < MAXM; ++i)
 #pragma unroll
-                    for (int j = i + 1; j < MAXM; ++j)
-                        if (j < M) {
-                            const float xr = re[i] * re[j] + im[i] * im[j];
-                            const float xi = im[i] * re[j] - re[i] * im[j];
-                            const T hr = cvt<T>(xr), hi = cvt<T>(xi);
-                            dst[p] = mkpair<T>(hr, hi);
-                            if (HILO) dlo[p] = mkpair<T>(cvt<T>(xr - (float)hr), cvt<T>(xi - (float)hi));
-                            ++p;
-                        }
+                    for (int j = i + 1; j < MAXM; ++j) {
+                        const float xr = re[i] * re[j] + im[i] * im[j];
+                        const float xi = im[i] * re[j] - re[i] * im[j];
+                        const T hr = cvt<T>(xr), hi = cvt<T>(xi);
+                        *slot(dst, pad, i, j) = mkpair<T>(hr, hi);
+                        if (HILO) *slot(dlo, padl, i, j) = mkpair<T>(cvt<T>(xr - (float)hr), cvt<T>(xi - (float)hi));
+                    }
             }
         }
         __syncthreads();
