@@ -308,8 +308,9 @@ void svdphat_ragged_destroy(svdphat_ragged* ragged);
  *   FP32 accumulation and master weights.  Synchronous.
  * svdphat_proposal_locate  doa [F] int32, power [F] f32 as svdphat_locate,
  *   fell_back [F] u8 = 1 where the full search was used (top probability
- *   below conf_min, or no scored direction in any of the topk cells).
- *   Asynchronous.
+ *   below conf_min, or no scored direction in any of the topk cells): the
+ *   search of svdphat_locate with SVDPHAT_FP16 and SVDPHAT_RESCORE, without
+ *   the hi/lo pass.  Asynchronous.
  * svdphat_proposal_params  copies the FP32 parameters to (set = 0) or from
  *   (set = 1) a host buffer of svdphat_proposal_nparams() floats laid out
  *   W1 [hidden][2K], b1 [hidden], W2 [hidden][hidden], b2 [hidden],

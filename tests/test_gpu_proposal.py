@@ -151,11 +151,13 @@ def test_training_and_proposal_search(amd, torch, small):
     X = _frames(torch, small["mics"], 24, 99, snr=(0.0, 20.0))
     out = prop.locate(X, topk=4, conf_min=0.5)
     full = plan.locate(X, precision="fp16", rescore=True, hilo=True)
+    plain = plan.locate(X, precision="fp16", rescore=True, hilo=False)
     torch.cuda.synchronize()
     doa, fell = out["doa"].cpu().numpy(), out["fell_back"].cpu().numpy().astype(bool)
     fdoa = full["doa"].cpu().numpy()
-    # frames that fell back ran the full search: identical to it
-    assert np.array_equal(doa[fell], fdoa[fell])
+    # frames that fell back ran the full search (without the hi/lo pass):
+    # identical to it
+    assert np.array_equal(doa[fell], plain["doa"].cpu().numpy()[fell])
     assert fell.mean() < 0.5
     agree = np.mean(doa == fdoa)
     assert agree >= 0.95, agree
@@ -223,7 +225,7 @@ def test_empty_cells_fall_back(amd, torch, small):
     prop.set_params(params)
     X = _frames(torch, small["mics"], 2, 77, snr=(10.0, 20.0), seg=32)
     out = prop.locate(X, topk=min(len(empty), 2), conf_min=0.0)
-    full = plan.locate(X, precision="fp16", rescore=True, hilo=True)
+    full = plan.locate(X, precision="fp16", rescore=True, hilo=False)
     torch.cuda.synchronize()
     assert np.all(out["fell_back"].cpu().numpy() == 1)
     assert np.array_equal(out["doa"].cpu().numpy(), full["doa"].cpu().numpy())
@@ -234,3 +236,61 @@ def test_proposal_rejects(amd, small):
     with pytest.raises(amd.SvdphatError) as e:
         amd.Proposal(small["plan"], small["coarse"], hidden=100)
     assert e.value.code == amd.E_INVAL
+
+
+def test_proposal_at_q40962(amd, torch):
+    """The proposal's working size: the planar array at Q = 40962 (20,609
+    direction classes), 642 coarse cells, hidden 256, six passes over 1M
+    training pairs from the method's own labels, then 20,000 fresh frames
+    (SNR U[-5, 20] dB, 100-frame segments) with the top-8 cells and threshold
+    0.5.  Asserted: directions differ from the full search (FP16, rescoring,
+    hi/lo) on at most 0.5% of the frames; frames below the threshold take the
+    full search without the hi/lo pass (identical answers there); the rows
+    rescored per confident frame are at most 5% of the classes the full
+    search scores; the time per call is within 2x of the full search's
+    (measured 0.82-0.87x of its speed)."""
+    import time
+    print("proposal at Q = 40962", flush=True)
+    mics = synth.geometry("2d")
+    plan = amd.Plan(mics, synth.icosphere(6), 16000.0, 343.0, 512, 1e-5)
+    prop = amd.Proposal(plan, synth.icosphere(3), hidden=256, seed=1)
+    nb = 122
+    for step in range(6 * nb):
+        X = synth.plane_wave_fd_torch(mics, 128, 64, 512, 16000.0, 343.0, seed=5_000_000 + step % nb)
+        prop.train_step(X, lr=2e-3 if step < 0.7 * 6 * nb else 5e-4)
+    X = synth.plane_wave_fd_torch(mics, 200, 100, 512, 16000.0, 343.0, seed=9_999_999)
+    F = X.shape[0]
+
+    def timed(fn, n=10):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) / n
+
+    amd.svdphat_timing_reset()
+    amd.svdphat_timing_enable(False, counts=True)
+    out = prop.locate(X, topk=8, conf_min=0.5)
+    torch.cuda.synchronize()
+    amd.svdphat_timing_enable(False)
+    cnt = amd.svdphat_timing_read()
+    amd.svdphat_timing_reset()
+    out, tp = timed(lambda: prop.locate(X, topk=8, conf_min=0.5))
+    full, tf = timed(lambda: plan.locate(X, precision="fp16", rescore=True, hilo=True))
+    plain = plan.locate(X, precision="fp16", rescore=True, hilo=False)
+    doa, fdoa = out["doa"].cpu().numpy(), full["doa"].cpu().numpy()
+    pdoa = plain["doa"].cpu().numpy()
+    fell = out["fell_back"].cpu().numpy().astype(bool)
+    rows, frames = cnt["count:proposal_rows_rescored"]
+    ncls = plan.info["n_classes"]
+    miss = float(np.mean(doa != fdoa))
+    print(f"  miss {miss:.4%}, fell back {fell.mean():.2%}, rows per confident frame {rows / max(frames, 1):.0f} "
+          f"of {ncls}, proposal {1e3 * tp:.3f} ms vs full search {1e3 * tf:.3f} ms ({tf / tp:.2f}x)", flush=True)
+    assert np.array_equal(doa[fell], pdoa[fell])
+    assert miss <= 0.005
+    assert rows / max(frames, 1) <= 0.05 * ncls
+    assert tp <= 2.0 * tf
+    prop.close()
+    plan.close()
