@@ -12,7 +12,10 @@
  *   - Every function returns an int status: SVDPHAT_OK (0) or a negative
  *     SVDPHAT_E_* code.  No C++ exception crosses this boundary.  The
  *     message of the last failure on the calling thread is returned by
- *     svdphat_last_error().
+ *     svdphat_last_error().  For tests, the environment variable
+ *     SVDPHAT_FAULT (comma-separated) forces failures: "alloc" makes every
+ *     device allocation of the library fail (SVDPHAT_E_NOMEM), "eig" makes
+ *     the plan's eigensolver report no convergence (SVDPHAT_E_NUMERIC).
  *   - "host" pointers are read (or written) before the call returns.
  *     "device" pointers are HIP device memory owned by the caller; the call
  *     enqueues work on the given HIP stream (a hipStream_t passed as void*,

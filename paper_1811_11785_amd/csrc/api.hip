@@ -2,6 +2,8 @@
 // pool, and dispatch to the plan builder and the kernel launchers.
 #include "internal.h"
 
+#include <cstdlib>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -28,6 +30,29 @@ void zero_async(void* p, size_t bytes, hipStream_t s) {
 }
 void fail(int code, const std::string& msg) { throw Error{code, msg}; }
 
+bool fault_forced(const char* kind) {
+    const char* env = std::getenv("SVDPHAT_FAULT");
+    if (!env || !*env) return false;
+    const std::string list = std::string(",") + env + ",";
+    return list.find(std::string(",") + kind + ",") != std::string::npos;
+}
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+    if (fault_forced("alloc")) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+void dev_alloc(void** p, size_t bytes, const char* what) {
+    if (dev_malloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        fail(SVDPHAT_E_NOMEM, std::string(what) + ": device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+}
+
 // Workspace of one stream on one plan, grown on demand (hipMalloc outside any
 // kernel; calls on the same plan and stream are ordered by the stream).  A
 // HIP graph captured earlier on the stream may still reference a superseded
@@ -45,13 +70,15 @@ void* ws_get(svdphat_plan* p, hipStream_t s, size_t bytes, int slot) {
                    "the workspace of this stream must grow to " + std::to_string(bytes) +
                        " bytes while the stream is being captured: make one call of this size on the stream "
                        "before capturing");
-        if (w.buf) p->ws_retired.push_back(w.buf);
         size_t n = (size_t)round_up64((int64_t)std::max(bytes, w.bytes + w.bytes / 2), 1 << 20);
         void* nb = nullptr;
-        if (hipMalloc(&nb, n) != hipSuccess) {
+        if (dev_malloc(&nb, n) != hipSuccess) {
             (void)hipGetLastError();
             fail(SVDPHAT_E_NOMEM, "workspace allocation of " + std::to_string(n) + " bytes failed");
         }
+        // (the superseded buffer is retired only once its successor exists,
+        // so a failed growth leaves the workspace as it was)
+        if (w.buf) p->ws_retired.push_back(w.buf);
         w.buf = nb;
         w.bytes = n;
     }
@@ -94,6 +121,7 @@ static void free_plan(svdphat_plan* p) {
     for (auto& kv : p->ws)
         if (kv.second.buf) (void)hipFree(kv.second.buf);
     for (void* b : p->ws_retired) (void)hipFree(b);
+    (void)hipGetLastError();  // no error of the teardown outlives it
     delete p;
 }
 

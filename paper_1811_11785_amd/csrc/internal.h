@@ -321,6 +321,14 @@ void launch_mask(const svdphat_plan* p, const float2* X, int64_t F, const uint8_
 // zero `bytes` (a multiple of 4) of device memory on stream s with a kernel,
 // so that a caller capturing the stream into a graph records a kernel node
 void zero_async(void* p, size_t bytes, hipStream_t s);
+// Fault injection for tests: the environment variable SVDPHAT_FAULT holds a
+// comma-separated list of faults to force ("alloc": every device allocation
+// of the library fails; "eig": the eigensolver reports no convergence).
+bool fault_forced(const char* kind);
+// Every device allocation of the library: hipMalloc, or hipErrorOutOfMemory
+// when the "alloc" fault is forced.  dev_alloc fails with SVDPHAT_E_NOMEM.
+hipError_t dev_malloc(void** p, size_t bytes);
+void dev_alloc(void** p, size_t bytes, const char* what);
 // several peaks per frame (peaks.hip)
 int peaks_max();
 void launch_peaks(const float* y, int64_t F, int Q, int64_t ldy, const float* dirs, int n, float cos_sep,

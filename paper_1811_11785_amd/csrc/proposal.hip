@@ -892,7 +892,7 @@ PW carve(svdphat_proposal* pr, int64_t F, hipStream_t s, int topk = 0) {
                    "the proposal workspace must grow while the stream is being captured");
         const size_t n = std::max(off, pr->ws_bytes + pr->ws_bytes / 2);
         void* nb = nullptr;
-        if (hipMalloc(&nb, n) != hipSuccess) {
+        if (dev_malloc(&nb, n) != hipSuccess) {
             (void)hipGetLastError();
             fail(SVDPHAT_E_NOMEM, "proposal workspace of " + std::to_string(n) + " bytes");
         }
@@ -1051,7 +1051,7 @@ void proposal_build(svdphat_proposal* pr, const double* coarse, int C, int H, ui
     }
     int64_t bytes = 0;
     auto up = [&](const void* h, size_t n, void** d) {
-        if (hipMalloc(d, std::max<size_t>(n, 4)) != hipSuccess) {
+        if (dev_malloc(d, std::max<size_t>(n, 4)) != hipSuccess) {
             *d = nullptr;
             fail(SVDPHAT_E_NOMEM, "proposal allocation of " + std::to_string(n) + " bytes");
         }
@@ -1108,10 +1108,10 @@ void proposal_build(svdphat_proposal* pr, const double* coarse, int C, int H, ui
     up(zeros.data(), sizeof(float) * pr->nparam, (void**)&pr->Vv);
     const size_t wsz[3] = {(size_t)H * D0, (size_t)H * H, (size_t)Cp * H};
     for (int l = 0; l < 3; ++l) {
-        SP_HIP(hipMalloc((void**)&pr->Wh[l], wsz[l] * sizeof(_Float16)));
-        SP_HIP(hipMalloc((void**)&pr->Wt[l], wsz[l] * sizeof(_Float16)));
+        dev_alloc((void**)&pr->Wh[l], wsz[l] * sizeof(_Float16), "proposal weights");
+        dev_alloc((void**)&pr->Wt[l], wsz[l] * sizeof(_Float16), "proposal weights");
     }
-    SP_HIP(hipMalloc((void**)&pr->d_count, 8 * sizeof(int)));
+    dev_alloc((void**)&pr->d_count, 8 * sizeof(int), "proposal counters");
     cast_weights(pr, nullptr);
     SP_HIP(hipDeviceSynchronize());
 }
@@ -1354,6 +1354,7 @@ void proposal_free(svdphat_proposal* pr) {
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (void* b : pr->ws_retired) (void)hipFree(b);
+    (void)hipGetLastError();  // no error of the teardown outlives it
     delete pr;
 }
 

@@ -90,6 +90,7 @@ void free_ragged(svdphat_ragged* r) {
     if (r->d_desc) (void)hipFree(r->d_desc);
     if (r->h_desc) (void)hipHostFree(r->h_desc);
     if (r->ws) (void)hipFree(r->ws);
+    (void)hipGetLastError();  // no error of the teardown outlives it
     delete r;
 }
 
@@ -167,12 +168,12 @@ void ragged_build(svdphat_ragged* r, uint32_t flags, const char* cache_path) {
         of[i].zn = take(sizeof(float) * Fc);
         of[i].pm = take(sizeof(float) * pmax_stride(p) * Fc);
     }
-    if (hipMalloc(&r->ws, std::max<size_t>(total, 256)) != hipSuccess) {
+    if (dev_malloc(&r->ws, std::max<size_t>(total, 256)) != hipSuccess) {
         r->ws = nullptr;
         fail(SVDPHAT_E_NOMEM, "ragged workspace of " + std::to_string(total) + " bytes");
     }
     SP_HIP(hipHostMalloc((void**)&r->h_desc, sizeof(RDesc) * n, hipHostMallocDefault));
-    SP_HIP(hipMalloc((void**)&r->d_desc, sizeof(RDesc) * n));
+    dev_alloc((void**)&r->d_desc, sizeof(RDesc) * n, "ragged descriptors");
     char* w = (char*)r->ws;
     for (int i = 0; i < n; ++i) {
         svdphat_plan* p = r->plans[i];
@@ -290,7 +291,7 @@ void ragged_build(svdphat_ragged* r, uint32_t flags, const char* cache_path) {
         gl.cls = kv.first.second;
         gl.nwork = (int)kv.second.size();
         gl.lds = lds.count(kv.first) ? lds[kv.first] : 0;
-        SP_HIP(hipMalloc((void**)&gl.work, sizeof(int4) * kv.second.size()));
+        dev_alloc((void**)&gl.work, sizeof(int4) * kv.second.size(), "ragged work list");
         SP_HIP(hipMemcpy(gl.work, kv.second.data(), sizeof(int4) * kv.second.size(), hipMemcpyHostToDevice));
         r->launches.push_back(gl);
     }

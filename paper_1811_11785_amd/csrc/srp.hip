@@ -205,13 +205,13 @@ void build_w_fp32_frags(svdphat_plan* p) {
     p->Wks = Wk;
     p->Wrows_pad = round_up(p->Q, 128);
     const int64_t total = (int64_t)p->Wrows_pad * Wk * 4;
-    if (hipMalloc((void**)&p->Wfr, total * sizeof(float)) != hipSuccess) {
+    if (dev_malloc((void**)&p->Wfr, total * sizeof(float)) != hipSuccess) {
         p->Wfr = nullptr;
         fail(SVDPHAT_E_NOMEM, "device allocation of W (" + std::to_string(total * 4) + " bytes) failed");
     }
     p->device_bytes += total * (int64_t)sizeof(float);
     double* dtau = nullptr;
-    SP_HIP(hipMalloc((void**)&dtau, p->tau.size() * sizeof(double)));
+    dev_alloc((void**)&dtau, p->tau.size() * sizeof(double), "steering delays");
     SP_HIP(hipMemcpy(dtau, p->tau.data(), p->tau.size() * sizeof(double), hipMemcpyHostToDevice));
     k_w_frag<<<dim3((unsigned)((total + 255) / 256)), 256>>>(dtau, p->Q, p->P, p->N, p->L, Wk, p->Wrows_pad, p->Wfr);
     hipError_t e = hipGetLastError();
