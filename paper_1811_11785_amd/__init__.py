@@ -17,7 +17,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsvdphat.so")
+LIB_PATH = os.environ.get("SVDPHAT_LIB") or os.path.join(HERE, "libsvdphat.so")  # (a variant build: testing)
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NUMERIC, E_NODEV, E_UNSUPPORTED, E_IO = 0, -1, -2, -3, -4, -5, -6, -7
 KEEP_W, NO_DEDUP = 0x1, 0x2
