@@ -139,6 +139,8 @@ def main():
     ap.add_argument("--train-frames", type=int, default=2_000_000, help="training pairs of the proposal")
     ap.add_argument("--train-epochs", type=int, default=20, help="passes over the proposal's training pairs")
     ap.add_argument("--arrays", type=int, default=256, help="arrays of the ragged workload")
+    ap.add_argument("--single-frames", type=int, default=2048,
+                    help="single-frame calls timed at batch 1 (3-D workloads)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MB (a known-size reference "
                          "for hardware byte counters)")
@@ -157,10 +159,7 @@ def main():
     amd.lib()
     if args.workload == "ragged256":
         return bench_ragged(args, torch, amd, synth)
-    if args.workload == "proposal_q40962":
-        return bench_proposal(args, torch, amd, synth)
-    if args.workload in ("cube_q10242", "cube_q40962"):
-        return bench_cube(args, torch, amd, synth)
+    # a plain device copy of known size, to scale the traffic counters
     if args.calib_copy_mb:
         n = args.calib_copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -168,6 +167,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload == "proposal_q40962":
+        return bench_proposal(args, torch, amd, synth)
+    if args.workload in ("cube_q10242", "cube_q40962"):
+        return bench_cube(args, torch, amd, synth)
     w = synth.workload("planar_q10242", frames=args.frames)
     F = w["X"].shape[0]
     t0 = time.perf_counter()
@@ -426,7 +429,7 @@ def bench_cube(args, torch, amd, synth):
            "plan_build_s": plan_s, "batches": {}}
     for B in [int(b) for b in args.batches.split(",")]:
         if B == 1:
-            n1 = 2048
+            n1 = args.single_frames
             sl = [X[f:f + 1] for f in range(n1)]
             outs = [(doa[f:f + 1], power[f:f + 1], yhat[f:f + 1], margin[f:f + 1]) for f in range(n1)]
 
@@ -461,7 +464,7 @@ def bench_cube(args, torch, amd, synth):
             # per-kernel durations (HIP events around each launch)
             amd.svdphat_timing_reset()
             amd.svdphat_timing_enable(True)
-            for f in range(256):
+            for f in range(min(256, n1)):
                 amd.svdphat_locate(h, sl[f], prec, mode, *outs[f])
             amd.svdphat_timing_enable(False)
             kt = amd.svdphat_timing_read()
