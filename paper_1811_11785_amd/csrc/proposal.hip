@@ -1146,18 +1146,15 @@ void proposal_locate(svdphat_proposal* pr, const float2* X, int64_t F, int topk,
     kt.begin("prop_front");
     front_fp16(p, X, F, o.zpart, o.z32, o.zfrag, o.zsc, o.zn, s);
     kt.end();
-    // the forward pass: fused, with as many frames per workgroup as two
-    // workgroups' activations fit a CU's LDS (else layer by layer)
+    // the forward pass: fused, 32 frames per workgroup (61 us per 20,000
+    // frames at hidden 256, against 71 with 64 and 84 with 16: more
+    // workgroups in flight hide the weight loads, fewer reuse them less),
+    // 16 where 32 frames' activations do not fit; else layer by layer
     kt.begin("prop_mlp");
     const size_t lds_cap = 80 * 1024;
-    const int ft = mlp_infer_lds(64, D0, H) <= lds_cap ? 64 : mlp_infer_lds(32, D0, H) <= lds_cap ? 32
-                   : mlp_infer_lds(16, D0, H) <= 2 * lds_cap ? 16 : 0;
+    const int ft = mlp_infer_lds(32, D0, H) <= lds_cap ? 32 : mlp_infer_lds(16, D0, H) <= 2 * lds_cap ? 16 : 0;
     const float* P = pr->P;
-    if (ft == 64)
-        k_mlp_infer<64><<<dim3((unsigned)cdiv64(F, 64)), 256, mlp_infer_lds(64, D0, H), s>>>(
-            o.z32, o.zn, F, D0, H, Cp, pr->Wh[0], P + pr->off[1], pr->Wh[1], P + pr->off[3], pr->Wh[2],
-            P + pr->off[5], o.logits);
-    else if (ft == 32)
+    if (ft == 32)
         k_mlp_infer<32><<<dim3((unsigned)cdiv64(F, 32)), 256, mlp_infer_lds(32, D0, H), s>>>(
             o.z32, o.zn, F, D0, H, Cp, pr->Wh[0], P + pr->off[1], pr->Wh[1], P + pr->off[3], pr->Wh[2],
             P + pr->off[5], o.logits);
