@@ -114,6 +114,8 @@ static void free_plan(svdphat_plan* p) {
         if (p->Alo[i]) (void)hipFree(p->Alo[i]);
         for (auto& sr : p->sr)
             if (sr.Ufr[i]) (void)hipFree(sr.Ufr[i]);
+        for (void* a : p->As[i])
+            if (a) (void)hipFree(a);
     }
     void* bufs[] = {p->sr[0].U32T, p->sr[1].U32T, p->A32T, p->sr[0].tkappa, p->sr[1].tkappa, p->d_sig, p->d_rows, p->d_rep, p->d_rowof, p->d_tauN, p->d_tauN_all, p->d_tauM_all, p->d_rowcls, p->d_pi, p->d_pj, p->Wfr};
     for (void* b : bufs)

@@ -428,13 +428,18 @@ bool g1s_layout(int M, int nRB, int kstep, int* CW, int* BB) {
 bool g1s_sched(int prec, const svdphat_plan* p, int64_t F, G1Sched* out) {
     const int nRB = p->Rp / 16;
     int cw = 0, bb = 0;
-    const G1Layout& g = p->g1[prec];
-    if (prec == P_FP32 || p->B < 2 || F < 1 || !g1s_layout(p->M, nRB, 32, &cw, &bb) || g.CW != cw || g.BB != bb)
-        return false;
+    const bool split = p->as_split > 0 && prec != P_FP32;  // two row-group passes
+    const G1Layout& g = split ? p->g1s[prec] : p->g1[prec];
+    if (prec == P_FP32 || p->B < 2 || F < 1) return false;
+    if (!split && (!g1s_layout(p->M, nRB, 32, &cw, &bb) || g.CW != cw || g.BB != bb)) return false;
     G1Sched sc;
     const int64_t ftiles = (F + G1S_NF - 1) / G1S_NF;
     sc.nch = g.nch;
     sc.U = ftiles * g.nch;
+    // two passes pay the pipeline's start twice: only with at least 8 units
+    // per workgroup of a full grid (at 4096 frames of the 3-D plan, K = 71:
+    // 67 us against 75 for the general kernel; at 256 frames 54 against 36)
+    if (split && sc.U < 8 * (int64_t)cu_count(p->device)) return false;
     // one workgroup per CU, at least 8 units each
     sc.G = (int)std::max<int64_t>(1, std::min<int64_t>(cu_count(p->device), sc.U / 8));
     int runs = 1;
@@ -445,11 +450,12 @@ bool g1s_sched(int prec, const svdphat_plan* p, int64_t F, G1Sched* out) {
     return true;
 }
 
-void launch_g1_streamed(int prec, const svdphat_plan* p, const G1Sched& sc, const float2* X, int64_t F, float* zpart,
-                        int64_t zstride, hipStream_t s) {
-    const int nRB = p->Rp / 16;
-    const void* A = p->A[prec];
+// one launch of the streamed kernel over nRB row blocks whose A fragments
+// start at A, writing rows 0 .. 16 nRB - 1 of the Z slots at zpart
+static void launch_g1_pass(int prec, const svdphat_plan* p, const G1Sched& sc, const float2* X, int64_t F,
+                           const void* A, int nRB, float* zpart, int64_t zstride, hipStream_t s) {
     const int B = p->B, Rp = p->Rp;
+    SP_REQUIRE(nRB == 2 || nRB == 4 || nRB == 6, SVDPHAT_E_UNSUPPORTED, "streamed GEMM1: 2, 4 or 6 row blocks");
     if (prec == P_FP16) {
         switch (p->M) {
             case 6: launch_mm<_Float16, 6>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp); return;
@@ -464,6 +470,21 @@ void launch_g1_streamed(int prec, const svdphat_plan* p, const G1Sched& sc, cons
         }
     }
     fail(SVDPHAT_E_UNSUPPORTED, "streamed GEMM1 launched for an unsupported plan");
+}
+
+void launch_g1_streamed(int prec, const svdphat_plan* p, const G1Sched& sc, const float2* X, int64_t F, float* zpart,
+                        int64_t zstride, hipStream_t s) {
+    if (p->as_split > 0) {
+        // two passes over the frames, each with its row group's A; the second
+        // writes Z's rows from 16 as_split on, in the same slots (the two
+        // passes share the schedule)
+        const int nRB = p->Rp / 16, n0 = p->as_split;
+        launch_g1_pass(prec, p, sc, X, F, p->As[prec][0], n0, zpart, zstride, s);
+        SP_HIP(hipGetLastError());
+        launch_g1_pass(prec, p, sc, X, F, p->As[prec][1], nRB - n0, zpart + 16 * n0, zstride, s);
+        return;
+    }
+    launch_g1_pass(prec, p, sc, X, F, p->A[prec], p->Rp / 16, zpart, zstride, s);
 }
 
 }  // namespace svdphat

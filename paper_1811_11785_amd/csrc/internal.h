@@ -237,6 +237,12 @@ struct svdphat_plan {
     // device operands (all owned)
     void* A[3] = {nullptr, nullptr, nullptr};    // GEMM1 operand per precision
     void* Alo[3] = {nullptr, nullptr, nullptr};  // low parts (16-bit only)
+    // streamed GEMM1 in two row-group passes (8 to 12 row blocks of Z, 6 to
+    // 8 microphones, 16-bit operands): A of row blocks [0, as_split) and
+    // [as_split, Rp / 16) in the streamed chunk layout g1s; as_split = 0: none
+    void* As[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+    int as_split = 0;
+    svdphat::G1Layout g1s[3];
     svdphat::ScoreRows sr[2];                    // scored rows: [0] U (eq. (14)), [1] U / ||U sigma|| (eq. (15))
     float* A32T = nullptr;                       // [B P 2][Rp] FP32 A = S V^H, transposed (GEMV form)
     float* d_sig = nullptr;                      // [Rp] singular value of each stacked row of Z

@@ -123,18 +123,23 @@ G1Layout make_layout(int P, int B, int M, int esize, int kstep, int nRB, int epl
 // block rb and lane l, the EPL elements A[rb*16 + l%16][ks*KSTEP +
 // EPL*(l/16) + e] of that chunk's columns.  Column (b, p, ri) of a chunk is
 // (b * P + p) * 2 + ri, bin = ch * BB + b.
+// (rb0, nrb: only row blocks [rb0, rb0 + nrb), packed as blocks 0 .. nrb-1;
+// nrb = 0: all)
 template <typename T>
 static void pack_A(const svdphat_plan* p, const G1Layout& g, std::vector<T>& hi, std::vector<T>& lo,
-                   bool want_lo) {
+                   bool want_lo, int rb0 = 0, int nrb = 0) {
     constexpr int KS = Mf<T>::KSTEP, EPL = Mf<T>::EPL;
-    const int K = p->K, P = p->P, nRB = p->Rp / 16;
-    hi.assign(g.elems, to_t<T>(0.f));
-    if (want_lo) lo.assign(g.elems, to_t<T>(0.f));
+    const int K = p->K, P = p->P;
+    const int nRB = nrb > 0 ? nrb : p->Rp / 16;
+    const int64_t elems = (int64_t)g.nch * g.ks_chunk * nRB * 64 * EPL;
+    hi.assign(elems, to_t<T>(0.f));
+    if (want_lo) lo.assign(elems, to_t<T>(0.f));
     for (int ch = 0; ch < g.nch; ++ch)
         for (int ks = 0; ks < g.ks_chunk; ++ks)
-            for (int rb = 0; rb < nRB; ++rb)
+            for (int rbl = 0; rbl < nRB; ++rbl)
                 for (int l = 0; l < 64; ++l)
                     for (int e = 0; e < EPL; ++e) {
+                        const int rb = rb0 + rbl;
                         int r = rb * 16 + l % 16;
                         int col = ks * KS + EPL * (l / 16) + e;
                         int b = col / (2 * P), rem = col % (2 * P);
@@ -151,7 +156,7 @@ static void pack_A(const svdphat_plan* p, const G1Layout& g, std::vector<T>& hi,
                             if (r < K) v = ri == 0 ? ar : -ai;
                             else v = ri == 0 ? ai : ar;
                         }
-                        int64_t off = ((((int64_t)ch * g.ks_chunk + ks) * nRB + rb) * 64 + l) * EPL + e;
+                        int64_t off = ((((int64_t)ch * g.ks_chunk + ks) * nRB + rbl) * 64 + l) * EPL + e;
                         float vf = (float)v;
                         T h = to_t<T>(vf);
                         hi[off] = h;
@@ -484,6 +489,33 @@ void build_plan(svdphat_plan* p, const double* mics, const double* grid, bool fa
         pack_A<__bf16>(p, p->g1[P_BF16], bh, bl, true);
         upload(bh, &p->A[P_BF16], bytes);
         upload(bl, &p->Alo[P_BF16], bytes);
+        // two row-group passes of the streamed GEMM1 where Z has 8 to 12 row
+        // blocks (6 in the first pass, the rest in the second)
+        int cws = 0, bbs = 0;
+        p->as_split = 0;
+        if ((nRB == 8 || nRB == 10 || nRB == 12) && B >= 2 && g1s_layout(M, 6, Mf<_Float16>::KSTEP, &cws, &bbs)) {
+            p->as_split = 6;
+            for (int pr : {P_FP16, P_BF16}) {
+                G1Layout& gs = p->g1s[pr];
+                gs.CW = cws;
+                gs.BB = bbs;
+                gs.nch = cdiv(B, bbs);
+                gs.ks_chunk = cws / Mf<_Float16>::KSTEP;
+                gs.elems = 0;
+                for (int g = 0; g < 2; ++g) {
+                    const int rb0 = g == 0 ? 0 : 6, nrb = g == 0 ? 6 : nRB - 6;
+                    if (pr == P_FP16) {
+                        std::vector<_Float16> sh, sl;
+                        pack_A<_Float16>(p, gs, sh, sl, false, rb0, nrb);
+                        upload(sh, &p->As[pr][g], bytes);
+                    } else {
+                        std::vector<__bf16> sh, sl;
+                        pack_A<__bf16>(p, gs, sh, sl, false, rb0, nrb);
+                        upload(sh, &p->As[pr][g], bytes);
+                    }
+                }
+            }
+        }
         // FP32 rows of A = S V^H transposed for the GEMV form of small
         // batches: [(b P + p) 2 + ri][Rp], stacked as in pack_A
         std::vector<float> at((size_t)B * P * 2 * p->Rp, 0.f);
