@@ -226,9 +226,14 @@ int64_t svdphat_noalloc_scratch_bytes(void);
  *   mask   device, uint8 [F][N/2+1]: nonzero keeps bin k of frame f, 0 drops
  *          it (a frame with every bin dropped has every power 0 and returns
  *          the lowest index, as a silent frame does).
- *   The other arguments are those of svdphat_locate.  The masked frames are
- *   written to a second workspace of the plan and stream (F (N/2+1) M 8
- *   bytes), which is grown on demand like the first.
+ *   The other arguments are those of svdphat_locate.  For FP16 and BF16
+ *   batches of 6 to 8 microphones, the kernels read the mask with the
+ *   frames.  A hi/lo pass still needs a second workspace of the plan and
+ *   stream, of F (N/2+1) M 8 bytes, into which its listed frames are copied
+ *   masked.  Otherwise (FP32, small batches of 16 frames or fewer, other
+ *   plans), every masked frame is written to that workspace first.  The
+ *   workspace is grown on demand like the first.  The results are the same
+ *   either way: those of svdphat_locate on frames whose dropped bins hold 0.
  * Errors: as svdphat_locate; E_INVAL also for a NULL mask with F > 0.
  */
 int svdphat_locate_masked(svdphat_plan* plan, const void* X, int64_t F,

@@ -391,9 +391,21 @@ int svdphat_locate_masked(svdphat_plan* p, const void* X, int64_t F, const uint8
         SP_REQUIRE(X && mask && doa && power, SVDPHAT_E_INVAL, "NULL X, mask, doa or power");
         SP_HIP(hipSetDevice(p->device));
         const hipStream_t s = (hipStream_t)stream;
-        // the masked frames live in the stream's second workspace slot for the
-        // whole call (the power of Algorithm 1 step 4 reads them last)
-        float2* xm = (float2*)ws_get(p, s, (size_t)F * p->M * p->B * sizeof(float2), 1);
+        const size_t xbytes = (size_t)F * p->M * p->B * sizeof(float2);
+        if (mask_fused(p, F, precision, y_opt != nullptr)) {
+            // the streamed GEMM1's producers and the power kernel read the
+            // mask with the frames; only the hi/lo pass's listed frames are
+            // copied masked, each to its own place in the stream's second
+            // workspace slot
+            const bool hilo = (mode & (SVDPHAT_HILO | SVDPHAT_HILO_ALL)) && precision != SVDPHAT_FP32;
+            float2* xm = hilo ? (float2*)ws_get(p, s, xbytes, 1) : nullptr;
+            launch_locate(p, X, F, precision, mode, doa, power, yhat, margin, y_opt, s, nullptr, 0, mask, xm);
+            return;
+        }
+        // otherwise the masked frames are written whole into that slot, which
+        // holds them for the whole call (the power of Algorithm 1 step 4
+        // reads them last)
+        float2* xm = (float2*)ws_get(p, s, xbytes, 1);
         launch_mask(p, (const float2*)X, F, mask, xm, s);
         launch_locate(p, xm, F, precision, mode, doa, power, yhat, margin, y_opt, s);
     });

@@ -55,7 +55,7 @@ __device__ __forceinline__ typename Vec<T>::pair mkpair(T a, T b) {
 // finite normal float (silent, or non-finite input) are treated as silent and
 // give 0, so every product they enter is 0.
 __device__ __forceinline__ void unit(float& re, float& im) {
-    const float m2 = re * re + im * im;
+    const float m2 = fmaf(re, re, im * im);
     const bool ok = m2 >= FLT_MIN && m2 <= FLT_MAX;
     const float s = ok ? rsqrtf(m2) : 0.f;
     re = ok ? re * s : 0.f;
@@ -158,9 +158,10 @@ __device__ __forceinline__ bool better(float a, int ia, float b, int ib) {
 // Bmain = B - tail bins (all STFT loads of a block of 4 x 64 bins issued
 // before any is used), and the last `tail` bins (B mod 64 when tail x M <=
 // 64, typically the Nyquist bin) one (bin, microphone) per lane.  Returns
-// the wave's total.
+// the wave's total.  MK: mk = the frame's mask bytes [B]; a bin it drops
+// contributes nothing (as a silent bin).
 __device__ __forceinline__ float ds_term(float2 x, bool live, float cr, float ci, float& sre, float& sim) {
-    const float m2 = x.x * x.x + x.y * x.y;
+    const float m2 = fmaf(x.x, x.x, x.y * x.y);
     const bool ok = live && __builtin_amdgcn_classf(m2, 0x100);
     const float s = __builtin_amdgcn_rsqf(m2);
     const float ur = ok ? x.x * s : 0.f, ui = ok ? x.y * s : 0.f;
@@ -169,22 +170,23 @@ __device__ __forceinline__ float ds_term(float2 x, bool live, float cr, float ci
     return ok ? 1.f : 0.f;
 }
 
-template <int MAXM>
+template <int MAXM, bool MK = false>
 __device__ __forceinline__ float power_ds(const float2* __restrict__ xf, int M, int B, const float (&t)[MAXM],
-                                          int lane) {
+                                          int lane, const uint8_t* __restrict__ mk = nullptr) {
     constexpr int NJ = MAXM <= 8 ? 4 : 1;
     const int tail = ((B % 64) * M <= 64) ? B % 64 : 0;
     const int Bm = B - tail;
     float acc = 0.f;
     for (int b0 = 0; b0 < Bm; b0 += 64 * NJ) {
         float2 v[NJ][MAXM];
+        bool kp[NJ];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j)
+        for (int j = 0; j < NJ; ++j) {
+            const int bin = b0 + lane + 64 * j;
 #pragma unroll
-            for (int m = 0; m < MAXM; ++m) {
-                const int bin = b0 + lane + 64 * j;
-                v[j][m] = xf[(bin < Bm && m < M) ? (int64_t)m * B + bin : 0];
-            }
+            for (int m = 0; m < MAXM; ++m) v[j][m] = xf[(bin < Bm && m < M) ? (int64_t)m * B + bin : 0];
+            kp[j] = !MK || mk[bin < Bm ? bin : 0] != 0;
+        }
         // phase of the lane's first bin and its step over 64 bins, per mic
         float cr[MAXM], ci[MAXM], sr[MAXM], si[MAXM];
 #pragma unroll
@@ -200,7 +202,7 @@ __device__ __forceinline__ float power_ds(const float2* __restrict__ xf, int M, 
         }
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-            const bool live = b0 + lane + 64 * j < Bm;
+            const bool live = b0 + lane + 64 * j < Bm && kp[j];
             float sre = 0.f, sim = 0.f, cnt = 0.f;
 #pragma unroll
             for (int m = 0; m < MAXM; ++m)
@@ -220,6 +222,7 @@ __device__ __forceinline__ float power_ds(const float2* __restrict__ xf, int M, 
         const bool mine = lane >= tb * M && lane < (tb + 1) * M;
         const int m = lane - tb * M;
         const float2 x = xf[mine ? (int64_t)m * B + bin : 0];
+        const bool kb = !MK || mk[bin] != 0;
         float tm = 0.f;
 #pragma unroll
         for (int k = 0; k < MAXM; ++k)
@@ -227,7 +230,7 @@ __device__ __forceinline__ float power_ds(const float2* __restrict__ xf, int M, 
         float p0 = (float)bin * tm;
         p0 -= rintf(p0);
         float sre = 0.f, sim = 0.f;
-        const float cnt = ds_term(x, mine, __builtin_amdgcn_cosf(p0), -__builtin_amdgcn_sinf(p0), sre, sim);
+        const float cnt = ds_term(x, mine && kb, __builtin_amdgcn_cosf(p0), -__builtin_amdgcn_sinf(p0), sre, sim);
         const float sr = wave_sum(sre), sm = wave_sum(sim), c = wave_sum(cnt);
         tot += 0.5f * (fmaf(sr, sr, sm * sm) - c);
     }

@@ -69,7 +69,7 @@ struct __attribute__((aligned(8))) f4u {
 // STFT value, rounded to a half pair; values whose |X|^2 is not a finite
 // normal float are silent and give 0
 __device__ __forceinline__ h2 unit_h2(float re, float im) {
-    const float m2 = re * re + im * im;
+    const float m2 = fmaf(re, re, im * im);  // fused as written, so every instance rounds alike
     const float s = __builtin_amdgcn_rsqf(m2);
     const h2 u = h2{(_Float16)(re * s), (_Float16)(im * s)};
     return __builtin_amdgcn_classf(m2, 0x100) ? u : h2{(_Float16)0.f, (_Float16)0.f};
@@ -89,10 +89,11 @@ __device__ inline int g1s_phi(int64_t t, int nch, int G, int64_t U) {
     return s2 < t0 + nch ? (int)(nch - (s2 - t0)) : 0;
 }
 
-template <typename T, int MM, int NRB, int XD>
+template <typename T, int MM, int NRB, int XD, bool MK>
 __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, int64_t nfr, int B,
                                                 const T* __restrict__ A, int nch, int64_t U,
-                                                float* __restrict__ zpart, int64_t zstride, int Rp) {
+                                                float* __restrict__ zpart, int64_t zstride, int Rp,
+                                                const uint8_t* __restrict__ mask) {
     constexpr int KS = Mf<T>::KSTEP, EPL = Mf<T>::EPL, NF = G1S_NF, FB = NF / 16;
     constexpr int P = MM * (MM - 1) / 2, TWOP = 2 * P;
     constexpr int BB = G1S_BB, BP = BB / 2;
@@ -164,6 +165,9 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
         // bins 0-1; the values are selected (or zeroed) where consumed.
         f4u xv[XD][MM];
         int xmode[XD];  // 2: both bins, 1: first bin only (shifted load), 0: none
+        // MK: the mask bytes of the two loaded bins (bit 0: the load's first
+        // bin, bit 8: its second), fetched with the values
+        int xmk[XD];
         auto fetch = [&](int d, const Cur& cu) {
             const int64_t t = cu.t;
             const int c = chunk(cu);
@@ -174,6 +178,10 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
             const int64_t off = mode == 2 ? f * MM * B + s0 : mode == 1 ? f * MM * B + s0 - 1 : 0;
 #pragma unroll
             for (int m = 0; m < MM; ++m) xv[d][m] = *reinterpret_cast<const f4u*>(X + off + (int64_t)m * B);
+            if constexpr (MK) {
+                const int64_t mo = mode == 2 ? f * B + s0 : mode == 1 ? f * B + s0 - 1 : 0;
+                xmk[d] = (int)mask[mo] | ((int)mask[mo + 1] << 8);
+            }
         };
         // PHAT tile of one chunk from ring slot d; FULL: every pair of the
         // chunk lies inside the data (no per-value selection)
@@ -183,6 +191,10 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 VP* dst = reinterpret_cast<VP*>(xs + fl * LDX + (b0 + q) * TWOP);
+                // MK: whether the mask keeps this bin (bin q of the pair is the
+                // load's bin q, or its second bin for the shifted load)
+                bool keep = true;
+                if constexpr (MK) keep = (xmk[d] >> (q == 1 || (!FULL && mode == 1) ? 8 : 0)) & 0xFF;
                 float re[MM], im[MM];
 #pragma unroll
                 for (int m = 0; m < MM; ++m) {
@@ -202,6 +214,9 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
                     h2 u[MM];
 #pragma unroll
                     for (int m = 0; m < MM; ++m) u[m] = unit_h2(re[m], im[m]);
+                    if constexpr (MK)
+#pragma unroll
+                        for (int m = 0; m < MM; ++m) u[m] = keep ? u[m] : h2{(_Float16)0.f, (_Float16)0.f};
                     // (Re, Im) of X_i conj(X_j) = (a c + b d, b c - a d) for
                     // X_i = a + ib, X_j = c + id
                     int p = 0;
@@ -218,13 +233,21 @@ __global__ __launch_bounds__(512) void k_gemm1s(const float2* __restrict__ X, in
                 } else {
 #pragma unroll
                     for (int m = 0; m < MM; ++m) unit(re[m], im[m]);
+                    if constexpr (MK)
+#pragma unroll
+                        for (int m = 0; m < MM; ++m) {
+                            re[m] = keep ? re[m] : 0.f;
+                            im[m] = keep ? im[m] : 0.f;
+                        }
                     int p = 0;
 #pragma unroll
                     for (int i = 0; i < MM; ++i)
 #pragma unroll
                         for (int j = i + 1; j < MM; ++j) {
-                            dst[p] = mkpair<T>(cvt<T>(re[i] * re[j] + im[i] * im[j]),
-                                               cvt<T>(im[i] * re[j] - re[i] * im[j]));
+                            // FMAs as written: every instance of the kernel
+                            // (with or without the mask) rounds alike
+                            dst[p] = mkpair<T>(cvt<T>(fmaf(re[i], re[j], im[i] * im[j])),
+                                               cvt<T>(fmaf(im[i], re[j], -(re[i] * im[j]))));
                             ++p;
                         }
                 }
@@ -389,14 +412,19 @@ constexpr size_t g1s_lds() {
 
 template <typename T, int MM>
 void launch_mm(int nRB, int G, hipStream_t s, const float2* X, int64_t F, int B, const void* A, int nch, int64_t U,
-               float* zpart, int64_t zstride, int Rp) {
+               float* zpart, int64_t zstride, int Rp, const uint8_t* mask) {
     const T* a = (const T*)A;
     switch (nRB) {
-#define G1S_CASE(NRB_)                                                                                         \
-    case NRB_:                                                                                                 \
-        if constexpr (g1s_ok(MM, NRB_))                                                                        \
-            k_gemm1s<T, MM, NRB_, G1S_XD><<<G, 512, g1s_lds<T, MM, NRB_>(), s>>>(X, F, B, a, nch, U, zpart, zstride, \
-                                                                           Rp);                               \
+#define G1S_CASE(NRB_)                                                                                          \
+    case NRB_:                                                                                                  \
+        if constexpr (g1s_ok(MM, NRB_)) {                                                                       \
+            constexpr size_t lds = g1s_lds<T, MM, NRB_>();                                                      \
+            if (mask)                                                                                           \
+                k_gemm1s<T, MM, NRB_, G1S_XD, true><<<G, 512, lds, s>>>(X, F, B, a, nch, U, zpart, zstride, Rp, mask); \
+            else                                                                                                \
+                k_gemm1s<T, MM, NRB_, G1S_XD, false><<<G, 512, lds, s>>>(X, F, B, a, nch, U, zpart, zstride, Rp,   \
+                                                                      nullptr);                                 \
+        }                                                                                                       \
         return;
         G1S_CASE(2)
         G1S_CASE(4)
@@ -453,38 +481,39 @@ bool g1s_sched(int prec, const svdphat_plan* p, int64_t F, G1Sched* out) {
 // one launch of the streamed kernel over nRB row blocks whose A fragments
 // start at A, writing rows 0 .. 16 nRB - 1 of the Z slots at zpart
 static void launch_g1_pass(int prec, const svdphat_plan* p, const G1Sched& sc, const float2* X, int64_t F,
-                           const void* A, int nRB, float* zpart, int64_t zstride, hipStream_t s) {
+                           const void* A, int nRB, float* zpart, int64_t zstride, const uint8_t* mask,
+                           hipStream_t s) {
     const int B = p->B, Rp = p->Rp;
     SP_REQUIRE(nRB == 2 || nRB == 4 || nRB == 6, SVDPHAT_E_UNSUPPORTED, "streamed GEMM1: 2, 4 or 6 row blocks");
     if (prec == P_FP16) {
         switch (p->M) {
-            case 6: launch_mm<_Float16, 6>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp); return;
-            case 7: launch_mm<_Float16, 7>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp); return;
-            case 8: launch_mm<_Float16, 8>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp); return;
+            case 6: launch_mm<_Float16, 6>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp, mask); return;
+            case 7: launch_mm<_Float16, 7>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp, mask); return;
+            case 8: launch_mm<_Float16, 8>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp, mask); return;
         }
     } else {
         switch (p->M) {
-            case 6: launch_mm<__bf16, 6>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp); return;
-            case 7: launch_mm<__bf16, 7>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp); return;
-            case 8: launch_mm<__bf16, 8>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp); return;
+            case 6: launch_mm<__bf16, 6>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp, mask); return;
+            case 7: launch_mm<__bf16, 7>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp, mask); return;
+            case 8: launch_mm<__bf16, 8>(nRB, sc.G, s, X, F, B, A, sc.nch, sc.U, zpart, zstride, Rp, mask); return;
         }
     }
     fail(SVDPHAT_E_UNSUPPORTED, "streamed GEMM1 launched for an unsupported plan");
 }
 
 void launch_g1_streamed(int prec, const svdphat_plan* p, const G1Sched& sc, const float2* X, int64_t F, float* zpart,
-                        int64_t zstride, hipStream_t s) {
+                        int64_t zstride, hipStream_t s, const uint8_t* mask) {
     if (p->as_split > 0) {
         // two passes over the frames, each with its row group's A; the second
         // writes Z's rows from 16 as_split on, in the same slots (the two
         // passes share the schedule)
         const int nRB = p->Rp / 16, n0 = p->as_split;
-        launch_g1_pass(prec, p, sc, X, F, p->As[prec][0], n0, zpart, zstride, s);
+        launch_g1_pass(prec, p, sc, X, F, p->As[prec][0], n0, zpart, zstride, mask, s);
         SP_HIP(hipGetLastError());
-        launch_g1_pass(prec, p, sc, X, F, p->As[prec][1], nRB - n0, zpart + 16 * n0, zstride, s);
+        launch_g1_pass(prec, p, sc, X, F, p->As[prec][1], nRB - n0, zpart + 16 * n0, zstride, mask, s);
         return;
     }
-    launch_g1_pass(prec, p, sc, X, F, p->A[prec], p->Rp / 16, zpart, zstride, s);
+    launch_g1_pass(prec, p, sc, X, F, p->A[prec], p->Rp / 16, zpart, zstride, mask, s);
 }
 
 }  // namespace svdphat

@@ -172,8 +172,9 @@ struct G1Sched {
     int slots = 0;
 };
 bool g1s_sched(int prec, const svdphat_plan* p, int64_t F, G1Sched* out);
+// mask: NULL, or uint8 [F][B] (0 drops the frame's bin from the PHAT tiles)
 void launch_g1_streamed(int prec, const svdphat_plan* p, const G1Sched& sc, const float2* X, int64_t F, float* zpart,
-                        int64_t zstride, hipStream_t s);
+                        int64_t zstride, hipStream_t s, const uint8_t* mask = nullptr);
 // times one GEMM1 + Z prep (nsplit) and one GEMM2 (fch) of plan p on F
 // synthetic frames in FP16; returns microseconds
 void proposal_build(svdphat_proposal* pr, const double* coarse, int C, int H, uint64_t seed);
@@ -295,9 +296,16 @@ inline int pmax_stride(const svdphat_plan* p) { return round_up(p->ncls_pad / QT
 // launchers
 // scratch: a caller-provided device buffer of scratch_bytes for the call's
 // intermediate results (nullptr: the plan's workspace of stream s)
+// mask: NULL, or uint8 [F][B] applied inside the kernels (only where
+// mask_fused holds); xm: device float2 [F][M][B] that receives the masked
+// copies of the hi/lo pass's frames (needed with SVDPHAT_HILO*)
 void launch_locate(svdphat_plan* p, const void* X, int64_t F, int prec, uint32_t mode,
                    int32_t* doa, float* power, float* yhat, float* margin, float* y_opt,
-                   hipStream_t s, void* scratch = nullptr, size_t scratch_bytes = 0);
+                   hipStream_t s, void* scratch = nullptr, size_t scratch_bytes = 0,
+                   const uint8_t* mask = nullptr, float2* xm = nullptr);
+// whether launch_locate takes a mask for F frames in precision prec (the
+// streamed GEMM1 serves the call)
+bool mask_fused(const svdphat_plan* p, int64_t F, int prec, bool y_opt);
 void launch_srp(svdphat_plan* p, const void* X, int64_t F, int32_t* doa, float* power,
                 float* y_opt, hipStream_t s);
 void build_w_fp32_frags(svdphat_plan* p);
@@ -324,6 +332,9 @@ void launch_gv(svdphat_plan* p, const ScoreRows& sr, const float2* X, int64_t F,
 void* ws_get(svdphat_plan* p, hipStream_t s, size_t bytes, int slot = 0);
 // binary time-frequency mask (mask.hip): xm = X where mask[f][b] != 0, else 0
 void launch_mask(const svdphat_plan* p, const float2* X, int64_t F, const uint8_t* mask, float2* xm, hipStream_t s);
+// the same for the frames flist[0 .. *fcount) only, each at its own place in xm
+void launch_mask_list(const svdphat_plan* p, const float2* X, const uint8_t* mask, const int* flist,
+                      const int* fcount, float2* xm, hipStream_t s);
 // zero `bytes` (a multiple of 4) of device memory on stream s with a kernel,
 // so that a caller capturing the stream into a graph records a kernel node
 void zero_async(void* p, size_t bytes, hipStream_t s);

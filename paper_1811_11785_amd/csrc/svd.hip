@@ -971,12 +971,14 @@ __global__ __launch_bounds__(256) void k_final_list(FinalArgs a) {
 // power of direction doa[f] from its row of W (delay-and-sum form).  One
 // wave per frame; the frame, its direction and the direction's delays are
 // wave-uniform (scalar loads), so the STFT loads are the only vector loads.
-// (With flist, the frames flist[0 .. *fcount), grid-stride.)
-template <int MAXM>
+// (With flist, the frames flist[0 .. *fcount), grid-stride.  MK: mask
+// [nfr][B], a dropped bin contributes nothing.)
+template <int MAXM, bool MK>
 __global__ __launch_bounds__(256) void k_power(const float2* __restrict__ X, int M, int B,
                                                const int32_t* __restrict__ doa, const float* __restrict__ tauM,
                                                int64_t nfr, float* __restrict__ power,
-                                               const int* __restrict__ flist, const int* __restrict__ fcount) {
+                                               const int* __restrict__ flist, const int* __restrict__ fcount,
+                                               const uint8_t* __restrict__ mask) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t n = fcount ? (int64_t)*fcount : nfr;
     for (int64_t pos = (int64_t)blockIdx.x * 4 + wave; pos < n; pos += (int64_t)gridDim.x * 4) {
@@ -985,20 +987,29 @@ __global__ __launch_bounds__(256) void k_power(const float2* __restrict__ X, int
         float t[MAXM];
 #pragma unroll
         for (int m = 0; m < MAXM; ++m) t[m] = m < M ? tauM[(int64_t)q * M + m] : 0.f;
-        const float acc = power_ds<MAXM>(X + f * M * B, M, B, t, lane);
+        const float acc = power_ds<MAXM, MK>(X + f * M * B, M, B, t, lane, MK ? mask + f * B : nullptr);
         if (lane == 0) power[f] = acc;
     }
 }
 
-void launch_power(const svdphat_plan* p, const float2* X, const int32_t* doa, int64_t F, float* power,
-                  const int* flist, const int* fcount, hipStream_t s) {
+template <bool MK>
+void launch_power_t(const svdphat_plan* p, const float2* X, const int32_t* doa, int64_t F, float* power,
+                    const int* flist, const int* fcount, const uint8_t* mask, hipStream_t s) {
     const dim3 grid(flist ? 512u : (unsigned)((F + 3) / 4));
+    const int M = p->M, B = p->B;
+    const float* tau = p->d_tauM_all;
     // the exact microphone count where it is common (no padded microphone's
     // loads, fewer registers)
-    if (p->M == 6) k_power<6><<<grid, 256, 0, s>>>(X, p->M, p->B, doa, p->d_tauM_all, F, power, flist, fcount);
-    else if (p->M == 7) k_power<7><<<grid, 256, 0, s>>>(X, p->M, p->B, doa, p->d_tauM_all, F, power, flist, fcount);
-    else if (p->M <= 8) k_power<8><<<grid, 256, 0, s>>>(X, p->M, p->B, doa, p->d_tauM_all, F, power, flist, fcount);
-    else k_power<16><<<grid, 256, 0, s>>>(X, p->M, p->B, doa, p->d_tauM_all, F, power, flist, fcount);
+    if (M == 6) k_power<6, MK><<<grid, 256, 0, s>>>(X, M, B, doa, tau, F, power, flist, fcount, mask);
+    else if (M == 7) k_power<7, MK><<<grid, 256, 0, s>>>(X, M, B, doa, tau, F, power, flist, fcount, mask);
+    else if (M <= 8) k_power<8, MK><<<grid, 256, 0, s>>>(X, M, B, doa, tau, F, power, flist, fcount, mask);
+    else k_power<16, MK><<<grid, 256, 0, s>>>(X, M, B, doa, tau, F, power, flist, fcount, mask);
+}
+
+void launch_power(const svdphat_plan* p, const float2* X, const int32_t* doa, int64_t F, float* power,
+                  const int* flist, const int* fcount, hipStream_t s, const uint8_t* mask) {
+    if (mask) launch_power_t<true>(p, X, doa, F, power, flist, fcount, mask, s);
+    else launch_power_t<false>(p, X, doa, F, power, flist, fcount, nullptr, s);
 }
 
 // ------------------------------------------------------------------ grouped
@@ -1223,7 +1234,8 @@ void launch_final_list(const FinalArgs& fa, int M, bool dedup, hipStream_t s) {
 
 template <typename T>
 void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t mode, int32_t* doa, float* power,
-                float* yhat, float* margin, float* y_opt, hipStream_t s, void* scratch, size_t scratch_bytes) {
+                float* yhat, float* margin, float* y_opt, hipStream_t s, void* scratch, size_t scratch_bytes,
+                const uint8_t* mask, float2* xm) {
     const G1Layout& g = p->g1[prec];
     const int Rp = p->Rp;
     const int ntile = p->ncls_pad / QTILE;
@@ -1235,6 +1247,9 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     const bool streamed = g1s_sched(prec, p, F, &sc);
     const int zslots = streamed ? sc.slots : nsplit;
     const bool hilo = (mode & (SVDPHAT_HILO | SVDPHAT_HILO_ALL)) && prec != P_FP32;
+    // a mask is applied by the streamed GEMM1's producers, the hi/lo pass
+    // (on masked copies of its listed frames, in xm) and the power
+    SP_REQUIRE(!mask || (streamed && (!hilo || xm)), SVDPHAT_E_UNSUPPORTED, "masked search without its streamed form");
     // the hi/lo pass covers few frames: more splits keep the grid busy
     int hsplit = g.nch, hcps = 1;
 
@@ -1281,7 +1296,7 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     const int64_t zstride = Fc * Rp;
     KernelTimer kt(s);
     kt.begin("gemm1");
-    if (streamed) launch_g1_streamed(prec, p, sc, X, F, zpart, zstride, s);
+    if (streamed) launch_g1_streamed(prec, p, sc, X, F, zpart, zstride, s, mask);
     else launch_g1<T, 64, false>(ftiles, nsplit, s, X, F, p, prec, g, cps, zpart, zstride, nullptr, nullptr);
     SP_HIP(hipGetLastError());
     kt.end();
@@ -1362,7 +1377,8 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     kt.end();
     if (hilo) {
         kt.begin("gemm1_hilo");
-        launch_g1_list<T>(s, X, p, prec, g, hsplit, hcps, zpart, zstride, hl, hc);
+        if (mask) launch_mask_list(p, X, mask, hl, hc, xm, s);
+        launch_g1_list<T>(s, mask ? xm : X, p, prec, g, hsplit, hcps, zpart, zstride, hl, hc);
         SP_HIP(hipGetLastError());
         kt.end();
         FinalArgs fb = fa;
@@ -1382,7 +1398,7 @@ void run_locate(svdphat_plan* p, const float2* X, int64_t F, int prec, uint32_t 
     }
     // Algorithm 1 online step 4 for every frame, once the directions are final
     kt.begin("power");
-    launch_power(p, X, doa, F, power, nullptr, nullptr, s);
+    launch_power(p, X, doa, F, power, nullptr, nullptr, s, mask);
     SP_HIP(hipGetLastError());
     kt.end();
     kt.flush();
@@ -1604,9 +1620,17 @@ void tune_time(svdphat_plan* p, int64_t F, int nsplit_want, int fch, double* us_
     *us_g2 = 1e3 * b / reps;
 }
 
+bool mask_fused(const svdphat_plan* p, int64_t F, int prec, bool y_opt) {
+    G1Sched sc;
+    return (y_opt || !gv_applicable(p, F)) && g1s_sched(prec, p, F, &sc);
+}
+
 void launch_locate(svdphat_plan* p, const void* X, int64_t F, int prec, uint32_t mode, int32_t* doa, float* power,
-                   float* yhat, float* margin, float* y_opt, hipStream_t s, void* scratch, size_t scratch_bytes) {
+                   float* yhat, float* margin, float* y_opt, hipStream_t s, void* scratch, size_t scratch_bytes,
+                   const uint8_t* mask, float2* xm) {
     const float2* x = (const float2*)X;
+    SP_REQUIRE(!mask || mask_fused(p, F, prec, y_opt != nullptr), SVDPHAT_E_UNSUPPORTED,
+               "masked search without its streamed form");
     if (!y_opt && gv_applicable(p, F)) {
         // a few frames: GEMV form in FP32 (frame1.hip), on the caller's
         // scratch buffer or the plan's workspace of this stream
@@ -1617,10 +1641,12 @@ void launch_locate(svdphat_plan* p, const void* X, int64_t F, int prec, uint32_t
         launch_gv(p, p->sr[(mode & SVDPHAT_NORMALIZED) ? 1 : 0], x, F, doa, power, yhat, margin, w, s);
         return;
     }
-    if (prec == P_FP32) run_locate<float>(p, x, F, prec, mode, doa, power, yhat, margin, y_opt, s, scratch, scratch_bytes);
+    if (prec == P_FP32)
+        run_locate<float>(p, x, F, prec, mode, doa, power, yhat, margin, y_opt, s, scratch, scratch_bytes, mask, xm);
     else if (prec == P_FP16)
-        run_locate<_Float16>(p, x, F, prec, mode, doa, power, yhat, margin, y_opt, s, scratch, scratch_bytes);
-    else run_locate<__bf16>(p, x, F, prec, mode, doa, power, yhat, margin, y_opt, s, scratch, scratch_bytes);
+        run_locate<_Float16>(p, x, F, prec, mode, doa, power, yhat, margin, y_opt, s, scratch, scratch_bytes, mask,
+                             xm);
+    else run_locate<__bf16>(p, x, F, prec, mode, doa, power, yhat, margin, y_opt, s, scratch, scratch_bytes, mask, xm);
 }
 
 }  // namespace svdphat

@@ -105,3 +105,43 @@ def test_mask_planar_q10242(amd, torch):
     judged = _check(out, ref, "fp16", ref_plan.W.shape[1])
     print(f"  judged {judged.sum()}/96 frames match", flush=True)
     plan.close()
+
+
+def _premasked(torch, Xd, md):
+    """The frames with the dropped bins written as 0 (what the mask means)."""
+    return torch.where(md.bool()[:, None, :], Xd, torch.zeros((), dtype=Xd.dtype, device=Xd.device)).contiguous()
+
+
+@pytest.mark.parametrize("name,F", [("planar_q10242", 2000), ("cube_q10242", 4096)])
+def test_mask_inside_kernels_equals_masked_frames(amd, torch, name, F):
+    """Where the streamed GEMM1 serves the call, the mask is applied inside the
+    kernels (the PHAT producers, the hi/lo pass's listed frames, the power)
+    instead of on a masked copy of every frame.  Its results must be those
+    of the unmasked call on the frames with the dropped bins set to 0, bit
+    for bit: the planar array (one GEMM1 pass) on a ragged last frame tile,
+    and the 3-D array at 4096 frames (GEMM1 in two row-group passes); FP16
+    and BF16, eq. (14) with hi/lo on the close frames and on every frame,
+    and eq. (15)."""
+    print(f"mask fused {name} F={F}", flush=True)
+    w = synth.workload(name, frames=F)
+    X = w["X"][:F]
+    B = X.shape[2]
+    rng = np.random.default_rng(11785820)
+    m = _masks(rng, F, B)
+    m[3:40] = 1                     # frames kept whole among the random ones
+    m[-1] = 0                       # the ragged tile's last frame: nothing kept
+    plan = amd.Plan(w["mics"], w["grid"], w["fs"], w["c"], w["N"], w["delta"])
+    Xd, md = torch.from_numpy(X).cuda(), torch.from_numpy(m).cuda()
+    Xz = _premasked(torch, Xd, md)
+    cases = [dict(precision="fp16", hilo=True), dict(precision="bf16", hilo=True),
+             dict(precision="fp16", hilo_all=True), dict(precision="fp16", hilo=True, normalized=True),
+             dict(precision="fp16", rescore=False)]
+    for kw in cases:
+        a = plan.locate(Xd, mask=md, **kw)
+        b = plan.locate(Xz, **kw)
+        torch.cuda.synchronize()
+        for k in a:
+            assert torch.equal(a[k], b[k]), (kw, k, (a[k] != b[k]).nonzero()[:5].flatten().tolist())
+        if kw.get("rescore", True):  # a frame with nothing kept: every direction ties, the first wins
+            assert a["doa"][-1].item() == 0 and a["power"][-1].item() == 0.0
+    plan.close()
