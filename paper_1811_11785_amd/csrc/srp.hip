@@ -13,42 +13,51 @@ namespace {
 // ------------------------------------------------------------------ SRP
 // PHAT vector in FP32, written as MFMA B-operand fragments of the 16x16x4
 // instruction: element (k, frame) -> [frame/16][k/4][lane = frame%16 +
-// 16 (k%4)], k = (bin P + p) 2 + {0: Re, 1: Im}.
-// Frames from nfr up to fpad and the columns past 2L are written as zeros.
-template <int MAXM>
-__global__ void k_phat_frag(const float2* __restrict__ X, int64_t nfr, int64_t fpad, int M, int P, int B, int Wks,
-                            float* __restrict__ xfr) {
-    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (it >= fpad * B) return;
-    const int64_t f = it / B;
-    const int bin = (int)(it % B);
-    const bool live = f < nfr;
-    const float2* xf = X + (live ? f : 0) * M * B + bin;
+// 16 (k%4)], k = (bin P + p) 2 + {0: Re, 1: Im}.  Frames from nfr up to the
+// padded count and the columns past 2L are written as zeros.
+// One workgroup per (block of 16 frames, run of SB bins): thread (bin b,
+// frame nn) forms the P pair products of its (frame, bin) into LDS in the
+// fragment order, and the block's fragments of those bins, one contiguous
+// run of the output ([k0/4, kend/4) x 64 floats), go out in 16-byte stores
+// (the last run takes the zero columns up to 4 Wks as well).
+template <int MAXM, int SB>
+__global__ __launch_bounds__(SB * 16) void k_phat_frag(const float2* __restrict__ X, int64_t nfr, int M, int P, int B,
+                                                       int Wks, int nchunk, float* __restrict__ xfr) {
+    extern __shared__ __align__(16) float st[];  // SB 2P x 16 staged values
+    const int64_t fb = blockIdx.x / nchunk;
+    const int c = (int)(blockIdx.x - fb * nchunk);
+    const int t = threadIdx.x, nn = t & 15, b = t >> 4;
+    const int64_t f = fb * 16 + nn;
+    const int bin = c * SB + b;
+    const bool live = f < nfr && bin < B;
+    const float2* xf = X + (live ? f * M * B + bin : 0);
     float re[MAXM], im[MAXM];
 #pragma unroll
     for (int m = 0; m < MAXM; ++m) {
-        float2 v = (live && m < M) ? xf[(int64_t)m * B] : float2{0.f, 0.f};
+        const float2 v = (live && m < M) ? xf[(int64_t)m * B] : float2{0.f, 0.f};
         re[m] = v.x;
         im[m] = v.y;
         unit(re[m], im[m]);
     }
-    const int64_t base = (f >> 4) * Wks * 64;
-    const int nn = (int)(f & 15);
-    if (bin == B - 1)
-        for (int k = 2 * P * B; k < 4 * Wks; ++k) xfr[base + (k >> 2) * 64 + nn + 16 * (k & 3)] = 0.f;
     int p = 0;
 #pragma unroll
     for (int i = 0; i < MAXM; ++i)
 #pragma unroll
         for (int j = i + 1; j < MAXM; ++j)
             if (j < M) {
-                const float xr = re[i] * re[j] + im[i] * im[j];
-                const float xi = im[i] * re[j] - re[i] * im[j];
-                const int k = (bin * P + p) * 2;
-                xfr[base + (k >> 2) * 64 + nn + 16 * (k & 3)] = xr;
-                xfr[base + ((k + 1) >> 2) * 64 + nn + 16 * ((k + 1) & 3)] = xi;
+                const int k = (b * P + p) * 2;  // column within the run
+                st[(k >> 2) * 64 + nn + 16 * (k & 3)] = fmaf(re[i], re[j], im[i] * im[j]);
+                st[((k + 1) >> 2) * 64 + nn + 16 * ((k + 1) & 3)] = fmaf(im[i], re[j], -(re[i] * im[j]));
                 ++p;
             }
+    __syncthreads();
+    const int kw = SB * 2 * P;  // staged columns (a multiple of 4)
+    const int k0 = c * kw;
+    const int kend = c == nchunk - 1 ? 4 * Wks : k0 + kw;
+    float4* out = reinterpret_cast<float4*>(xfr + (fb * Wks + k0 / 4) * 64);
+    const int n4 = (kend - k0) * 4;
+    for (int i = t; i < n4; i += SB * 16)
+        out[i] = 4 * i < kw * 16 ? *reinterpret_cast<const float4*>(st + 4 * i) : make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 // W in FP32 as A-operand fragments of the 16x16x4 instruction: element
@@ -241,11 +250,17 @@ void launch_srp(svdphat_plan* p, const void* Xv, int64_t F, int32_t* doa, float*
     float* pv = (float*)(w + o_v);
     int* pidx = (int*)(w + o_i);
     kt.begin("srp_phat");
-    const int64_t items = Fp * p->B;
+    // runs of 16 bins (4 above 8 microphones, to bound the LDS); a run of
+    // SB bins starts at column SB 2P c, a multiple of 4
+    const int sb = p->M <= 8 ? 16 : 4;
+    const int nchunk = (p->B + sb - 1) / sb;
+    const int64_t nblk = (Fp / 16) * nchunk;
+    SP_REQUIRE(nblk < ((int64_t)1 << 31), SVDPHAT_E_INVAL, "too many frames for one call");
+    const size_t lds = (size_t)sb * 2 * p->P * 16 * sizeof(float);
     if (p->M <= 8)
-        k_phat_frag<8><<<dim3((unsigned)((items + 255) / 256)), 256, 0, s>>>(X, F, Fp, p->M, p->P, p->B, Wks, xfr);
+        k_phat_frag<8, 16><<<dim3((unsigned)nblk), 256, lds, s>>>(X, F, p->M, p->P, p->B, Wks, nchunk, xfr);
     else
-        k_phat_frag<16><<<dim3((unsigned)((items + 255) / 256)), 256, 0, s>>>(X, F, Fp, p->M, p->P, p->B, Wks, xfr);
+        k_phat_frag<16, 4><<<dim3((unsigned)nblk), 64, lds, s>>>(X, F, p->M, p->P, p->B, Wks, nchunk, xfr);
     SP_HIP(hipGetLastError());
     kt.end();
     kt.begin("srp_gemm");
