@@ -56,9 +56,24 @@ __global__ __launch_bounds__(256) void k_stft(const float* __restrict__ pcm, int
     float2* b1 = b0 + N2;
     float* b0f = reinterpret_cast<float*>(b0);
     const int64_t step = (int64_t)gridDim.x * STFT_WAVES;
+    // R1 (N >= 512, so N2 / 4 >= 64): the first radix-4 stage runs in
+    // registers.  Lane l loads the inputs of its butterflies j = l + 64 b
+    // straight from memory, z[j + r N2/4] for r < 4 (sample index
+    // smp(i) below), and writes each butterfly's four outputs, which are
+    // adjacent, as two 16-byte LDS stores; the windowed samples never pass
+    // through LDS.  Otherwise sample n = lane + 64 i is staged in LDS.
+    constexpr bool R1 = NC >= 512;
+    auto smp = [&](int i) {
+        if constexpr (R1) {
+            const int bq = i >> 3, r = (i >> 1) & 3, e = i & 1;
+            return 2 * (lane + 64 * bq + r * (N2 / 4)) + e;
+        } else {
+            return min(lane + 64 * i, N - 1);
+        }
+    };
     // the samples of the wave's next pair are loaded into registers while
-    // the current pair's transform runs (sample n = lane + 64 i; lanes past
-    // N re-read sample N - 1 and are not used)
+    // the current pair's transform runs (without R1, lanes past N re-read
+    // sample N - 1 and are not used)
     float xs[NL];
     // (frame, microphone) of the pair to fetch, moved by the grid stride
     // without a division per pair
@@ -70,7 +85,7 @@ __global__ __launch_bounds__(256) void k_stft(const float* __restrict__ pcm, int
     auto fetch = [&]() {
         const float* src = pcm + (int64_t)fm * ld + ff * hop;
 #pragma unroll
-        for (int i = 0; i < NL; ++i) xs[i] = src[min(lane + 64 * i, N - 1)];
+        for (int i = 0; i < NL; ++i) xs[i] = src[smp(i)];
         ff += sf;
         fm += sm;
         if (fm >= M) {
@@ -81,7 +96,7 @@ __global__ __launch_bounds__(256) void k_stft(const float* __restrict__ pcm, int
     // the lane's window values and split twiddles stay in registers
     float wr[NL];
 #pragma unroll
-    for (int i = 0; i < NL; ++i) wr[i] = win[min(lane + 64 * i, N - 1)];
+    for (int i = 0; i < NL; ++i) wr[i] = win[smp(i)];
     // a pair's bins k = lane + 64 i stay in registers until the next pair's
     // samples are in LDS; their stores then go out before the next prefetch,
     // so they drain during a whole transform (vector stores count in the same
@@ -102,23 +117,39 @@ __global__ __launch_bounds__(256) void k_stft(const float* __restrict__ pcm, int
     if (pr < npair) fetch();
     for (; pr < npair; pr += step) {
         wave_sync();  // the previous pair's reads of the buffers are done
-        // windowed samples, read as z[n] = x[2n] + i x[2n+1]
+        if constexpr (R1) {
+            // stage 1 (span 1, unit twiddles) into b1
 #pragma unroll
-        for (int i = 0; i < NL; ++i)
-            if (lane + 64 * i < N) b0f[lane + 64 * i] = wr[i] * xs[i];
+            for (int bq = 0; bq < NL / 8; ++bq) {
+                float2 v[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    v[r] = float2{wr[8 * bq + 2 * r] * xs[8 * bq + 2 * r], wr[8 * bq + 2 * r + 1] * xs[8 * bq + 2 * r + 1]};
+                const float2 s02 = float2{v[0].x + v[2].x, v[0].y + v[2].y}, d02 = float2{v[0].x - v[2].x, v[0].y - v[2].y};
+                const float2 s13 = float2{v[1].x + v[3].x, v[1].y + v[3].y}, d13 = float2{v[1].x - v[3].x, v[1].y - v[3].y};
+                float4* o = reinterpret_cast<float4*>(b1 + 4 * (lane + 64 * bq));
+                o[0] = make_float4(s02.x + s13.x, s02.y + s13.y, d02.x + d13.y, d02.y - d13.x);
+                o[1] = make_float4(s02.x - s13.x, s02.y - s13.y, d02.x - d13.y, d02.y + d13.x);
+            }
+        } else {
+            // windowed samples, read as z[n] = x[2n] + i x[2n+1]
+#pragma unroll
+            for (int i = 0; i < NL; ++i)
+                if (lane + 64 * i < N) b0f[lane + 64 * i] = wr[i] * xs[i];
+        }
         wave_sync();
         if (opr >= 0) store();
         if (pr + step < npair) fetch();
-        float2* a = b0;
-        float2* b = b1;
+        float2* a = R1 ? b1 : b0;
+        float2* b = R1 ? b0 : b1;
         // radix-4 stages while four spans fit, then one radix-2 stage if
         // log2(N/2) is odd.  Butterfly j of span Ns takes inputs j + r N2/R,
         // multiplies input r by e^{-2 pi i r (j mod Ns) / (R Ns)}, and writes
         // the R-point DFT to R (j - j mod Ns) + j mod Ns + r Ns
         const int lg = NC > 0 ? ilog2c(NC / 2) : 31 - __builtin_clz(N2);
-        int Ns = 1;
+        int Ns = R1 ? 4 : 1;
 #pragma unroll
-        for (int r4 = 0; r4 < lg / 2; ++r4, Ns *= 4) {
+        for (int r4 = R1 ? 1 : 0; r4 < lg / 2; ++r4, Ns *= 4) {
             const int Q = N2 / 4, ts = N2 / (4 * Ns);
 #pragma unroll
             for (int j = lane; j < Q; j += 64) {
