@@ -282,6 +282,10 @@ struct svdphat_proposal {
     float* Vv = nullptr;
     _Float16* Wh[3] = {nullptr, nullptr, nullptr};  // [out][in]
     _Float16* Wt[3] = {nullptr, nullptr, nullptr};  // [in][out]
+    // Wh in MFMA B-fragment order for inference (one contiguous 1 KB per
+    // fragment load), repacked from Wh when wf_ok is false
+    _Float16* Wf[3] = {nullptr, nullptr, nullptr};
+    bool wf_ok = false;
     int64_t step = 0;
     // workspace
     void* ws = nullptr;

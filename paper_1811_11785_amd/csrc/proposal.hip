@@ -306,6 +306,20 @@ __global__ void k_cast_w(const float* __restrict__ W, int rows, int cols, _Float
     wt[(int64_t)c * ldt + r] = (_Float16)W[i];
 }
 
+// Wf: W [N][K] (f16, N a multiple of 64, K of 32) in the MFMA B-fragment
+// order of k_mlp_infer: element (n, k) at ((((n / 64) (K / 32) + k / 32) 4 +
+// (n / 16) mod 4) 64 + n mod 16 + 16 ((k / 8) mod 4)) 8 + k mod 8.  One
+// thread per 8 consecutive k of a row.
+__global__ void k_pack_wf(const _Float16* __restrict__ wh, int N, int K, _Float16* __restrict__ wf) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int kc = K / 8;
+    if (i >= (int64_t)N * kc) return;
+    const int n = (int)(i / kc), k = (int)(i - (int64_t)n * kc) * 8;
+    const int g = n >> 6, cb = (n >> 4) & 3, ks = k >> 5, lane = (n & 15) + 16 * ((k >> 3) & 3);
+    const int64_t off = ((((int64_t)g * (K / 32) + ks) * 4 + cb) * 64 + lane) * 8;
+    *reinterpret_cast<h8*>(wf + off) = *reinterpret_cast<const h8*>(wh + (int64_t)n * K + k);
+}
+
 // ------------------------------------------------------------- inference
 // Inference runs in stages:
 //   k_mlp_infer   the forward pass of FT frames per workgroup, activations in
@@ -331,7 +345,8 @@ constexpr int SEL_FPW = 2;   // frames per wave in the selection
 // b1), GELU(W2 . + b2), W3 . + b3, for FT frames per workgroup of 4 waves.
 // Activations stay in LDS in two buffers ([FT][max(D0, H) + 8] and [FT][H +
 // 8] halves); the weights are read as B fragments from their f16 copies
-// (L2-resident), two k-steps ahead of their MFMAs.  The arithmetic is that
+// (L2-resident; packed in fragment order, so that a fragment load reads
+// 1 KB in one piece), two k-steps ahead of their MFMAs.  The arithmetic is that
 // of the training path (f16 operands, FP32 accumulation, bias and GELU in
 // FP32, f16 hidden activations).  Writes FP32 logits [F][Cp].
 template <int FT>
@@ -375,25 +390,31 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ z32
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
-            const _Float16* wp = W + (int64_t)(g * 64 + (lane & 15)) * K + 8 * (lane >> 4);
+            // W in fragment order: fragment (k-step ks, column block cb) of
+            // group g is 64 lanes x 8 halves at wp + (ks 4 + cb) 512
+            const int nks = K / 32;
+            const _Float16* wp = W + ((int64_t)g * nks * 4 * 64 + lane) * 8;
+            auto frag = [&](int ks, int cb) {
+                return *reinterpret_cast<const h8*>(wp + (int64_t)(ks * 4 + cb) * 512);
+            };
             // B fragments two k-steps ahead (k-steps past the end reload the
             // last one)
             h8 b1[4], b2[4];
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
-                b1[cb] = *reinterpret_cast<const h8*>(wp + (int64_t)cb * 16 * K);
-                b2[cb] = *reinterpret_cast<const h8*>(wp + (int64_t)cb * 16 * K + min(32, K - 32));
+                b1[cb] = frag(0, cb);
+                b2[cb] = frag(min(1, nks - 1), cb);
             }
-            for (int k0 = 0; k0 < K; k0 += 32) {
+            for (int k0 = 0, ks = 0; k0 < K; k0 += 32, ++ks) {
                 h8 b[4];
 #pragma unroll
                 for (int cb = 0; cb < 4; ++cb) {
                     b[cb] = b1[cb];
                     b1[cb] = b2[cb];
                 }
-                const int kn = min(k0 + 64, K - 32);
+                const int kn = min(ks + 2, nks - 1);
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb) b2[cb] = *reinterpret_cast<const h8*>(wp + (int64_t)cb * 16 * K + kn);
+                for (int cb = 0; cb < 4; ++cb) b2[cb] = frag(kn, cb);
                 h8 a[RB];
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb)
@@ -1004,6 +1025,7 @@ void adam(svdphat_proposal* pr, const PW& o, int64_t F, float lr, hipStream_t s,
 }
 
 void cast_weights(svdphat_proposal* pr, hipStream_t s) {
+    pr->wf_ok = false;
     const int H = pr->H, Cp = pr->Cp, D0 = pr->D0;
     const int dims[3][2] = {{H, D0}, {H, H}, {Cp, H}};
     const int offs[3] = {0, 2, 4};
@@ -1110,6 +1132,7 @@ void proposal_build(svdphat_proposal* pr, const double* coarse, int C, int H, ui
     for (int l = 0; l < 3; ++l) {
         dev_alloc((void**)&pr->Wh[l], wsz[l] * sizeof(_Float16), "proposal weights");
         dev_alloc((void**)&pr->Wt[l], wsz[l] * sizeof(_Float16), "proposal weights");
+        dev_alloc((void**)&pr->Wf[l], wsz[l] * sizeof(_Float16), "proposal weights");
     }
     dev_alloc((void**)&pr->d_count, 8 * sizeof(int), "proposal counters");
     cast_weights(pr, nullptr);
@@ -1118,6 +1141,7 @@ void proposal_build(svdphat_proposal* pr, const double* coarse, int C, int H, ui
 
 float proposal_train_step(svdphat_proposal* pr, const float2* X, int64_t F, float lr, hipStream_t s) {
     svdphat_plan* p = pr->plan;
+    pr->wf_ok = false;  // Adam rewrites the f16 weights
     PW o = carve(pr, F, s);
     // labels: the cell of the method's own argmax (FP16, rescored, hi/lo)
     launch_locate(p, X, F, P_FP16, SVDPHAT_RESCORE | SVDPHAT_HILO, o.doa, o.pw, nullptr, nullptr, nullptr, s);
@@ -1154,13 +1178,23 @@ void proposal_locate(svdphat_proposal* pr, const float2* X, int64_t F, int topk,
     const size_t lds_cap = 80 * 1024;
     const int ft = mlp_infer_lds(32, D0, H) <= lds_cap ? 32 : mlp_infer_lds(16, D0, H) <= 2 * lds_cap ? 16 : 0;
     const float* P = pr->P;
+    if (ft != 0 && !pr->wf_ok) {
+        // the fragment-ordered weights, after a change of the f16 weights
+        const int dims[3][2] = {{H, D0}, {H, H}, {Cp, H}};
+        for (int l = 0; l < 3; ++l) {
+            const int64_t n = (int64_t)dims[l][0] * dims[l][1] / 8;
+            k_pack_wf<<<dim3((unsigned)cdiv64(n, 256)), 256, 0, s>>>(pr->Wh[l], dims[l][0], dims[l][1], pr->Wf[l]);
+        }
+        SP_HIP(hipGetLastError());
+        pr->wf_ok = true;
+    }
     if (ft == 32)
         k_mlp_infer<32><<<dim3((unsigned)cdiv64(F, 32)), 256, mlp_infer_lds(32, D0, H), s>>>(
-            o.z32, o.zn, F, D0, H, Cp, pr->Wh[0], P + pr->off[1], pr->Wh[1], P + pr->off[3], pr->Wh[2],
+            o.z32, o.zn, F, D0, H, Cp, pr->Wf[0], P + pr->off[1], pr->Wf[1], P + pr->off[3], pr->Wf[2],
             P + pr->off[5], o.logits);
     else if (ft == 16)
         k_mlp_infer<16><<<dim3((unsigned)cdiv64(F, 16)), 256, mlp_infer_lds(16, D0, H), s>>>(
-            o.z32, o.zn, F, D0, H, Cp, pr->Wh[0], P + pr->off[1], pr->Wh[1], P + pr->off[3], pr->Wh[2],
+            o.z32, o.zn, F, D0, H, Cp, pr->Wf[0], P + pr->off[1], pr->Wf[1], P + pr->off[3], pr->Wf[2],
             P + pr->off[5], o.logits);
     else {
         k_features<<<dim3((unsigned)((F * Rp + 255) / 256)), 256, 0, s>>>(o.z32, o.zn, F, Rp, o.feat);
@@ -1347,7 +1381,8 @@ void proposal_apply_grad(svdphat_proposal* pr, const float* grad, float lr) {
 void proposal_free(svdphat_proposal* pr) {
     if (!pr) return;
     void* bufs[] = {pr->d_cell_of_dir, pr->d_cell_start, pr->d_cell_dir, pr->d_U32C, pr->P, pr->Mm, pr->Vv,
-                    pr->ws, pr->d_count, pr->Wh[0], pr->Wh[1], pr->Wh[2], pr->Wt[0], pr->Wt[1], pr->Wt[2]};
+                    pr->ws, pr->d_count, pr->Wh[0], pr->Wh[1], pr->Wh[2], pr->Wt[0], pr->Wt[1], pr->Wt[2],
+                    pr->Wf[0], pr->Wf[1], pr->Wf[2]};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (void* b : pr->ws_retired) (void)hipFree(b);
