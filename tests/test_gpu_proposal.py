@@ -205,6 +205,34 @@ def test_training_and_proposal_search(amd, torch, small):
     prop.close()
 
 
+def test_inference_weights_follow_training(amd, torch, small):
+    """Inference reads a copy of the f16 weights in MFMA fragment order,
+    rebuilt whenever the weights change.  After inference, training steps
+    and inference again, the answers must be those of a fresh proposal given
+    the trained parameters, bit for bit; parameters set after a call must
+    take effect as well."""
+    plan = small["plan"]
+    prop = amd.Proposal(plan, small["coarse"], hidden=128, seed=11)
+    X = _frames(torch, small["mics"], 48, 4242, snr=(0.0, 20.0))
+    p0 = prop.get_params()
+    a0 = prop.locate(X, topk=4, conf_min=0.2)  # packs the initial weights
+    for step in range(3):
+        prop.train_step(_frames(torch, small["mics"], 48, 5000 + step, snr=(0.0, 20.0)), lr=1e-2)
+    a = prop.locate(X, topk=4, conf_min=0.2)
+    fresh = amd.Proposal(plan, small["coarse"], hidden=128, seed=3)
+    fresh.set_params(prop.get_params())
+    b = fresh.locate(X, topk=4, conf_min=0.2)
+    prop.set_params(p0)
+    c = prop.locate(X, topk=4, conf_min=0.2)
+    torch.cuda.synchronize()
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+        assert torch.equal(c[k], a0[k]), k
+    assert not np.array_equal(prop.get_params(), fresh.get_params())  # training moved the weights
+    fresh.close()
+    prop.close()
+
+
 def test_empty_cells_fall_back(amd, torch, small):
     """Coarse cells that hold no fine direction: a proposal whose topk
     cells are all empty takes the full search (fell_back = 1) instead of
