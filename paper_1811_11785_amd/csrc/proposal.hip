@@ -101,6 +101,10 @@ __global__ __launch_bounds__(256) void k_mlp_gemm(const _Float16* __restrict__ A
     f4 acc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+    // a transposed operand's 8 consecutive elements of a row in one 16-byte
+    // load where the row pitch and the pointer allow it
+    const bool va = AT && lda % 8 == 0 && ((uintptr_t)A & 15) == 0;
+    const bool vb = BT && ldb % 8 == 0 && ((uintptr_t)Bm & 15) == 0;
     for (int k0 = kbeg; k0 < kend; k0 += GK) {
         // stage 64 x 32 tiles of A and B with the reduction axis contiguous
         if (!AT) {
@@ -112,10 +116,16 @@ __global__ __launch_bounds__(256) void k_mlp_gemm(const _Float16* __restrict__ A
             }
         } else {
             const int kk = tid >> 3, r = (tid & 7) * 8;
+            if (va && m0 + r + 8 <= M && k0 + kk < kend) {
+                const h8 v = *reinterpret_cast<const h8*>(A + (int64_t)(k0 + kk) * lda + m0 + r);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int m = m0 + r + e, k = k0 + kk;
-                As[r + e][kk] = (m < M && k < kend) ? A[(int64_t)k * lda + m] : (_Float16)0.f;
+                for (int e = 0; e < 8; ++e) As[r + e][kk] = v[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int m = m0 + r + e, k = k0 + kk;
+                    As[r + e][kk] = (m < M && k < kend) ? A[(int64_t)k * lda + m] : (_Float16)0.f;
+                }
             }
         }
         if (!BT) {
@@ -127,10 +137,16 @@ __global__ __launch_bounds__(256) void k_mlp_gemm(const _Float16* __restrict__ A
             }
         } else {
             const int kk = tid >> 3, r = (tid & 7) * 8;
+            if (vb && n0 + r + 8 <= N && k0 + kk < kend) {
+                const h8 v = *reinterpret_cast<const h8*>(Bm + (int64_t)(k0 + kk) * ldb + n0 + r);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int n = n0 + r + e, k = k0 + kk;
-                Bs[r + e][kk] = (n < N && k < kend) ? Bm[(int64_t)k * ldb + n] : (_Float16)0.f;
+                for (int e = 0; e < 8; ++e) Bs[r + e][kk] = v[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int n = n0 + r + e, k = k0 + kk;
+                    Bs[r + e][kk] = (n < N && k < kend) ? Bm[(int64_t)k * ldb + n] : (_Float16)0.f;
+                }
             }
         }
         __syncthreads();
