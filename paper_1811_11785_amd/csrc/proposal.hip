@@ -493,6 +493,9 @@ inline size_t mlp_infer_lds(int FT, int D0, int H) {
 // a slot in a workgroup histogram (LDS) plus the workgroup's base, one
 // global add per cell the workgroup names.  stats (optional): rows to be
 // rescored and frames that take the proposal.
+// NJ = ceil(C / 64) logits per lane: the selection is VALU-bound, and every
+// slot costs in each of its passes (maximum, exponentials, keys, topk rounds)
+template <int NJ>
 __global__ __launch_bounds__(256) void k_select(const float* __restrict__ logits, int ld, int C, int topk,
                                                 float conf_min, const int32_t* __restrict__ cstart, int64_t F,
                                                 uint8_t* __restrict__ fell, int32_t* __restrict__ ntop,
@@ -511,13 +514,13 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ logits
     const int64_t fw = ((int64_t)blockIdx.x * 4 + wave) * SEL_FPW;
     int nsel[SEL_FPW];
     unsigned long long rows_sum = 0, nconf = 0;
-    // logits of a frame's cells, up to 1024 in registers (lane + 64 j)
+    // logits of a frame's cells, up to 64 NJ in registers (lane + 64 j)
     // (frame index clamped into range, so that the loads need no branch)
-    float lv[16];
-    auto load = [&](float (&v)[16], int64_t f) {
+    float lv[NJ];
+    auto load = [&](float (&v)[NJ], int64_t f) {
         const float* l = logits + min(f, F - 1) * ld;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = __builtin_nontemporal_load(l + min(lane + 64 * j, C - 1));
+        for (int j = 0; j < NJ; ++j) v[j] = __builtin_nontemporal_load(l + min(lane + 64 * j, C - 1));
     };
 #pragma unroll
     for (int i = 0; i < SEL_FPW; ++i) {
@@ -527,24 +530,24 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ logits
         if (f < F) {
             float mx = -INFINITY;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
+            for (int j = 0; j < NJ; ++j) {
                 if (lane + 64 * j >= C) lv[j] = -INFINITY;
                 mx = fmaxf(mx, lv[j]);
             }
             mx = wave_max(mx);
             float se = 0.f;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) se += lv[j] > -INFINITY ? __expf(lv[j] - mx) : 0.f;
+            for (int j = 0; j < NJ; ++j) se += lv[j] > -INFINITY ? __expf(lv[j] - mx) : 0.f;
             se = wave_sum(se);
             int n = 0;
             unsigned long long rs = 0;
             if (1.f / se >= conf_min) {
                 // cells ranked by one 32-bit key: the logit's order-preserving
                 // bits to 13 mantissa bits, then the lowest index (key 0: none)
-                uint32_t key[16];
+                uint32_t key[NJ];
                 uint32_t km = 0;
 #pragma unroll
-                for (int j = 0; j < 16; ++j) {
+                for (int j = 0; j < NJ; ++j) {
                     const uint32_t b = __float_as_uint(lv[j]);
                     const uint32_t o = b ^ ((uint32_t)((int32_t)b >> 31) | 0x80000000u);
                     key[j] = lv[j] > -INFINITY ? ((o & ~0x3FFu) | (uint32_t)(1023 - (lane + 64 * j))) : 0u;
@@ -558,7 +561,7 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ logits
                     const int c = 1023 - (int)(kw & 0x3FFu);
                     km = 0;
 #pragma unroll
-                    for (int j = 0; j < 16; ++j) {
+                    for (int j = 0; j < NJ; ++j) {
                         key[j] = key[j] == kw ? 0u : key[j];
                         km = max(km, key[j]);
                     }
@@ -1226,8 +1229,20 @@ void proposal_locate(svdphat_proposal* pr, const float2* X, int64_t F, int topk,
     kt.begin("prop_select");
     zero_async(o.ccount, sizeof(int) * (C + 1), s);
     const int64_t nwave = cdiv64(F, SEL_FPW);
-    k_select<<<dim3((unsigned)cdiv64(nwave, 4)), 256, 0, s>>>(o.logits, Cp, C, topk, conf_min, pr->d_cell_start, F,
-                                                            fell, o.ntop, o.cand, o.slot, o.ccount, o.best, stats);
+    {
+        const dim3 gs((unsigned)cdiv64(nwave, 4));
+        switch ((C + 63) / 64) {
+#define SP_SEL(NJ_)                                                                                                   \
+    case NJ_:                                                                                                         \
+        k_select<NJ_><<<gs, 256, 0, s>>>(o.logits, Cp, C, topk, conf_min, pr->d_cell_start, F, fell, o.ntop, o.cand, \
+                                         o.slot, o.ccount, o.best, stats);                                            \
+        break;
+            SP_SEL(1) SP_SEL(2) SP_SEL(3) SP_SEL(4) SP_SEL(5) SP_SEL(6) SP_SEL(7) SP_SEL(8)
+            SP_SEL(9) SP_SEL(10) SP_SEL(11) SP_SEL(12) SP_SEL(13) SP_SEL(14) SP_SEL(15) SP_SEL(16)
+#undef SP_SEL
+            default: fail(SVDPHAT_E_INVAL, "more than 1024 cells");
+        }
+    }
     SP_HIP(hipGetLastError());
     k_cell_scan<<<dim3(1), 1024, 0, s>>>(o.ccount, C, o.cpos, o.items, o.nitems, fell, F, o.flist, pr->d_count);
     SP_HIP(hipGetLastError());
