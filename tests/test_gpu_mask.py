@@ -144,4 +144,13 @@ def test_mask_inside_kernels_equals_masked_frames(amd, torch, name, F):
             assert torch.equal(a[k], b[k]), (kw, k, (a[k] != b[k]).nonzero()[:5].flatten().tolist())
         if kw.get("rescore", True):  # a frame with nothing kept: every direction ties, the first wins
             assert a["doa"][-1].item() == 0 and a["power"][-1].item() == 0.0
+    # every direction's reduced power as well (y_opt): the in-kernel form
+    # serves it at any frame count, also below the GEMV form's 16 frames
+    for n in (F, 12):
+        kw = dict(precision="fp16", hilo=True, want_y=True)
+        a = plan.locate(Xd[:n].contiguous(), mask=md[:n].contiguous(), **kw)
+        b = plan.locate(Xz[:n].contiguous(), **kw)
+        torch.cuda.synchronize()
+        for k in a:
+            assert torch.equal(a[k], b[k]), (n, k)
     plan.close()
